@@ -1,0 +1,175 @@
+/*
+ * curvelet.h - C ABI of the MI355X (gfx950) spin-0 spherical curvelet transform.
+ *
+ * Transform: second-generation scale-discretised curvelets on the sphere
+ * (Chan, Leistedt, Kitching, McEwen, IEEE TSP 65(1), 2017).  Every numerical
+ * step runs in hand-written HIP kernels; the host only validates, builds
+ * tables and launches.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Sampling (Sec. III-A-2): McEwen-Wiaux.  A sphere map of band-limit L is a
+ *   row-major array [t][p] of L x (2L-1) samples at theta_t = pi(2t+1)/(2L-1),
+ *   phi_p = 2 pi p/(2L-1).  An SO(3) grid of band-limits (L, N) is a row-major
+ *   array [a][b][g] of (2L-1) x L x (2N-1) samples at alpha_a = 2 pi a/(2L-1),
+ *   beta_b = pi(2b+1)/(2L-1), gamma_g = 2 pi g/(2N-1).
+ * - Harmonic coefficients f_lm (Sec. II-A) are complex128, flat, index
+ *   l*l + l + m, 0 <= l < L, |m| <= l.  Wigner coefficients F^l_mn are a dense
+ *   complex128 array [l][m + L - 1][n + N - 1] (entries with |m| > l or
+ *   |n| > l are ignored on input and written as zero on output).
+ * - Conventions of Sec. II-A: zyz Euler angles, D^l_mn = e^{-ima} d^l_mn(b)
+ *   e^{-ing}, Condon-Shortley phase, Y_lm = sqrt((2l+1)/4pi) d^l_{m0} e^{imphi}.
+ * - All data pointers are DEVICE pointers owned by the caller.  The library
+ *   never allocates or frees them.  Scratch memory is the caller's workspace
+ *   `ws` of `ws_bytes` bytes (size from cvl_workspace_bytes); the library
+ *   itself allocates only inside cvl_context_create (the resident Delta table)
+ *   and on the first use of a new (L, lambda, J0) (its kernel and DFT tables,
+ *   kept until cvl_context_destroy; cvl_prepare builds them ahead of time).
+ * - `stream` is a hipStream_t (NULL = legacy default stream).  Every call only
+ *   enqueues work on that stream and returns; results are ready when the
+ *   stream is.  Calls that share a workspace must be ordered on one stream.
+ * - Return value: CVL_OK, or a negative CVL_E* code.  Arguments are validated
+ *   before anything is enqueued; on error nothing is written to any output and
+ *   cvl_last_error() (thread-local) describes the failure.  NaN/Inf inputs are
+ *   not checked: they propagate to the outputs.
+ * - Precision: every step is IEEE FP64 (round to nearest, FMA contraction).
+ *   Results are bitwise run-to-run deterministic (no atomics, fixed orders).
+ */
+#ifndef CURVELET_H
+#define CURVELET_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CVL_OK = 0,
+    CVL_EINVAL = -1,       /* invalid argument */
+    CVL_ENOMEM = -2,       /* workspace too small or device allocation failed */
+    CVL_EDEVICE = -3,      /* HIP runtime error */
+    CVL_EUNSUPPORTED = -4  /* valid request outside what this build implements */
+};
+
+/* Flags of cvl_params. */
+#define CVL_REAL 1u        /* real map (f_{l,-m} = (-1)^m conj f_lm); required */
+
+typedef struct { double re, im; } cvl_c128;   /* layout of torch.complex128 */
+
+typedef struct cvl_ctx cvl_ctx;
+
+/* Curvelet parameters (Sec. II-B).  L: band-limit of the map (>= 2).
+ * N: azimuthal band-limit of the curvelets; curvelets have none, so N must be
+ * 0 or L (each scale then uses N_j = L_j).  lambda > 1: dilation.  J0 >= 1:
+ * lowest curvelet scale, J0 <= J where J = ceil(log_lambda L).  spin: must
+ * be 0.  flags: CVL_REAL. */
+typedef struct {
+    int L;
+    int N;
+    double lambda;
+    int J0;
+    int spin;
+    unsigned flags;
+} cvl_params;
+
+/* Create a context on HIP device `device` holding the quarter table
+ * Delta^l_{m'm} = d^l_{m'm}(pi/2), 0 <= m', m <= l < L_max (Sec. III-A-2,
+ * the Delta projection; built on the device by the Trapani-Navaza recursion),
+ * 8 * L_max(L_max+1)(2L_max+1)/6 bytes.  Synchronous.  2 <= L_max <= 2048. */
+int cvl_context_create(cvl_ctx **ctx, int L_max, int device);
+
+/* Release the context and every table it owns (synchronises the device). */
+void cvl_context_destroy(cvl_ctx *ctx);
+
+/* J = ceil(log_lambda L), the top scale needed for admissibility (Sec. II-D). */
+int cvl_num_scales(const cvl_params *p, int *J);
+
+/* Per-scale band-limits L_j = min(ceil(lambda^(j+1)), L) and N_j = L_j
+ * (Sec. III-A-3, multiresolution).  Grid of scale j: (2L_j-1) x L_j x (2N_j-1). */
+int cvl_scale_shape(const cvl_params *p, int j, int *Lj, int *Nj);
+
+/* Band-limit of the scaling-coefficient map, L_Phi = min(ceil(lambda^J0), L). */
+int cvl_scaling_bandlimit(const cvl_params *p, int *Lphi);
+
+/* Workspace bytes needed by cvl_curvelet_analysis / cvl_curvelet_synthesis
+ * for `batch` maps (the workspace is reused map after map). */
+int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes);
+
+/* Workspace bytes needed by the SHT (L) and Wigner (L, N) entry points. */
+int cvl_sht_workspace_bytes(int L, size_t *bytes);
+int cvl_wigner_workspace_bytes(int L, int N, size_t *bytes);
+
+/* Build (synchronously) the tables of parameters `p` so that later calls with
+ * the same (L, lambda, J0) allocate nothing. */
+int cvl_prepare(cvl_ctx *ctx, const cvl_params *p);
+
+/* Forward SHT of a real spin-0 map (L x (2L-1) doubles) to f_lm (L^2 complex,
+ * negative m filled by f_{l,-m} = (-1)^m conj f_lm).  MW sampling theorem
+ * (Sec. III-A-2 applied with n = 0).  spin must be 0.  2 <= L <= L_max. */
+int cvl_sht_forward(cvl_ctx *ctx, int L, int spin, const double *map,
+                    cvl_c128 *flm, void *ws, size_t ws_bytes, void *stream);
+
+/* Inverse SHT to a real map: uses f_lm for m >= 0 and assumes the reality
+ * condition for m < 0 (the m < 0 entries are not read). */
+int cvl_sht_inverse(cvl_ctx *ctx, int L, int spin, const cvl_c128 *flm,
+                    double *map, void *ws, size_t ws_bytes, void *stream);
+
+/* Inverse Wigner transform (Sec. II-A, Sec. III-A-2): complex grid
+ * W(rho) = sum_lmn (2l+1)/(8pi^2) F^l_mn D^{l*}_mn(rho), general complex F,
+ * 1 <= N <= L <= L_max. */
+int cvl_wigner_inverse(cvl_ctx *ctx, int L, int N, const cvl_c128 *flmn,
+                       cvl_c128 *grid, void *ws, size_t ws_bytes, void *stream);
+
+/* Forward Wigner transform (exact for band-limited grids):
+ * F^l_mn = <W, D^{l*}_mn>, via the alpha/gamma DFT, the beta extension, the
+ * beta DFT, the sin(beta) weight correlation and the Delta projection
+ * (Sec. III-A-2). */
+int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid,
+                       cvl_c128 *flmn, void *ws, size_t ws_bytes, void *stream);
+
+/* Curvelet analysis (Sec. II-D-1) of `batch` real maps (contiguous,
+ * batch x L x (2L-1) doubles).  Outputs per map i:
+ *   scal_maps + i * L_Phi * (2L_Phi-1): the scaling coefficients as a real MW
+ *     map of band-limit L_Phi;
+ *   grids[i * nJ + (j - J0)], nJ = J - J0 + 1: complex128 SO(3) grid
+ *     W^(j)[a][b][g] of scale j, (2L_j-1) x L_j x (2L_j-1).  For a real map the
+ *     curvelet coefficients are real: the imaginary parts are written as 0.
+ * `grids` is a HOST array of batch * nJ device pointers. */
+int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
+                          const double *maps, double *scal_maps,
+                          cvl_c128 *const *grids, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* Curvelet synthesis (Sec. II-D-2, exact reconstruction): the inverse of
+ * cvl_curvelet_analysis on its range.  Reads the full complex grids.  Writes
+ * `batch` real maps.  Same layouts as cvl_curvelet_analysis. */
+int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
+                           const double *scal_maps, const cvl_c128 *const *grids,
+                           double *maps, void *ws, size_t ws_bytes, void *stream);
+
+/* Host copy of the kernel tables of `p` (no device work; usable without a
+ * GPU): kappa[(j - J0) * L + l] = kappa^(j)(l) for J0 <= j <= J, and
+ * phi[l] = Phi_l0 (Sec. II-B).  kappa needs (J - J0 + 1) * L doubles, phi L. */
+int cvl_kernel_tables(const cvl_params *p, double *kappa, double *phi);
+
+/* Per-stage device time accounting for benchmarks.  When enabled, every
+ * kernel launch of the calls that follow is bracketed by HIP events on the
+ * call's stream; cvl_profile_read synchronises those events and returns, for
+ * stage index i < *n, its name, launch count and total milliseconds. */
+int cvl_profile_enable(cvl_ctx *ctx, int on);
+int cvl_profile_read(cvl_ctx *ctx, int max, int *n, const char **names,
+                     int *launches, double *ms);
+
+/* Copy block l of the resident Delta table to host memory (synchronous):
+ * out[m' * (l+1) + m] = Delta^l_{m'm} = d^l_{m'm}(pi/2), 0 <= m', m <= l < L_max. */
+int cvl_delta_block(cvl_ctx *ctx, int l, double *out);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *cvl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CURVELET_H */

@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libcurvelet.so (include/curvelet.h).
+
+Argument marshalling only: every step of every transform runs in the HIP
+kernels of the library.  PyTorch provides device memory and the current
+stream.  Importing this module loads the library and raises if it has not
+been built (``python -m paper_1511_05578_amd.build``); there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcurvelet.so")
+
+CVL_OK, CVL_EINVAL, CVL_ENOMEM, CVL_EDEVICE, CVL_EUNSUPPORTED = 0, -1, -2, -3, -4
+CVL_REAL = 1
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_size_p = ctypes.POINTER(ctypes.c_size_t)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class CvlParams(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("N", ctypes.c_int), ("lambda_", ctypes.c_double),
+                ("J0", ctypes.c_int), ("spin", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "cvl_context_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int]),
+    "cvl_context_destroy": (None, [ctypes.c_void_p]),
+    "cvl_num_scales": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_int_p]),
+    "cvl_scale_shape": (ctypes.c_int, [ctypes.POINTER(CvlParams), ctypes.c_int, _c_int_p, _c_int_p]),
+    "cvl_scaling_bandlimit": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_int_p]),
+    "cvl_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(CvlParams), ctypes.c_int, _c_size_p]),
+    "cvl_sht_workspace_bytes": (ctypes.c_int, [ctypes.c_int, _c_size_p]),
+    "cvl_wigner_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_size_p]),
+    "cvl_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams)]),
+    "cvl_sht_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_sht_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_wigner_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_wigner_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_curvelet_analysis": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams), ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_curvelet_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams), ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                              ctypes.c_void_p]),
+    "cvl_kernel_tables": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_double_p, _c_double_p]),
+    "cvl_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "cvl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p,
+                                        ctypes.POINTER(ctypes.c_char_p), _c_int_p, _c_double_p]),
+    "cvl_delta_block": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p]),
+    "cvl_last_error": (ctypes.c_char_p, []),
+}
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError("libcurvelet.so is not built: run `python -m paper_1511_05578_amd.build`")
+lib = ctypes.CDLL(_LIB_PATH)
+for _name, (_res, _args) in SIGNATURES.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class CvlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("cvl error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != CVL_OK:
+        raise CvlError(rc, lib.cvl_last_error().decode())
+
+
+def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL):
+    return CvlParams(L, N, float(lam), J0, spin, flags)
+
+
+def num_scales(L, lam=2.0, J0=2):
+    J = ctypes.c_int()
+    _check(lib.cvl_num_scales(ctypes.byref(params(L, lam, J0)), ctypes.byref(J)))
+    return J.value
+
+
+def scale_shape(L, j, lam=2.0, J0=2):
+    Lj, Nj = ctypes.c_int(), ctypes.c_int()
+    _check(lib.cvl_scale_shape(ctypes.byref(params(L, lam, J0)), j, ctypes.byref(Lj), ctypes.byref(Nj)))
+    return Lj.value, Nj.value
+
+
+def scaling_bandlimit(L, lam=2.0, J0=2):
+    v = ctypes.c_int()
+    _check(lib.cvl_scaling_bandlimit(ctypes.byref(params(L, lam, J0)), ctypes.byref(v)))
+    return v.value
+
+
+def workspace_bytes(L, lam=2.0, J0=2, batch=1):
+    v = ctypes.c_size_t()
+    _check(lib.cvl_workspace_bytes(ctypes.byref(params(L, lam, J0)), batch, ctypes.byref(v)))
+    return v.value
+
+
+def kernel_tables(L, lam=2.0, J0=2):
+    """Host tables (no GPU): kappa[j - J0, l] and phi[l]."""
+    J = num_scales(L, lam, J0)
+    kap = np.zeros((J - J0 + 1, L))
+    phi = np.zeros(L)
+    _check(lib.cvl_kernel_tables(ctypes.byref(params(L, lam, J0)),
+                                 kap.ctypes.data_as(_c_double_p), phi.ctypes.data_as(_c_double_p)))
+    return kap, phi
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """Resident Delta table (and kernel / DFT tables built on first use)."""
+
+    def __init__(self, L_max, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.L_max = L_max
+        h = ctypes.c_void_p()
+        _check(lib.cvl_context_create(ctypes.byref(h), L_max, device))
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.cvl_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes):
+        t = self.torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = t.empty(max(nbytes, 256), dtype=t.uint8, device=self.device)
+        return self._ws
+
+    def prepare(self, L, lam=2.0, J0=2):
+        _check(lib.cvl_prepare(self.h, ctypes.byref(params(L, lam, J0))))
+
+    # ---- SHT ----
+    def sht_forward(self, fmap, out=None):
+        t = self.torch
+        L = fmap.shape[-2]
+        assert fmap.dtype == t.float64 and fmap.is_contiguous() and fmap.shape[-1] == 2 * L - 1
+        if out is None:
+            out = t.empty(L * L, dtype=t.complex128, device=self.device)
+        nb = ctypes.c_size_t()
+        _check(lib.cvl_sht_workspace_bytes(L, ctypes.byref(nb)))
+        ws = self.workspace(nb.value)
+        _check(lib.cvl_sht_forward(self.h, L, 0, fmap.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), _stream(t)))
+        return out
+
+    def sht_inverse(self, flm, L, out=None):
+        t = self.torch
+        assert flm.dtype == t.complex128 and flm.is_contiguous() and flm.numel() == L * L
+        if out is None:
+            out = t.empty((L, 2 * L - 1), dtype=t.float64, device=self.device)
+        nb = ctypes.c_size_t()
+        _check(lib.cvl_sht_workspace_bytes(L, ctypes.byref(nb)))
+        ws = self.workspace(nb.value)
+        _check(lib.cvl_sht_inverse(self.h, L, 0, flm.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), _stream(t)))
+        return out
+
+    # ---- Wigner ----
+    def wigner_inverse(self, F, L, N, out=None):
+        t = self.torch
+        assert F.dtype == t.complex128 and F.is_contiguous() and F.shape == (L, 2 * L - 1, 2 * N - 1)
+        if out is None:
+            out = t.empty((2 * L - 1, L, 2 * N - 1), dtype=t.complex128, device=self.device)
+        nb = ctypes.c_size_t()
+        _check(lib.cvl_wigner_workspace_bytes(L, N, ctypes.byref(nb)))
+        ws = self.workspace(nb.value)
+        _check(lib.cvl_wigner_inverse(self.h, L, N, F.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _stream(t)))
+        return out
+
+    def wigner_forward(self, grid, L, N, out=None):
+        t = self.torch
+        assert grid.dtype == t.complex128 and grid.is_contiguous() and grid.shape == (2 * L - 1, L, 2 * N - 1)
+        if out is None:
+            out = t.empty((L, 2 * L - 1, 2 * N - 1), dtype=t.complex128, device=self.device)
+        nb = ctypes.c_size_t()
+        _check(lib.cvl_wigner_workspace_bytes(L, N, ctypes.byref(nb)))
+        ws = self.workspace(nb.value)
+        _check(lib.cvl_wigner_forward(self.h, L, N, grid.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _stream(t)))
+        return out
+
+    # ---- curvelets ----
+    def grid_shapes(self, L, lam=2.0, J0=2):
+        J = num_scales(L, lam, J0)
+        out = []
+        for j in range(J0, J + 1):
+            Lj, Nj = scale_shape(L, j, lam, J0)
+            out.append((2 * Lj - 1, Lj, 2 * Nj - 1))
+        return out
+
+    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1):
+        t = self.torch
+        Lp = scaling_bandlimit(L, lam, J0)
+        scal = t.empty((batch, Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
+        grids = [[t.empty(s, dtype=t.complex128, device=self.device)
+                  for s in self.grid_shapes(L, lam, J0)] for _ in range(batch)]
+        return scal, grids
+
+    def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None):
+        """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids)."""
+        t = self.torch
+        single = maps.dim() == 2
+        if single:
+            maps = maps.unsqueeze(0)
+        assert maps.dtype == t.float64 and maps.is_contiguous()
+        batch, L = maps.shape[0], maps.shape[1]
+        if out is None:
+            out = self.alloc_outputs(L, lam, J0, batch)
+        scal, grids = out
+        flat = [g for per in grids for g in per]
+        arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch))
+        _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(params(L, lam, J0)), batch,
+                                         maps.data_ptr(), scal.data_ptr(), arr, ws.data_ptr(),
+                                         ws.numel(), _stream(t)))
+        if single:
+            return scal[0], grids[0]
+        return scal, grids
+
+    def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None):
+        t = self.torch
+        single = scal.dim() == 2
+        if single:
+            scal = scal.unsqueeze(0)
+            grids = [grids]
+        batch = scal.shape[0]
+        if out is None:
+            out = t.empty((batch, L, 2 * L - 1), dtype=t.float64, device=self.device)
+        flat = [g for per in grids for g in per]
+        for g in flat:
+            assert g.dtype == t.complex128 and g.is_contiguous()
+        arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch))
+        _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(params(L, lam, J0)), batch,
+                                          scal.data_ptr(), arr, out.data_ptr(), ws.data_ptr(),
+                                          ws.numel(), _stream(t)))
+        return out[0] if single else out
+
+    def delta_block(self, l):
+        out = np.zeros((l + 1, l + 1))
+        _check(lib.cvl_delta_block(self.h, l, out.ctypes.data_as(_c_double_p)))
+        return out
+
+    # ---- profiling ----
+    def profile_enable(self, on=True):
+        _check(lib.cvl_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        n = ctypes.c_int()
+        mx = 32
+        names = (ctypes.c_char_p * mx)()
+        launches = (ctypes.c_int * mx)()
+        ms = (ctypes.c_double * mx)()
+        _check(lib.cvl_profile_read(self.h, mx, ctypes.byref(n), names, launches, ms))
+        return {names[i].decode(): (launches[i], ms[i]) for i in range(min(n.value, mx))}

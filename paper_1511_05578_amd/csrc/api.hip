@@ -1,0 +1,881 @@
+// C ABI of the curvelet transform: validation, resident tables, workspace
+// carving and the launch sequences of every entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/curvelet.h"
+#include "cvl_device.h"
+#include "host_tables.h"
+
+using namespace cvl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e__ = (expr);                                                           \
+        if (e__ != hipSuccess)                                                             \
+            return fail(CVL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e__));      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum Stage {
+    ST_SHT_PHI,
+    ST_SHT_THETA,
+    ST_SHT_DELTA,
+    ST_CONTRACT_INV,
+    ST_BETA_INV,
+    ST_ALPHA_INV,
+    ST_GAMMA_INV,
+    ST_GAMMA_FWD,
+    ST_ALPHA_FWD,
+    ST_BETA_FWD,
+    ST_CONTRACT_FWD,
+    ST_REDUCE_FWD,
+    ST_MISC,
+    ST_COUNT
+};
+const char *kStageNames[ST_COUNT] = {"sht_phi_dft",     "sht_theta",       "sht_delta",
+                                     "contract_inv",    "beta_gemm_inv",   "alpha_dft_inv",
+                                     "gamma_dft_inv",   "gamma_dft_fwd",   "alpha_dft_fwd",
+                                     "beta_gemm_fwd",   "contract_fwd",    "reduce_fwd",
+                                     "misc"};
+
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    ~DeviceArena() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    int upload(const std::vector<T> &v, T **out) {
+        void *p = nullptr;
+        size_t bytes = v.size() * sizeof(T);
+        if (bytes == 0) bytes = sizeof(T);
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return fail(CVL_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        ptrs.push_back(p);
+        if (!v.empty()) {
+            e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(CVL_EDEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+        }
+        *out = (T *)p;
+        return CVL_OK;
+    }
+};
+
+struct BetaTabs {  // parity-folded beta matrices of one band-limit
+    double *Cinv = nullptr, *Sinv = nullptr, *Qp = nullptr, *Qs = nullptr;
+};
+
+struct ScaleRt {
+    int j;
+    ScaleGeom g;
+    double *psi;  // [l][k]: Psi^(j)_{l,2k}
+    BetaTabs beta;
+    BluesteinDev inv_full, fwd_full, fwd_half;
+};
+
+struct Plan {
+    int L, J0, J, Lphi;
+    double lambda;
+    std::vector<ScaleRt> scales;
+    double *phifac;  // [Lphi]: sqrt(4pi/(2l+1)) Phi_l0
+    int ngroups;
+    size_t ws_per_map;  // bytes
+};
+
+struct ShtRt {
+    int L;
+    BetaTabs beta;  // factor 2 pi
+    BluesteinDev inv, fwd;
+};
+
+struct GenRt {
+    int L, N;
+    BetaTabs beta;  // factor (2 pi)^2
+    BluesteinDev a_inv, a_fwd, g_inv, g_fwd;
+};
+
+}  // namespace
+
+struct cvl_ctx {
+    int device = 0;
+    int Lmax = 0;
+    double *delta = nullptr;
+    std::mutex mu;
+    DeviceArena arena;
+    std::map<int, cd *> tw;
+    std::map<std::tuple<int, int, int, int, int, int, int>, BluesteinDev> blue;
+    std::map<std::pair<int, int>, BetaTabs> beta;  // (L, factor id)
+    std::map<std::tuple<int, double, int>, std::unique_ptr<Plan>> plans;
+    std::map<int, std::unique_ptr<ShtRt>> sht;
+    std::map<std::pair<int, int>, std::unique_ptr<GenRt>> gen;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
+    double stage_ms[ST_COUNT] = {0};
+    int stage_n[ST_COUNT] = {0};
+};
+
+namespace {
+
+int get_twiddles(cvl_ctx *c, int P, const cd **out) {
+    auto it = c->tw.find(P);
+    if (it != c->tw.end()) {
+        *out = it->second;
+        return CVL_OK;
+    }
+    auto t = host::twiddles(P);
+    std::vector<cd> v(P);
+    for (int i = 0; i < P; ++i) v[i] = cd{t[i].real(), t[i].imag()};
+    cd *d;
+    int rc = c->arena.upload(v, &d);
+    if (rc) return rc;
+    c->tw[P] = d;
+    *out = d;
+    return CVL_OK;
+}
+
+int get_bluestein(cvl_ctx *c, int Nd, int Kin, int j0, int Kout, int k0, int sigma,
+                  BluesteinDev *out) {
+    auto key = std::make_tuple(Nd, Kin, j0, Kout, k0, sigma, 0);
+    auto it = c->blue.find(key);
+    if (it != c->blue.end()) {
+        *out = it->second;
+        return CVL_OK;
+    }
+    const double scale = sigma < 0 ? 1.0 / Nd : 1.0;
+    host::Bluestein B = host::make_bluestein(Nd, Kin, j0, Kout, k0, sigma, scale);
+    if (B.P > 4096) return fail(CVL_EUNSUPPORTED, "DFT length %d needs FFT size %d > 4096", Nd, B.P);
+    auto cv = [](const std::vector<std::complex<double>> &s) {
+        std::vector<cd> v(s.size());
+        for (size_t i = 0; i < s.size(); ++i) v[i] = cd{s[i].real(), s[i].imag()};
+        return v;
+    };
+    BluesteinDev D{};
+    D.Nd = Nd;
+    D.P = B.P;
+    D.Kin = Kin;
+    D.j0 = j0;
+    D.Kout = Kout;
+    D.k0 = k0;
+    cd *pre, *post, *vhat;
+    int rc;
+    if ((rc = c->arena.upload(cv(B.pre), &pre))) return rc;
+    if ((rc = c->arena.upload(cv(B.post), &post))) return rc;
+    if ((rc = c->arena.upload(cv(B.vhat), &vhat))) return rc;
+    const cd *tw;
+    if ((rc = get_twiddles(c, B.P, &tw))) return rc;
+    D.pre = pre;
+    D.post = post;
+    D.vhat = vhat;
+    D.tw = tw;
+    c->blue[key] = D;
+    *out = D;
+    return CVL_OK;
+}
+
+// factor id 0: (2 pi)^2 (Wigner), 1: 2 pi (SHT)
+int get_beta(cvl_ctx *c, int L, int fid, BetaTabs *out) {
+    auto key = std::make_pair(L, fid);
+    auto it = c->beta.find(key);
+    if (it != c->beta.end()) {
+        *out = it->second;
+        return CVL_OK;
+    }
+    std::vector<double> C, S, Qp, Qs;
+    host::beta_inverse_mats(L, C, S);
+    host::beta_forward_mats(L, fid == 0 ? 4.0 * M_PI * M_PI : 2.0 * M_PI, Qp, Qs);
+    BetaTabs T;
+    int rc;
+    if ((rc = c->arena.upload(C, &T.Cinv))) return rc;
+    if ((rc = c->arena.upload(S, &T.Sinv))) return rc;
+    if ((rc = c->arena.upload(Qp, &T.Qp))) return rc;
+    if ((rc = c->arena.upload(Qs, &T.Qs))) return rc;
+    c->beta[key] = T;
+    *out = T;
+    return CVL_OK;
+}
+
+int num_scales(int L, double lam) {
+    int J = 0;
+    double p = 1.0;
+    while (p < L) {
+        p *= lam;
+        ++J;
+    }
+    return J;
+}
+int scale_bandlimit(int j, int L, double lam) {
+    double v = std::ceil(std::pow(lam, j + 1) - 1e-9);
+    return v >= L ? L : (int)v;
+}
+int scaling_bandlimit(int L, double lam, int J0) {
+    double v = std::ceil(std::pow(lam, J0) - 1e-9);
+    return v >= L ? L : (int)v;
+}
+
+int check_params(const cvl_params *p, int *J) {
+    if (!p) return fail(CVL_EINVAL, "params is NULL");
+    if (p->L < 2 || p->L > 2048) return fail(CVL_EINVAL, "L=%d outside [2, 2048]", p->L);
+    if (p->N != 0 && p->N != p->L)
+        return fail(CVL_EINVAL, "N=%d: curvelets have no azimuthal band-limit, N must be 0 or L",
+                    p->N);
+    if (!(p->lambda > 1.0) || !std::isfinite(p->lambda))
+        return fail(CVL_EINVAL, "lambda=%g must be a finite number > 1", p->lambda);
+    int JJ = num_scales(p->L, p->lambda);
+    if (p->J0 < 1 || p->J0 > JJ)
+        return fail(CVL_EINVAL, "J0=%d outside [1, J=%d]", p->J0, JJ);
+    if (p->spin != 0) return fail(CVL_EUNSUPPORTED, "spin=%d: only spin 0 is implemented", p->spin);
+    if (!(p->flags & CVL_REAL))
+        return fail(CVL_EUNSUPPORTED, "complex maps are not implemented: set CVL_REAL");
+    if (J) *J = JJ;
+    return CVL_OK;
+}
+
+ScaleGeom geom_of(int Lj) {
+    ScaleGeom g{};
+    g.L = Lj;
+    g.Nm = 2 * Lj - 1;
+    g.h = (Lj - 1) / 2;
+    g.Ne = 2 * g.h + 1;
+    g.Nep = (g.Ne + 31) / 32 * 32;
+    g.llo = 0;
+    g.lhi = Lj - 1;
+    return g;
+}
+
+size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int ngroups) {
+    size_t b0 = 0, b1 = 0;
+    for (int j = J0; j <= J; ++j) {
+        ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
+        size_t cube = (size_t)g.L * g.L * g.Nep;
+        size_t w2 = (size_t)g.L * g.Nm * (g.h + 1);
+        size_t v1 = (size_t)g.L * g.Nm * g.Nep;
+        size_t part = (size_t)ngroups * g.L * g.L;
+        b0 = std::max({b0, cube, w2, v1});
+        b1 = std::max({b1, cube, part});
+    }
+    const int Lphi = scaling_bandlimit(L, lam, J0);
+    size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
+    return align_up(b0 * 16) + align_up(b1 * 16) + align_up(small * 16) + 4 * kAlign;
+}
+
+int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
+    int J;
+    int rc = check_params(p, &J);
+    if (rc) return rc;
+    if (p->L > c->Lmax) return fail(CVL_EINVAL, "L=%d exceeds the context's L_max=%d", p->L, c->Lmax);
+    auto key = std::make_tuple(p->L, p->lambda, p->J0);
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+        *out = it->second.get();
+        return CVL_OK;
+    }
+    std::unique_ptr<Plan> P(new Plan);
+    P->L = p->L;
+    P->J0 = p->J0;
+    P->J = J;
+    P->lambda = p->lambda;
+    P->Lphi = scaling_bandlimit(p->L, p->lambda, p->J0);
+    P->ngroups = 32;
+    const int L = p->L;
+    std::vector<double> kap = host::kappa_table(L, p->lambda, p->J0, J);
+    std::vector<double> phi = host::phi_table(L, p->lambda, p->J0);
+    std::vector<double> acol = host::delta_col_l(L);
+    for (int j = p->J0; j <= J; ++j) {
+        ScaleRt S{};
+        S.j = j;
+        const int Lj = scale_bandlimit(j, L, p->lambda);
+        S.g = geom_of(Lj);
+        const double *kj = &kap[(size_t)(j - p->J0) * L];
+        int llo = Lj, lhi = Lj - 1;
+        for (int l = 0; l < Lj; ++l)
+            if (kj[l] > 0.0) {
+                if (l < llo) llo = l;
+                lhi = l;
+            }
+        S.g.llo = llo;
+        S.g.lhi = lhi;
+        const int h = S.g.h;
+        std::vector<double> psi((size_t)Lj * (h + 1), 0.0);
+        for (int l = 0; l < Lj; ++l)
+            for (int k = 0; 2 * k <= l && k <= h; ++k)
+                psi[(size_t)l * (h + 1) + k] = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) *
+                                               kj[l] * std::sqrt(2.0) * acol[(size_t)l * L + 2 * k];
+        if ((rc = c->arena.upload(psi, &S.psi))) return rc;
+        if ((rc = get_beta(c, Lj, 0, &S.beta))) return rc;
+        const int Nm = 2 * Lj - 1;
+        if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full))) return rc;
+        if ((rc = get_bluestein(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full))) return rc;
+        if ((rc = get_bluestein(c, Nm, Nm, 0, Lj, 0, -1, &S.fwd_half))) return rc;
+        P->scales.push_back(S);
+    }
+    std::vector<double> pf(P->Lphi);
+    for (int l = 0; l < P->Lphi; ++l) pf[l] = std::sqrt(4.0 * M_PI / (2.0 * l + 1.0)) * phi[l];
+    if ((rc = c->arena.upload(pf, &P->phifac))) return rc;
+    P->ws_per_map = curvelet_ws_bytes(L, p->lambda, p->J0, J, P->ngroups);
+    *out = P.get();
+    c->plans[key] = std::move(P);
+    return CVL_OK;
+}
+
+int get_sht(cvl_ctx *c, int L, ShtRt **out) {
+    // caller holds c->mu
+    auto it = c->sht.find(L);
+    if (it != c->sht.end()) {
+        *out = it->second.get();
+        return CVL_OK;
+    }
+    std::unique_ptr<ShtRt> S(new ShtRt);
+    S->L = L;
+    int rc;
+    if ((rc = get_beta(c, L, 1, &S->beta))) return rc;
+    const int Nm = 2 * L - 1;
+    if ((rc = get_bluestein(c, Nm, Nm, -(L - 1), Nm, 0, +1, &S->inv))) return rc;
+    if ((rc = get_bluestein(c, Nm, Nm, 0, L, 0, -1, &S->fwd))) return rc;
+    *out = S.get();
+    c->sht[L] = std::move(S);
+    return CVL_OK;
+}
+
+// ---- profiling ----
+struct Prof {
+    cvl_ctx *c;
+    hipStream_t st;
+    int stage;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Prof(cvl_ctx *c_, hipStream_t s, int stg) : c(c_), st(s), stage(stg) {
+        if (!c->prof) return;
+        e0 = take();
+        e1 = take();
+        if (e0) (void)hipEventRecord(e0, st);
+    }
+    hipEvent_t take() {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (!c->pool.empty()) {
+            hipEvent_t e = c->pool.back();
+            c->pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Prof() {
+        if (!c->prof || !e0 || !e1) return;
+        (void)hipEventRecord(e1, st);
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->rec.emplace_back(stage, e0, e1);
+    }
+};
+
+#define LAUNCH(stage, call)                                                                \
+    do {                                                                                   \
+        Prof pr__(ctx, st, stage);                                                         \
+        hipError_t e__ = (call);                                                           \
+        if (e__ != hipSuccess)                                                             \
+            return fail(CVL_EDEVICE, "launch of %s failed: %s", kStageNames[stage],        \
+                        hipGetErrorString(e__));                                           \
+    } while (0)
+
+struct Carver {
+    char *p;
+    size_t left;
+    template <class T>
+    T *take(size_t n) {
+        size_t b = align_up(n * sizeof(T));
+        if (b > left) return nullptr;
+        T *r = (T *)p;
+        p += b;
+        left -= b;
+        return r;
+    }
+};
+
+// ---- SHT launch sequences (device scratch passed in) ----
+int sht_forward_run(cvl_ctx *ctx, ShtRt *S, const double *map, cd *fpad, int Lf, cd *F1,
+                    cd *Zs, hipStream_t st) {
+    const int L = S->L;
+    LAUNCH(ST_SHT_PHI, launch_sht_fwd_phi(L, S->fwd, map, F1, st));
+    LAUNCH(ST_SHT_THETA, launch_sht_theta(L, L, L, 1, S->beta.Qp, S->beta.Qs, F1, Zs, st));
+    LAUNCH(ST_SHT_DELTA, launch_sht_fwd_delta(L, Lf, ctx->delta, Zs, fpad, st));
+    return CVL_OK;
+}
+
+int sht_inverse_run(cvl_ctx *ctx, ShtRt *S, const cd *fpad, int Lf, double *map, cd *F,
+                    cd *G, hipStream_t st) {
+    const int L = S->L;
+    LAUNCH(ST_SHT_DELTA, launch_sht_inv_delta(L, Lf, ctx->delta, fpad, F, st));
+    LAUNCH(ST_SHT_THETA, launch_sht_theta(L, L, L, 0, S->beta.Cinv, S->beta.Sinv, F, G, st));
+    LAUNCH(ST_SHT_PHI, launch_sht_inv_phi(L, S->inv, G, map, st));
+    return CVL_OK;
+}
+
+int check_ctx(cvl_ctx *ctx) {
+    if (!ctx) return fail(CVL_EINVAL, "context is NULL");
+    return CVL_OK;
+}
+
+int set_device(cvl_ctx *ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(CVL_EDEVICE, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
+    return CVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cvl_last_error(void) { return g_err.c_str(); }
+
+int cvl_context_create(cvl_ctx **out, int L_max, int device) {
+    g_err.clear();
+    if (!out) return fail(CVL_EINVAL, "ctx out-pointer is NULL");
+    *out = nullptr;
+    if (L_max < 2 || L_max > 2048) return fail(CVL_EINVAL, "L_max=%d outside [2, 2048]", L_max);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(CVL_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(CVL_EINVAL, "device=%d outside [0, %d)", device, ndev);
+    std::unique_ptr<cvl_ctx> c(new cvl_ctx);
+    c->device = device;
+    c->Lmax = L_max;
+    HIP_TRY(hipSetDevice(device));
+    size_t n = (size_t)delta_off(L_max);
+    void *p = nullptr;
+    e = hipMalloc(&p, n * sizeof(double));
+    if (e != hipSuccess) return fail(CVL_ENOMEM, "Delta table of %zu bytes: %s", n * sizeof(double), hipGetErrorString(e));
+    c->arena.ptrs.push_back(p);
+    c->delta = (double *)p;
+    HIP_TRY(launch_delta_toprows(c->delta, L_max, nullptr));
+    HIP_TRY(launch_delta_fill(c->delta, L_max, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    *out = c.release();
+    return CVL_OK;
+}
+
+void cvl_context_destroy(cvl_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &r : ctx->rec) {
+        (void)hipEventDestroy(std::get<1>(r));
+        (void)hipEventDestroy(std::get<2>(r));
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int cvl_num_scales(const cvl_params *p, int *J) {
+    g_err.clear();
+    if (!J) return fail(CVL_EINVAL, "J out-pointer is NULL");
+    return check_params(p, J);
+}
+
+int cvl_scale_shape(const cvl_params *p, int j, int *Lj, int *Nj) {
+    g_err.clear();
+    int J, rc = check_params(p, &J);
+    if (rc) return rc;
+    if (j < p->J0 || j > J) return fail(CVL_EINVAL, "scale j=%d outside [%d, %d]", j, p->J0, J);
+    if (!Lj || !Nj) return fail(CVL_EINVAL, "output pointer is NULL");
+    *Lj = scale_bandlimit(j, p->L, p->lambda);
+    *Nj = *Lj;
+    return CVL_OK;
+}
+
+int cvl_scaling_bandlimit(const cvl_params *p, int *Lphi) {
+    g_err.clear();
+    int rc = check_params(p, nullptr);
+    if (rc) return rc;
+    if (!Lphi) return fail(CVL_EINVAL, "output pointer is NULL");
+    *Lphi = scaling_bandlimit(p->L, p->lambda, p->J0);
+    return CVL_OK;
+}
+
+int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
+    g_err.clear();
+    int J, rc = check_params(p, &J);
+    if (rc) return rc;
+    if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
+    if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
+    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, 32);
+    return CVL_OK;
+}
+
+int cvl_sht_workspace_bytes(int L, size_t *bytes) {
+    g_err.clear();
+    if (L < 2 || L > 2048) return fail(CVL_EINVAL, "L=%d outside [2, 2048]", L);
+    if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
+    *bytes = 3 * align_up((size_t)L * L * 16) + kAlign;
+    return CVL_OK;
+}
+
+int cvl_wigner_workspace_bytes(int L, int N, size_t *bytes) {
+    g_err.clear();
+    if (L < 1 || L > 2048 || N < 1 || N > L) return fail(CVL_EINVAL, "need 1 <= N <= L <= 2048 (L=%d, N=%d)", L, N);
+    if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
+    const size_t Nnp = ((2 * N - 1) + 31) / 32 * 32;
+    const size_t one = (size_t)L * (2 * L - 1) * Nnp * 16;
+    *bytes = 2 * align_up(one) + kAlign;
+    return CVL_OK;
+}
+
+int cvl_prepare(cvl_ctx *ctx, const cvl_params *p) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    Plan *P;
+    if ((rc = get_plan(ctx, p, &P))) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ShtRt *S;
+    if ((rc = get_sht(ctx, P->L, &S))) return rc;
+    if ((rc = get_sht(ctx, P->Lphi, &S))) return rc;
+    return CVL_OK;
+}
+
+int cvl_kernel_tables(const cvl_params *p, double *kappa, double *phi) {
+    g_err.clear();
+    int J, rc = check_params(p, &J);
+    if (rc) return rc;
+    if (!kappa || !phi) return fail(CVL_EINVAL, "output pointer is NULL");
+    auto k = host::kappa_table(p->L, p->lambda, p->J0, J);
+    auto f = host::phi_table(p->L, p->lambda, p->J0);
+    std::memcpy(kappa, k.data(), k.size() * sizeof(double));
+    std::memcpy(phi, f.data(), f.size() * sizeof(double));
+    return CVL_OK;
+}
+
+int cvl_sht_forward(cvl_ctx *ctx, int L, int spin, const double *map, cvl_c128 *flm, void *ws,
+                    size_t ws_bytes, void *stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (L < 2 || L > ctx->Lmax) return fail(CVL_EINVAL, "L=%d outside [2, L_max=%d]", L, ctx->Lmax);
+    if (spin != 0) return fail(CVL_EUNSUPPORTED, "spin=%d: only spin 0 is implemented", spin);
+    if (!map || !flm || !ws) return fail(CVL_EINVAL, "NULL device pointer");
+    size_t need;
+    cvl_sht_workspace_bytes(L, &need);
+    if (ws_bytes < need) return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    if ((rc = set_device(ctx))) return rc;
+    ShtRt *S;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if ((rc = get_sht(ctx, L, &S))) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Carver cv{(char *)ws, ws_bytes};
+    cd *fpad = cv.take<cd>((size_t)L * L);
+    cd *F1 = cv.take<cd>((size_t)L * L);
+    cd *Zs = cv.take<cd>((size_t)L * L);
+    if ((rc = sht_forward_run(ctx, S, map, fpad, L, F1, Zs, st))) return rc;
+    LAUNCH(ST_MISC, launch_flm_unpack(L, fpad, (cd *)flm, st));
+    return CVL_OK;
+}
+
+int cvl_sht_inverse(cvl_ctx *ctx, int L, int spin, const cvl_c128 *flm, double *map, void *ws,
+                    size_t ws_bytes, void *stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (L < 2 || L > ctx->Lmax) return fail(CVL_EINVAL, "L=%d outside [2, L_max=%d]", L, ctx->Lmax);
+    if (spin != 0) return fail(CVL_EUNSUPPORTED, "spin=%d: only spin 0 is implemented", spin);
+    if (!map || !flm || !ws) return fail(CVL_EINVAL, "NULL device pointer");
+    size_t need;
+    cvl_sht_workspace_bytes(L, &need);
+    if (ws_bytes < need) return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    if ((rc = set_device(ctx))) return rc;
+    ShtRt *S;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if ((rc = get_sht(ctx, L, &S))) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Carver cv{(char *)ws, ws_bytes};
+    cd *fpad = cv.take<cd>((size_t)L * L);
+    cd *F = cv.take<cd>((size_t)L * L);
+    cd *G = cv.take<cd>((size_t)L * L);
+    LAUNCH(ST_MISC, launch_flm_pack(L, (const cd *)flm, fpad, st));
+    return sht_inverse_run(ctx, S, fpad, L, map, F, G, st);
+}
+
+static int get_gen(cvl_ctx *ctx, int L, int N, GenRt **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto key = std::make_pair(L, N);
+    auto it = ctx->gen.find(key);
+    if (it != ctx->gen.end()) {
+        *out = it->second.get();
+        return CVL_OK;
+    }
+    std::unique_ptr<GenRt> G(new GenRt);
+    G->L = L;
+    G->N = N;
+    int rc;
+    if ((rc = get_beta(ctx, L, 0, &G->beta))) return rc;
+    const int Nm = 2 * L - 1, Ng = 2 * N - 1;
+    if ((rc = get_bluestein(ctx, Nm, Nm, -(L - 1), Nm, 0, +1, &G->a_inv))) return rc;
+    if ((rc = get_bluestein(ctx, Nm, Nm, 0, Nm, -(L - 1), -1, &G->a_fwd))) return rc;
+    if ((rc = get_bluestein(ctx, Ng, Ng, -(N - 1), Ng, 0, +1, &G->g_inv))) return rc;
+    if ((rc = get_bluestein(ctx, Ng, Ng, 0, Ng, -(N - 1), -1, &G->g_fwd))) return rc;
+    *out = G.get();
+    ctx->gen[key] = std::move(G);
+    return CVL_OK;
+}
+
+static int check_wigner(cvl_ctx *ctx, int L, int N, const void *a, const void *b, void *ws,
+                        size_t ws_bytes) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (L < 1 || L > ctx->Lmax || N < 1 || N > L)
+        return fail(CVL_EINVAL, "need 1 <= N <= L <= L_max=%d (L=%d, N=%d)", ctx->Lmax, L, N);
+    if (!a || !b || !ws) return fail(CVL_EINVAL, "NULL device pointer");
+    size_t need;
+    cvl_wigner_workspace_bytes(L, N, &need);
+    if (ws_bytes < need) return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    return CVL_OK;
+}
+
+int cvl_wigner_inverse(cvl_ctx *ctx, int L, int N, const cvl_c128 *flmn, cvl_c128 *grid, void *ws,
+                       size_t ws_bytes, void *stream) {
+    g_err.clear();
+    int rc = check_wigner(ctx, L, N, flmn, grid, ws, ws_bytes);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    GenRt *G;
+    if ((rc = get_gen(ctx, L, N, &G))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t Nnp = ((2 * N - 1) + 31) / 32 * 32;
+    const size_t one = (size_t)L * (2 * L - 1) * Nnp;
+    Carver cv{(char *)ws, ws_bytes};
+    cd *b0 = cv.take<cd>(one);
+    cd *b1 = cv.take<cd>(one);
+    const int ncols = (2 * L - 1) * (int)Nnp;
+    LAUNCH(ST_CONTRACT_INV, launch_gen_contract_inv(L, N, ctx->delta, (const cd *)flmn, b0, st));
+    LAUNCH(ST_BETA_INV, launch_beta_gemm(L, L, ncols, (int)Nnp, 1, (L + N) & 1, G->beta.Cinv,
+                                         G->beta.Sinv, b0, b1, st));
+    LAUNCH(ST_ALPHA_INV, launch_gen_inv_alpha(L, N, G->a_inv, b1, b0, st));
+    LAUNCH(ST_GAMMA_INV, launch_gen_inv_gamma(L, N, G->g_inv, b0, (cd *)grid, st));
+    return CVL_OK;
+}
+
+int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid, cvl_c128 *flmn, void *ws,
+                       size_t ws_bytes, void *stream) {
+    g_err.clear();
+    int rc = check_wigner(ctx, L, N, grid, flmn, ws, ws_bytes);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    GenRt *G;
+    if ((rc = get_gen(ctx, L, N, &G))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t Nnp = ((2 * N - 1) + 31) / 32 * 32;
+    const size_t one = (size_t)L * (2 * L - 1) * Nnp;
+    Carver cv{(char *)ws, ws_bytes};
+    cd *b0 = cv.take<cd>(one);
+    cd *b1 = cv.take<cd>(one);
+    const int ncols = (2 * L - 1) * (int)Nnp;
+    LAUNCH(ST_GAMMA_FWD, launch_gen_fwd_gamma(L, N, G->g_fwd, (const cd *)grid, b0, st));
+    LAUNCH(ST_ALPHA_FWD, launch_gen_fwd_alpha(L, N, G->a_fwd, b0, b1, st));
+    LAUNCH(ST_BETA_FWD, launch_beta_gemm(L, L, ncols, (int)Nnp, 1, (L + N) & 1, G->beta.Qp,
+                                         G->beta.Qs, b1, b0, st));
+    LAUNCH(ST_CONTRACT_FWD, launch_gen_contract_fwd(L, N, ctx->delta, b0, (cd *)flmn, st));
+    return CVL_OK;
+}
+
+static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, const void *a,
+                               const void *b, const void *grids, void *ws, size_t ws_bytes,
+                               Plan **P) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
+    if (!a || !b || !grids || !ws) return fail(CVL_EINVAL, "NULL pointer argument");
+    if ((rc = set_device(ctx))) return rc;
+    if ((rc = get_plan(ctx, p, P))) return rc;
+    if (ws_bytes < (*P)->ws_per_map)
+        return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, (*P)->ws_per_map);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ShtRt *S;
+    if ((rc = get_sht(ctx, (*P)->L, &S))) return rc;
+    if ((rc = get_sht(ctx, (*P)->Lphi, &S))) return rc;
+    return CVL_OK;
+}
+
+struct CurveletBufs {
+    cd *b0, *b1, *fpad, *facc, *s0, *s1, *fphi;
+};
+
+static CurveletBufs carve_curvelet(const Plan *P, void *ws, size_t ws_bytes) {
+    size_t b0 = 0, b1 = 0;
+    for (const ScaleRt &S : P->scales) {
+        const ScaleGeom &g = S.g;
+        b0 = std::max({b0, (size_t)g.L * g.L * g.Nep, (size_t)g.L * g.Nm * (g.h + 1),
+                       (size_t)g.L * g.Nm * g.Nep});
+        b1 = std::max({b1, (size_t)g.L * g.L * g.Nep, (size_t)P->ngroups * g.L * g.L});
+    }
+    Carver cv{(char *)ws, ws_bytes};
+    CurveletBufs B;
+    B.b0 = cv.take<cd>(b0);
+    B.b1 = cv.take<cd>(b1);
+    const size_t L2 = (size_t)P->L * P->L;
+    B.fpad = cv.take<cd>(L2);
+    B.facc = cv.take<cd>(L2);
+    B.s0 = cv.take<cd>(L2);
+    B.s1 = cv.take<cd>(L2);
+    B.fphi = cv.take<cd>((size_t)P->Lphi * P->Lphi);
+    return B;
+}
+
+int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *maps,
+                          double *scal_maps, cvl_c128 *const *grids, void *ws, size_t ws_bytes,
+                          void *stream) {
+    g_err.clear();
+    Plan *P;
+    int rc = check_curvelet_call(ctx, p, batch, maps, scal_maps, grids, ws, ws_bytes, &P);
+    if (rc) return rc;
+    const int nJ = P->J - P->J0 + 1;
+    for (int i = 0; i < batch * nJ; ++i)
+        if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
+    ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
+    hipStream_t st = (hipStream_t)stream;
+    CurveletBufs B = carve_curvelet(P, ws, ws_bytes);
+    const int L = P->L, Lp = P->Lphi;
+    for (int bi = 0; bi < batch; ++bi) {
+        const double *map = maps + (size_t)bi * L * (2 * L - 1);
+        double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        if ((rc = sht_forward_run(ctx, SL, map, B.fpad, L, B.s0, B.s1, st))) return rc;
+        LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
+        if ((rc = sht_inverse_run(ctx, SP, B.fphi, Lp, smap, B.s0, B.s1, st))) return rc;
+        for (int s = 0; s < nJ; ++s) {
+            const ScaleRt &S = P->scales[s];
+            const ScaleGeom &g = S.g;
+            cd *grid = (cd *)grids[(size_t)bi * nJ + s];
+            LAUNCH(ST_CONTRACT_INV,
+                   launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, B.b0, st));
+            LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0,
+                                                 S.beta.Cinv, S.beta.Sinv, B.b0, B.b1, st));
+            LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full, B.b1, B.b0, st));
+            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, B.b0, grid, st));
+        }
+    }
+    return CVL_OK;
+}
+
+int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *scal_maps,
+                           const cvl_c128 *const *grids, double *maps, void *ws, size_t ws_bytes,
+                           void *stream) {
+    g_err.clear();
+    Plan *P;
+    int rc = check_curvelet_call(ctx, p, batch, scal_maps, maps, grids, ws, ws_bytes, &P);
+    if (rc) return rc;
+    const int nJ = P->J - P->J0 + 1;
+    for (int i = 0; i < batch * nJ; ++i)
+        if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
+    ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
+    hipStream_t st = (hipStream_t)stream;
+    CurveletBufs B = carve_curvelet(P, ws, ws_bytes);
+    const int L = P->L, Lp = P->Lphi;
+    for (int bi = 0; bi < batch; ++bi) {
+        const double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        double *map = maps + (size_t)bi * L * (2 * L - 1);
+        LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
+        for (int s = 0; s < nJ; ++s) {
+            const ScaleRt &S = P->scales[s];
+            const ScaleGeom &g = S.g;
+            const cd *grid = (const cd *)grids[(size_t)bi * nJ + s];
+            LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, B.b0, st));
+            LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_half, B.b0, B.b1, st));
+            LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
+                                                 S.beta.Qs, B.b1, B.b0, st));
+            LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd(g, L, ctx->delta, B.b0, S.psi, B.b1,
+                                                        P->ngroups, st));
+            LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, B.b1, P->ngroups, B.facc, st));
+        }
+        if ((rc = sht_forward_run(ctx, SP, smap, B.fphi, Lp, B.s0, B.s1, st))) return rc;
+        LAUNCH(ST_MISC, launch_scale_flm(Lp, Lp, L, P->phifac, B.fphi, B.facc, 1, st));
+        if ((rc = sht_inverse_run(ctx, SL, B.facc, L, map, B.s0, B.s1, st))) return rc;
+    }
+    return CVL_OK;
+}
+
+int cvl_delta_block(cvl_ctx *ctx, int l, double *out) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (l < 0 || l >= ctx->Lmax) return fail(CVL_EINVAL, "l=%d outside [0, L_max=%d)", l, ctx->Lmax);
+    if (!out) return fail(CVL_EINVAL, "out is NULL");
+    if ((rc = set_device(ctx))) return rc;
+    HIP_TRY(hipMemcpy(out, ctx->delta + delta_off(l), sizeof(double) * (size_t)(l + 1) * (l + 1),
+                      hipMemcpyDeviceToHost));
+    return CVL_OK;
+}
+
+int cvl_profile_enable(cvl_ctx *ctx, int on) {
+    g_err.clear();
+    if (!ctx) return fail(CVL_EINVAL, "context is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->prof = on != 0;
+    for (int i = 0; i < ST_COUNT; ++i) {
+        ctx->stage_ms[i] = 0;
+        ctx->stage_n[i] = 0;
+    }
+    return CVL_OK;
+}
+
+int cvl_profile_read(cvl_ctx *ctx, int max, int *n, const char **names, int *launches,
+                     double *ms) {
+    g_err.clear();
+    if (!ctx || !n) return fail(CVL_EINVAL, "NULL argument");
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        rec.swap(ctx->rec);
+    }
+    for (auto &r : rec) {
+        hipEvent_t e0 = std::get<1>(r), e1 = std::get<2>(r);
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        ctx->stage_ms[std::get<0>(r)] += t;
+        ctx->stage_n[std::get<0>(r)] += 1;
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &r : rec) {
+            ctx->pool.push_back(std::get<1>(r));
+            ctx->pool.push_back(std::get<2>(r));
+        }
+    }
+    *n = ST_COUNT;
+    for (int i = 0; i < ST_COUNT && i < max; ++i) {
+        if (names) names[i] = kStageNames[i];
+        if (launches) launches[i] = ctx->stage_n[i];
+        if (ms) ms[i] = ctx->stage_ms[i];
+    }
+    return CVL_OK;
+}
+
+}  // extern "C"

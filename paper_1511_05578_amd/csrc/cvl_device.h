@@ -1,0 +1,115 @@
+// Device-side types and launch wrappers shared by the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cvl {
+
+struct __align__(16) cd {
+    double x, y;
+};
+
+__host__ __device__ __forceinline__ cd mk(double x, double y) { return cd{x, y}; }
+__host__ __device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+__host__ __device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
+__host__ __device__ __forceinline__ cd cmul(cd a, cd b) {
+    return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ __forceinline__ cd cconj(cd a) { return cd{a.x, -a.y}; }
+__host__ __device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.x * s, a.y * s}; }
+// multiply by i^q (q taken mod 4, may be negative)
+__host__ __device__ __forceinline__ cd ipow(cd a, int q) {
+    switch (q & 3) {
+        case 0: return a;
+        case 1: return cd{-a.y, a.x};
+        case 2: return cd{-a.x, -a.y};
+        default: return cd{a.y, -a.x};
+    }
+}
+
+// Offset of block l in the quarter Delta table: sum_{k<l} (k+1)^2.
+__host__ __device__ __forceinline__ int64_t delta_off(int l) {
+    return (int64_t)l * (l + 1) * (2 * l + 1) / 6;
+}
+
+// Device tables of one Bluestein DFT configuration (see host::Bluestein).
+struct BluesteinDev {
+    int Nd, P, Kin, j0, Kout, k0;
+    const cd *pre, *post, *vhat, *tw;
+};
+
+// Geometry of one curvelet scale (or one SHT / Wigner band-limit).
+struct ScaleGeom {
+    int L;     // band-limit L_j (alpha band-limit M = L_j too)
+    int Nm;    // 2L - 1
+    int h;     // (L-1)/2: even n = 2k with |k| <= h
+    int Ne;    // 2h + 1 even-n values
+    int Nep;   // Ne padded to a multiple of 32 (cube row length)
+    int llo, lhi;  // l range where the curvelet kernel is non-zero (inclusive)
+};
+
+// ---- launch wrappers (defined in the .hip files) ----
+hipError_t launch_delta_toprows(double *tab, int Lmax, hipStream_t st);
+hipError_t launch_delta_fill(double *tab, int Lmax, hipStream_t st);
+
+// Bluestein stages.  Each returns hipSuccess or the launch error.
+hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
+                            cd *W2, hipStream_t st);
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                            cd *grid, hipStream_t st);
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                            cd *V1, hipStream_t st);
+hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
+                            cd *V2, hipStream_t st);
+hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,
+                              hipStream_t st);
+hipError_t launch_sht_fwd_phi(int L, const BluesteinDev &B, const double *map, cd *F1,
+                              hipStream_t st);
+// general complex Wigner transforms (all m, all n)
+hipError_t launch_gen_inv_alpha(int L, int N, const BluesteinDev &B, const cd *W1,
+                                cd *W2, hipStream_t st);
+hipError_t launch_gen_inv_gamma(int L, int N, const BluesteinDev &B, const cd *W2,
+                                cd *grid, hipStream_t st);
+hipError_t launch_gen_fwd_gamma(int L, int N, const BluesteinDev &B, const cd *grid,
+                                cd *V1, hipStream_t st);
+hipError_t launch_gen_fwd_alpha(int L, int N, const BluesteinDev &B, const cd *V1,
+                                cd *V2, hipStream_t st);
+
+// Parity-folded beta stage as a real-matrix x complex-data GEMM:
+// out[r][c] = sum_k A^{par(c)}[r][k] in[k][c] (times i for odd parity), rows
+// r < M, k < K, complex columns c < ncols.  Column parity: (c / Nep) & 1 when
+// mode == 0 (curvelet layout, parity of m), ((c / Nep) + (c % Nep) + par0) & 1
+// when mode == 1 (general layout [m][n], parity of m + n).
+hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0,
+                            const double *Aeven, const double *Aodd, const cd *in,
+                            cd *out, hipStream_t st);
+
+// Curvelet contractions.
+hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
+                               const cd *fpad, const double *psi, cd *X, hipStream_t st);
+hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
+                               const cd *Z, const double *psi, cd *part, int ngroups,
+                               hipStream_t st);
+hipError_t launch_reduce_fwd(const ScaleGeom &g, int Lf, const cd *part, int ngroups,
+                             cd *facc, hipStream_t st);
+
+// General Wigner contractions (dense F^l_mn).
+hipError_t launch_gen_contract_inv(int L, int N, const double *delta, const cd *F,
+                                   cd *X, hipStream_t st);
+hipError_t launch_gen_contract_fwd(int L, int N, const double *delta, const cd *Z,
+                                   cd *F, hipStream_t st);
+
+// SHT helpers.
+hipError_t launch_sht_inv_delta(int L, int Lf, const double *delta, const cd *fpad,
+                                cd *F, hipStream_t st);
+hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int mode_fwd, const double *Aeven,
+                            const double *Aodd, const cd *in, cd *out, hipStream_t st);
+hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z, cd *fpad,
+                                hipStream_t st);
+hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, hipStream_t st);
+hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st);
+hipError_t launch_scale_flm(int Lphi, int Lsrc, int Ldst, const double *fac, const cd *src,
+                            cd *dst, int accumulate, hipStream_t st);
+hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
+
+}  // namespace cvl

@@ -1,0 +1,652 @@
+// Dense kernels of the curvelet transform on gfx950, all FP64:
+//  * Delta = d(pi/2) quarter table by the Trapani-Navaza recursion;
+//  * the parity-folded beta stage as a real-matrix x complex-data GEMM;
+//  * the l-contraction of the analysis (harmonic product f_lm Psi_ln folded
+//    into the Fourier-cube sum over l) and the Delta-projection + Psi
+//    contraction of the synthesis;
+//  * dense Wigner contractions for general F^l_mn;
+//  * small SHT helpers.
+#include "cvl_device.h"
+
+namespace cvl {
+
+// ---------------------------------------------------------------------------
+// Delta table: tab[off(l) + r*(l+1) + c] = Delta^l_{r,c}, 0 <= r, c <= l.
+// Top rows (r = l) from the previous l:
+//   Delta^l_{l,0} = -sqrt((2l-1)/(2l)) Delta^{l-1}_{l-1,0}
+//   Delta^l_{l,c} = sqrt(l(2l-1)/(2(l+c)(l+c-1))) Delta^{l-1}_{l-1,c-1}
+// then every column downwards (r = l-1 .. 0):
+//   Delta^l_{r,c} = 2c/sqrt((l-r)(l+r+1)) Delta^l_{r+1,c}
+//                   - sqrt((l-r-1)(l+r+2)/((l-r)(l+r+1))) Delta^l_{r+2,c}.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_delta_toprows(double *tab, int Lmax) {
+    const int tid = threadIdx.x;
+    if (tid == 0) tab[0] = 1.0;
+    __syncthreads();
+    for (int l = 1; l < Lmax; ++l) {
+        const double *prev = tab + delta_off(l - 1) + (int64_t)(l - 1) * l;
+        double *row = tab + delta_off(l) + (int64_t)l * (l + 1);
+        for (int c = tid; c <= l; c += blockDim.x) {
+            double v;
+            if (c == 0)
+                v = -sqrt((2.0 * l - 1.0) / (2.0 * l)) * prev[0];
+            else
+                v = sqrt((double)l * (2.0 * l - 1.0) /
+                         (2.0 * (double)(l + c) * (double)(l + c - 1))) * prev[c - 1];
+            row[c] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_delta_fill(double *tab, int Lmax) {
+    const int l = blockIdx.x;
+    if (l == 0) return;
+    double *blk = tab + delta_off(l);
+    const int w = l + 1;
+    for (int c = threadIdx.x; c <= l; c += blockDim.x) {
+        double d2 = 0.0;                      // Delta_{r+2, c}
+        double d1 = blk[(int64_t)l * w + c];  // Delta_{r+1, c}
+        for (int r = l - 1; r >= 0; --r) {
+            const double den = (double)(l - r) * (double)(l + r + 1);
+            const double a = 2.0 * c / sqrt(den);
+            const double b = sqrt((double)(l - r - 1) * (double)(l + r + 2) / den);
+            const double d0 = a * d1 - b * d2;
+            blk[(int64_t)r * w + c] = d0;
+            d2 = d1;
+            d1 = d0;
+        }
+    }
+}
+
+hipError_t launch_delta_toprows(double *tab, int Lmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_delta_toprows, dim3(1), dim3(1024), 0, st, tab, Lmax);
+    return hipGetLastError();
+}
+hipError_t launch_delta_fill(double *tab, int Lmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_delta_fill, dim3(Lmax), dim3(256), 0, st, tab, Lmax);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Parity-folded beta stage: out[r][c] = (i^par) * sum_k A^{par(c)}[r][k] in[k][c].
+// Real GEMM over interleaved (re, im) columns; tile 64 rows x 32 complex
+// columns x 16 k; each thread owns 4 rows x 2 complex columns.
+// UNIFORM: all columns of a tile share one parity (curvelet layout, Nep % 32 == 0).
+// ---------------------------------------------------------------------------
+template <bool UNIFORM>
+__global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int Nep, int mode,
+                                                   int par0, const double *__restrict__ Ae,
+                                                   const double *__restrict__ Ao,
+                                                   const double *__restrict__ in,
+                                                   double *__restrict__ out) {
+    __shared__ double As[UNIFORM ? 1 : 2][16][64];
+    __shared__ double Bs[16][64];
+    const int tid = threadIdx.x;
+    const int tr = tid / 16, tc = tid % 16;
+    const int r0 = blockIdx.y * 64;
+    const int c0 = blockIdx.x * 32;  // complex column base
+    const size_t ld = 2 * (size_t)ncols;
+    auto parity = [&](int c) -> int {
+        if (mode == 0) return (c / Nep) & 1;
+        return ((c / Nep) + (c % Nep) + par0) & 1;
+    };
+    const int tpar = parity(c0 < ncols ? c0 : 0);
+    const double *Au = tpar ? Ao : Ae;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[i][e] = 0.0;
+    double acc2[UNIFORM ? 1 : 4][UNIFORM ? 1 : 4];
+    if constexpr (!UNIFORM) {
+#pragma unroll
+        for (int i = 0; i < (UNIFORM ? 1 : 4); ++i)
+#pragma unroll
+            for (int e = 0; e < (UNIFORM ? 1 : 4); ++e) acc2[i][e] = 0.0;
+    }
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int i = tid; i < 1024; i += 256) {
+            const int rr = i / 16, kk = i % 16;
+            const int r = r0 + rr, k = k0 + kk;
+            const bool ok = (r < M && k < K);
+            if constexpr (UNIFORM) {
+                As[0][kk][rr] = ok ? Au[(size_t)r * K + k] : 0.0;
+            } else {
+                As[0][kk][rr] = ok ? Ae[(size_t)r * K + k] : 0.0;
+                As[UNIFORM ? 0 : 1][kk][rr] = ok ? Ao[(size_t)r * K + k] : 0.0;
+            }
+        }
+        for (int i = tid; i < 1024; i += 256) {
+            const int kk = i / 64, cc = i % 64;
+            const int k = k0 + kk;
+            const size_t col = 2 * (size_t)c0 + cc;
+            Bs[kk][cc] = (k < K && col < ld) ? in[(size_t)k * ld + col] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double b[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) b[e] = Bs[kk][tc * 4 + e];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double a = As[0][kk][tr + 16 * i];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[i][e] += a * b[e];
+                if constexpr (!UNIFORM) {
+                    const double ao = As[UNIFORM ? 0 : 1][kk][tr + 16 * i];
+#pragma unroll
+                    for (int e = 0; e < (UNIFORM ? 1 : 4); ++e) acc2[i][e] += ao * b[e];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + tr + 16 * i;
+        if (r >= M) continue;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = c0 + tc * 2 + q;
+            if (c >= ncols) continue;
+            int par;
+            double re, im;
+            if constexpr (UNIFORM) {
+                par = tpar;
+                re = acc[i][2 * q];
+                im = acc[i][2 * q + 1];
+            } else {
+                par = parity(c);
+                re = par ? acc2[i][2 * q] : acc[i][2 * q];
+                im = par ? acc2[i][2 * q + 1] : acc[i][2 * q + 1];
+            }
+            double *o = out + (size_t)r * ld + 2 * (size_t)c;
+            if (par) {
+                o[0] = -im;
+                o[1] = re;
+            } else {
+                o[0] = re;
+                o[1] = im;
+            }
+        }
+    }
+}
+
+hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0,
+                            const double *Aeven, const double *Aodd, const cd *in, cd *out,
+                            hipStream_t st) {
+    dim3 grid((ncols + 31) / 32, (M + 63) / 64);
+    if (mode == 0 && Nep % 32 == 0)
+        hipLaunchKernelGGL(k_beta_gemm<true>, grid, dim3(256), 0, st, M, K, ncols, Nep, mode,
+                           par0, Aeven, Aodd, (const double *)in, (double *)out);
+    else
+        hipLaunchKernelGGL(k_beta_gemm<false>, grid, dim3(256), 0, st, M, K, ncols, Nep, mode,
+                           par0, Aeven, Aodd, (const double *)in, (double *)out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Analysis contraction of one curvelet scale (Fourier cube, parity-folded):
+//   P_e/o[m][k] = sum_{l even/odd} (Delta^l_{m'm} f_lm) (Delta^l_{m',2k} Psi_{l,2k})
+//   X[m'][m][h+k] = (-1)^k i^{-m} (P_e + P_o)
+//   X[m'][m][h-k] = (-1)^k i^{-m} (-1)^{m'} (P_e - P_o)
+// over l in [max(llo, m', m, 2k), lhi].  Tile 64 m x 32 k per work-group,
+// one m' per grid row; each thread owns 4 m x 2 k (x 2 parities).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_contract_inv(ScaleGeom g, int Lf,
+                                                      const double *__restrict__ delta,
+                                                      const cd *__restrict__ fpad,
+                                                      const double *__restrict__ psi,
+                                                      cd *__restrict__ X) {
+    __shared__ cd Ash[8][64];
+    __shared__ double Bsh[8][32];
+    const int L = g.L, h = g.h;
+    const int mp = blockIdx.y;
+    const int nkt = (h + 1 + 31) / 32;
+    const int m0 = (blockIdx.x / nkt) * 64, k0 = (blockIdx.x % nkt) * 32;
+    const int tid = threadIdx.x;
+    const int tm = tid % 16, tk = tid / 16;
+    cd pe[4][2], po[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) pe[i][q] = po[i][q] = cd{0.0, 0.0};
+    int lstart = g.llo;
+    if (mp > lstart) lstart = mp;
+    if (m0 > lstart) lstart = m0;
+    if (2 * k0 > lstart) lstart = 2 * k0;
+    const int lend = g.lhi;
+    for (int lb = lstart & ~1; lb <= lend; lb += 8) {
+        for (int idx = tid; idx < 512; idx += 256) {
+            const int lc = idx / 64, mm = idx % 64;
+            const int l = lb + lc, m = m0 + mm;
+            cd v = cd{0.0, 0.0};
+            if (l >= lstart && l <= lend && m <= l && m < L)
+                v = cscale(fpad[(size_t)l * Lf + m],
+                           delta[delta_off(l) + (int64_t)mp * (l + 1) + m]);
+            Ash[lc][mm] = v;
+        }
+        {
+            const int lc = tid / 32, kk = tid % 32;
+            const int l = lb + lc, k = k0 + kk;
+            double v = 0.0;
+            if (l >= lstart && l <= lend && k <= h && 2 * k <= l)
+                v = delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] * psi[(size_t)l * (h + 1) + k];
+            Bsh[lc][kk] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int lc = 0; lc < 8; lc += 2) {
+            double b0[2], b1[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                b0[q] = Bsh[lc][tk + 16 * q];
+                b1[q] = Bsh[lc + 1][tk + 16 * q];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const cd a0 = Ash[lc][tm + 16 * i];
+                const cd a1 = Ash[lc + 1][tm + 16 * i];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    pe[i][q].x += a0.x * b0[q];
+                    pe[i][q].y += a0.y * b0[q];
+                    po[i][q].x += a1.x * b1[q];
+                    po[i][q].y += a1.y * b1[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int Nep = g.Nep;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + tm + 16 * i;
+        if (m >= L) continue;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int k = k0 + tk + 16 * q;
+            if (k > h) continue;
+            const double sk = (k & 1) ? -1.0 : 1.0;
+            cd *row = X + ((size_t)mp * L + m) * Nep;
+            const cd sp = cadd(pe[i][q], po[i][q]);
+            row[h + k] = ipow(cscale(sp, sk), -m);
+            if (k > 0) {
+                const double sm = (mp & 1) ? -sk : sk;
+                const cd sd = csub(pe[i][q], po[i][q]);
+                row[h - k] = ipow(cscale(sd, sm), -m);
+            }
+        }
+    }
+}
+
+hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta, const cd *fpad,
+                               const double *psi, cd *X, hipStream_t st) {
+    const int nkt = (g.h + 1 + 31) / 32;
+    dim3 grid(((g.L + 63) / 64) * nkt, g.L);
+    hipLaunchKernelGGL(k_contract_inv, grid, dim3(256), 0, st, g, Lf, delta, fpad, psi, X);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis contraction of one curvelet scale:
+//   f_lm = i^m sum_{m'} Delta^l_{m'm} sum_k Z^{par(l)}[m'][m][k] B'[k][l],
+//   B'[k][l] = (-1)^k Delta^l_{m',2k} Psi_{l,2k},
+//   Z^{+/-}[m'][m][k] = Z[m'][m][h+k] +/- (-1)^{m'} Z[m'][m][h-k]  (k > 0),
+//   Z^{+/-}[m'][m][0] = Z[m'][m][h].
+// Work-group: 64 m x 32 l tile, m' restricted to one of `ngroups` groups; the
+// partial sums part[grp][l][m] are reduced in a fixed order afterwards.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_contract_fwd(ScaleGeom g, int Lf,
+                                                      const double *__restrict__ delta,
+                                                      const cd *__restrict__ Z,
+                                                      const double *__restrict__ psi,
+                                                      cd *__restrict__ part, int ngroups) {
+    __shared__ cd Zp[16][64];
+    __shared__ cd Zm[16][64];
+    __shared__ double Bsh[16][32];
+    const int L = g.L, h = g.h, Nep = g.Nep;
+    const int nl = g.lhi - g.llo + 1;
+    const int nlt = (nl + 31) / 32;
+    const int m0 = (blockIdx.x / nlt) * 64;
+    const int l0 = g.llo + (blockIdx.x % nlt) * 32;
+    const int grp = blockIdx.y;
+    const int gsz = (L + ngroups - 1) / ngroups;
+    const int mpa = grp * gsz;
+    int mpb = mpa + gsz;
+    if (mpb > L) mpb = L;
+    int ltop = l0 + 31;
+    if (ltop > g.lhi) ltop = g.lhi;
+    if (mpb > ltop + 1) mpb = ltop + 1;
+    const int tid = threadIdx.x;
+    const int tm = tid % 16, tl = tid / 16;
+    const int lpar = (l0 + tl) & 1;
+    cd acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[i][q] = cd{0.0, 0.0};
+    int kmax = ltop / 2;
+    if (kmax > h) kmax = h;
+    for (int mp = mpa; mp < mpb; ++mp) {
+        const double smp = (mp & 1) ? -1.0 : 1.0;
+        cd tmp[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) tmp[i][q] = cd{0.0, 0.0};
+        for (int kb = 0; kb <= kmax; kb += 16) {
+            for (int idx = tid; idx < 1024; idx += 256) {
+                const int kk = idx / 64, mm = idx % 64;
+                const int k = kb + kk, m = m0 + mm;
+                cd vp = cd{0.0, 0.0}, vm = cd{0.0, 0.0};
+                if (k <= kmax && m < L) {
+                    const cd *row = Z + ((size_t)mp * L + m) * Nep;
+                    const cd zp = row[h + k];
+                    if (k == 0) {
+                        vp = vm = zp;
+                    } else {
+                        const cd zn = cscale(row[h - k], smp);
+                        vp = cadd(zp, zn);
+                        vm = csub(zp, zn);
+                    }
+                }
+                Zp[kk][mm] = vp;
+                Zm[kk][mm] = vm;
+            }
+            for (int idx = tid; idx < 512; idx += 256) {
+                const int kk = idx / 32, ll = idx % 32;
+                const int k = kb + kk, l = l0 + ll;
+                double v = 0.0;
+                if (k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l) {
+                    v = delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] *
+                        psi[(size_t)l * (h + 1) + k];
+                    if (k & 1) v = -v;
+                }
+                Bsh[kk][ll] = v;
+            }
+            __syncthreads();
+            const cd(*Zs)[64] = lpar ? Zm : Zp;
+#pragma unroll 4
+            for (int kk = 0; kk < 16; ++kk) {
+                const double b0 = Bsh[kk][tl], b1 = Bsh[kk][tl + 16];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const cd z = Zs[kk][tm + 16 * i];
+                    tmp[i][0].x += z.x * b0;
+                    tmp[i][0].y += z.y * b0;
+                    tmp[i][1].x += z.x * b1;
+                    tmp[i][1].y += z.y * b1;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int l = l0 + tl + 16 * q;
+            if (l > g.lhi || mp > l) continue;
+            const double *drow = delta + delta_off(l) + (int64_t)mp * (l + 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + tm + 16 * i;
+                if (m > l) continue;
+                const double d = drow[m];
+                acc[i][q].x += d * tmp[i][q].x;
+                acc[i][q].y += d * tmp[i][q].y;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int l = l0 + tl + 16 * q;
+        if (l > g.lhi) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + tm + 16 * i;
+            if (m >= L) continue;
+            part[((size_t)grp * L + l) * L + m] = acc[i][q];
+        }
+    }
+}
+
+__global__ void k_reduce_fwd(ScaleGeom g, int Lf, const cd *__restrict__ part, int ngroups,
+                             cd *__restrict__ facc) {
+    const int L = g.L;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nl = g.lhi - g.llo + 1;
+    if (idx >= nl * L) return;
+    const int l = g.llo + idx / L, m = idx % L;
+    if (m > l) return;
+    cd s = cd{0.0, 0.0};
+    for (int grp = 0; grp < ngroups; ++grp) s = cadd(s, part[((size_t)grp * L + l) * L + m]);
+    cd *o = facc + (size_t)l * Lf + m;
+    *o = cadd(*o, ipow(s, m));
+}
+
+hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta, const cd *Z,
+                               const double *psi, cd *part, int ngroups, hipStream_t st) {
+    const int nl = g.lhi - g.llo + 1;
+    if (nl <= 0) return hipSuccess;
+    dim3 grid(((g.L + 63) / 64) * ((nl + 31) / 32), ngroups);
+    hipLaunchKernelGGL(k_contract_fwd, grid, dim3(256), 0, st, g, Lf, delta, Z, psi, part,
+                       ngroups);
+    return hipGetLastError();
+}
+hipError_t launch_reduce_fwd(const ScaleGeom &g, int Lf, const cd *part, int ngroups, cd *facc,
+                             hipStream_t st) {
+    const int nl = g.lhi - g.llo + 1;
+    if (nl <= 0) return hipSuccess;
+    const int n = nl * g.L;
+    hipLaunchKernelGGL(k_reduce_fwd, dim3((n + 255) / 256), dim3(256), 0, st, g, Lf, part,
+                       ngroups, facc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// General Wigner contractions (dense F^l_mn, any m, n).  Delta^l_{m',-k} =
+// (-1)^(l+m') Delta^l_{m',k}.  Layouts: F[l][m+L-1][n+N-1] (row 2N-1),
+// X / Z[m'][m+L-1][n+N-1] (row Nnp).
+// ---------------------------------------------------------------------------
+__global__ void k_gen_contract_inv(int L, int N, int Nnp, const double *__restrict__ delta,
+                                   const cd *__restrict__ F, cd *__restrict__ X) {
+    const int Nm = 2 * L - 1, Nn = 2 * N - 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mp = blockIdx.y;
+    if (idx >= Nm * Nnp) return;
+    const int mi = idx / Nnp, ni = idx % Nnp;
+    cd *o = X + ((size_t)mp * Nm + mi) * Nnp + ni;
+    if (ni >= Nn) {
+        *o = cd{0.0, 0.0};
+        return;
+    }
+    const int m = mi - (L - 1), n = ni - (N - 1);
+    const int am = m < 0 ? -m : m, an = n < 0 ? -n : n;
+    int l0 = am > an ? am : an;
+    if (mp > l0) l0 = mp;
+    cd s = cd{0.0, 0.0};
+    for (int l = l0; l < L; ++l) {
+        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        double w = row[am] * row[an] * (2.0 * l + 1.0) * (1.0 / (8.0 * M_PI * M_PI));
+        const int flip = ((m < 0) + (n < 0)) * ((l + mp) & 1);
+        if (flip & 1) w = -w;
+        const cd f = F[((size_t)l * Nm + mi) * Nn + ni];
+        s.x += w * f.x;
+        s.y += w * f.y;
+    }
+    *o = ipow(s, n - m);
+}
+
+__global__ void k_gen_contract_fwd(int L, int N, int Nnp, const double *__restrict__ delta,
+                                   const cd *__restrict__ Z, cd *__restrict__ F) {
+    const int Nm = 2 * L - 1, Nn = 2 * N - 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (idx >= Nm * Nn) return;
+    const int mi = idx / Nn, ni = idx % Nn;
+    const int m = mi - (L - 1), n = ni - (N - 1);
+    const int am = m < 0 ? -m : m, an = n < 0 ? -n : n;
+    cd *o = F + ((size_t)l * Nm + mi) * Nn + ni;
+    if (am > l || an > l) {
+        *o = cd{0.0, 0.0};
+        return;
+    }
+    cd s = cd{0.0, 0.0};
+    for (int mp = 0; mp <= l; ++mp) {
+        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        double w = row[am] * row[an];
+        const int flip = ((m < 0) + (n < 0)) * ((l + mp) & 1);
+        if (flip & 1) w = -w;
+        const cd z = Z[((size_t)mp * Nm + mi) * Nnp + ni];
+        s.x += w * z.x;
+        s.y += w * z.y;
+    }
+    *o = ipow(s, m - n);
+}
+
+hipError_t launch_gen_contract_inv(int L, int N, const double *delta, const cd *F, cd *X,
+                                   hipStream_t st) {
+    const int Nnp = ((2 * N - 1) + 31) / 32 * 32;
+    const int n = (2 * L - 1) * Nnp;
+    hipLaunchKernelGGL(k_gen_contract_inv, dim3((n + 255) / 256, L), dim3(256), 0, st, L, N,
+                       Nnp, delta, F, X);
+    return hipGetLastError();
+}
+hipError_t launch_gen_contract_fwd(int L, int N, const double *delta, const cd *Z, cd *F,
+                                   hipStream_t st) {
+    const int Nnp = ((2 * N - 1) + 31) / 32 * 32;
+    const int n = (2 * L - 1) * (2 * N - 1);
+    hipLaunchKernelGGL(k_gen_contract_fwd, dim3((n + 255) / 256, L), dim3(256), 0, st, L, N,
+                       Nnp, delta, Z, F);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// SHT (spin 0) helpers.  c_l = sqrt((2l+1)/(4 pi)).
+//   inverse: F[m'][m] = i^{-m} sum_{l>=max(m,m')} c_l Delta^l_{m'm} Delta^l_{m'0} f_lm
+//   forward: f_lm = i^m c_l sum_{m'<=l} Delta^l_{m'm} Delta^l_{m'0} Z[m'][m]
+// (Delta^l_{m'0} = 0 when l + m' is odd.)
+// ---------------------------------------------------------------------------
+__global__ void k_sht_inv_delta(int L, int Lf, const double *__restrict__ delta,
+                                const cd *__restrict__ fpad, cd *__restrict__ F) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    const int mp = idx / L, m = idx % L;
+    int l0 = m > mp ? m : mp;
+    if ((l0 + mp) & 1) ++l0;
+    cd s = cd{0.0, 0.0};
+    for (int l = l0; l < L; l += 2) {
+        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        const double w = sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * row[m] * row[0];
+        const cd f = fpad[(size_t)l * Lf + m];
+        s.x += w * f.x;
+        s.y += w * f.y;
+    }
+    F[(size_t)mp * L + m] = ipow(s, -m);
+}
+
+__global__ void k_sht_fwd_delta(int L, int Lf, const double *__restrict__ delta,
+                                const cd *__restrict__ Z, cd *__restrict__ fpad) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    const int l = idx / L, m = idx % L;
+    cd *o = fpad + (size_t)l * Lf + m;
+    if (m > l) {
+        *o = cd{0.0, 0.0};
+        return;
+    }
+    cd s = cd{0.0, 0.0};
+    for (int mp = (l & 1); mp <= l; mp += 2) {
+        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        const double w = row[m] * row[0];
+        const cd z = Z[(size_t)mp * L + m];
+        s.x += w * z.x;
+        s.y += w * z.y;
+    }
+    *o = ipow(cscale(s, sqrt((2.0 * l + 1.0) / (4.0 * M_PI))), m);
+}
+
+hipError_t launch_sht_inv_delta(int L, int Lf, const double *delta, const cd *fpad, cd *F,
+                                hipStream_t st) {
+    const int n = L * L;
+    hipLaunchKernelGGL(k_sht_inv_delta, dim3((n + 255) / 256), dim3(256), 0, st, L, Lf, delta,
+                       fpad, F);
+    return hipGetLastError();
+}
+hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z, cd *fpad,
+                                hipStream_t st) {
+    const int n = L * L;
+    hipLaunchKernelGGL(k_sht_fwd_delta, dim3((n + 255) / 256), dim3(256), 0, st, L, Lf, delta,
+                       Z, fpad);
+    return hipGetLastError();
+}
+hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int, const double *Aeven,
+                            const double *Aodd, const cd *in, cd *out, hipStream_t st) {
+    (void)L;
+    // columns are m = 0..L-1 with parity m & 1: general-mode GEMM with Nep = 1.
+    return launch_beta_gemm(Mrows, Kdim, L, 1, 1, 0, Aeven, Aodd, in, out, st);
+}
+
+// f (flat l^2+l+m) <-> fpad [l][m], m >= 0.
+__global__ void k_flm_unpack(int L, const cd *__restrict__ fpad, cd *__restrict__ flm) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    int l = (int)sqrt((double)idx);
+    while (l * l > idx) --l;
+    while ((l + 1) * (l + 1) <= idx) ++l;
+    const int m = idx - l * l - l;
+    const cd v = fpad[(size_t)l * L + (m < 0 ? -m : m)];
+    if (m >= 0)
+        flm[idx] = v;
+    else
+        flm[idx] = cscale(cconj(v), (m & 1) ? -1.0 : 1.0);
+}
+__global__ void k_flm_pack(int L, const cd *__restrict__ flm, cd *__restrict__ fpad) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    const int l = idx / L, m = idx % L;
+    fpad[idx] = (m <= l) ? flm[(size_t)l * l + l + m] : cd{0.0, 0.0};
+}
+hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, hipStream_t st) {
+    hipLaunchKernelGGL(k_flm_unpack, dim3((L * L + 255) / 256), dim3(256), 0, st, L, fpad, flm);
+    return hipGetLastError();
+}
+hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st) {
+    hipLaunchKernelGGL(k_flm_pack, dim3((L * L + 255) / 256), dim3(256), 0, st, L, flm, fpad);
+    return hipGetLastError();
+}
+
+// dst[l][m] (=|+=) fac[l] * src[l][m] for l < Lphi, m <= l.
+__global__ void k_scale_flm(int Lphi, int Lsrc, int Ldst, const double *__restrict__ fac,
+                            const cd *__restrict__ src, cd *__restrict__ dst, int accumulate) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Lphi * Lphi) return;
+    const int l = idx / Lphi, m = idx % Lphi;
+    cd v = (m <= l) ? cscale(src[(size_t)l * Lsrc + m], fac[l]) : cd{0.0, 0.0};
+    cd *o = dst + (size_t)l * Ldst + m;
+    if (accumulate) {
+        if (m <= l) *o = cadd(*o, v);
+    } else {
+        *o = v;
+    }
+}
+hipError_t launch_scale_flm(int Lphi, int Lsrc, int Ldst, const double *fac, const cd *src,
+                            cd *dst, int accumulate, hipStream_t st) {
+    const int n = Lphi * Lphi;
+    hipLaunchKernelGGL(k_scale_flm, dim3((n + 255) / 256), dim3(256), 0, st, Lphi, Lsrc, Ldst,
+                       fac, src, dst, accumulate);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(cd *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = cd{0.0, 0.0};
+}
+hipError_t launch_zero(cd *p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace cvl
