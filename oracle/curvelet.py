@@ -86,13 +86,18 @@ def analysis(plan, flm):
     return scal, grids
 
 
-def synthesis_scale(plan, grid, j):
-    """f^(j)_lm = sum_n (W^(j))^l_mn Psi^(j)_ln as a flat length-L^2 array."""
+def synthesis_scale(plan, grid, j, nodes_subset=None):
+    """f^(j)_lm = sum_n (W^(j))^l_mn Psi^(j)_ln as a flat length-L^2 array.
+
+    ``nodes_subset`` restricts the Gauss-Legendre sum to those node indices
+    (a partial sum, used only to time a bounded sample)."""
     Lj = plan.Lj[j]
     P = plan.psi_j(j, Lj)
     nodes, weights, Xq = so3.gl_rows(grid, Lj, Lj)
     acc = np.zeros((Lj, 2 * Lj - 1), dtype=np.complex128)
     for q, bq in enumerate(nodes):
+        if nodes_subset is not None and q not in nodes_subset:
+            continue
         for l, D in wigner.d_iter(Lj, bq, Lj, Lj):
             if not np.any(P[l]):
                 continue
