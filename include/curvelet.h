@@ -142,8 +142,11 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
                           void *stream);
 
 /* Curvelet synthesis (Sec. II-D-2, exact reconstruction): the inverse of
- * cvl_curvelet_analysis on its range.  Reads the full complex grids.  Writes
- * `batch` real maps.  Same layouts as cvl_curvelet_analysis. */
+ * cvl_curvelet_analysis on its range.  Synthesis is linear, and a grid's
+ * imaginary part only feeds the imaginary part of the synthesised map, so the
+ * real map returned is the synthesis of the grids' real parts (the imaginary
+ * parts are not used).  Writes `batch` real maps.  Same layouts as
+ * cvl_curvelet_analysis. */
 int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
                            const double *scal_maps, const cvl_c128 *const *grids,
                            double *maps, void *ws, size_t ws_bytes, void *stream);

@@ -9,10 +9,12 @@
 // folded in), and a chirp post-multiply.  The inverse FFT is the forward one
 // between two conjugations.
 //
-// A work-group of 256 threads transforms LINES lines; each line lives in its
-// own P-element LDS slice and is worked on by 256/LINES threads.  The stage
-// IO policies below gather / scatter each stage's lines with the symmetries
-// the stage uses (reality of the map, evenness of n, parity in beta).
+// Two engines: for P <= 128 a work-group of 256 threads transforms LINES
+// lines with radix-4 stages in LDS; for P >= 256 a register-resident radix-16
+// engine (below).  The stage IO policies gather / scatter each stage's lines
+// with the symmetries the stage uses (reality of the map, evenness of n) and
+// say whether a line is contiguous in memory (DIRECT) or interleaved with its
+// neighbours (STAGED through LDS for coalescing).
 #include "cvl_device.h"
 
 namespace cvl {
@@ -131,10 +133,253 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinD
     }
 }
 
-template <bool IN_IL, bool OUT_IL, class IO>
-static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B,
-                                hipStream_t st) {
+// ---------------------------------------------------------------------------
+// Register-resident Bluestein engine for P >= 256.
+//
+// A line of P points is held by T = P/16 threads, 16 complex values each;
+// after every FFT thread t holds elements t + T*s (s = 0..15).  The FFT is a
+// Stockham transform with two radix-16 passes (Ns = 1, 16) and, for P > 256,
+// a last radix-(P/256) pass (Ns = 256).  Passes exchange data through a
+// padded LDS line (index e + e/16).  Because the forward FFT ends with the
+// layout the next FFT's first pass reads, the chirp-spectrum multiply and the
+// second FFT need no exchange in between.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cd mul_mi(cd a) { return cd{a.y, -a.x}; }  // -i * a
+
+__device__ __forceinline__ void bfly4(cd &x0, cd &x1, cd &x2, cd &x3) {
+    const cd a0 = cadd(x0, x2), a1 = csub(x0, x2);
+    const cd b0 = cadd(x1, x3), b1 = mul_mi(csub(x1, x3));
+    x0 = cadd(a0, b0);
+    x2 = csub(a0, b0);
+    x1 = cadd(a1, b1);
+    x3 = csub(a1, b1);
+}
+__device__ __forceinline__ void bfly2(cd &x0, cd &x1) {
+    const cd a = cadd(x0, x1);
+    x1 = csub(x0, x1);
+    x0 = a;
+}
+
+// e^{-2 pi i e / 16} for the exponents a 4x4 split of the 16-point DFT needs.
+#define CVL_C1 0.92387953251128675613
+#define CVL_S1 0.38268343236508977173
+#define CVL_R2 0.70710678118654752440
+
+// 16-point forward DFT, natural order in and out (4 x 4 split).
+__device__ __forceinline__ void dft16(cd v[16]) {
+#pragma unroll
+    for (int r0 = 0; r0 < 4; ++r0) bfly4(v[r0], v[r0 + 4], v[r0 + 8], v[r0 + 12]);
+    v[5] = cmul(v[5], cd{CVL_C1, -CVL_S1});
+    v[9] = cmul(v[9], cd{CVL_R2, -CVL_R2});
+    v[13] = cmul(v[13], cd{CVL_S1, -CVL_C1});
+    v[6] = cmul(v[6], cd{CVL_R2, -CVL_R2});
+    v[10] = mul_mi(v[10]);
+    v[14] = cmul(v[14], cd{-CVL_R2, -CVL_R2});
+    v[7] = cmul(v[7], cd{CVL_S1, -CVL_C1});
+    v[11] = cmul(v[11], cd{-CVL_R2, -CVL_R2});
+    v[15] = cmul(v[15], cd{-CVL_C1, CVL_S1});
+#pragma unroll
+    for (int k0 = 0; k0 < 4; ++k0) bfly4(v[4 * k0], v[4 * k0 + 1], v[4 * k0 + 2], v[4 * k0 + 3]);
+    cd t[16];
+#pragma unroll
+    for (int k0 = 0; k0 < 4; ++k0)
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) t[k0 + 4 * k1] = v[4 * k0 + k1];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = t[k];
+}
+
+// 8-point forward DFT (4 x 2 split), natural order.
+__device__ __forceinline__ void dft8(cd *v) {
+    bfly4(v[0], v[2], v[4], v[6]);
+    bfly4(v[1], v[3], v[5], v[7]);
+    v[3] = cmul(v[3], cd{CVL_R2, -CVL_R2});
+    v[5] = mul_mi(v[5]);
+    v[7] = cmul(v[7], cd{-CVL_R2, -CVL_R2});
+#pragma unroll
+    for (int k0 = 0; k0 < 4; ++k0) bfly2(v[2 * k0], v[2 * k0 + 1]);
+    cd t[8];
+#pragma unroll
+    for (int k0 = 0; k0 < 4; ++k0) {
+        t[k0] = v[2 * k0];
+        t[k0 + 4] = v[2 * k0 + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = t[k];
+}
+
+template <int R>
+__device__ __forceinline__ void dft_small(cd *v) {
+    if constexpr (R == 2) {
+        bfly2(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        bfly4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        dft8(v);
+    } else {
+        dft16(v);
+    }
+}
+
+__device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
+
+template <int P>
+struct R16 {
+    static constexpr int T = P / 16;                 // threads per line
+    static constexpr int WG = T < 128 ? 128 : T;     // threads per work-group
+    static constexpr int LINES = WG / T;             // lines per work-group
+    static constexpr int RC = P / 256;               // radix of the last pass (1: none)
+    static constexpr int LW = P + P / 16;            // padded LDS line length
+};
+
+// Forward FFT of one line; v[s] = element tid + T*s on entry and on exit.
+template <int P>
+__device__ __forceinline__ void fft_r16(cd v[16], cd *lds, const cd *__restrict__ tw, int tid) {
+    constexpr int T = R16<P>::T, RC = R16<P>::RC;
+    dft16(v);  // pass Ns = 1: butterfly tid, no twiddles
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lds[lpad(16 * tid + k)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[lpad(tid + T * r)];
+    {
+        const int k16 = tid & 15;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[r * k16 * (P / 256)]);
+    }
+    dft16(v);  // pass Ns = 16
+    if constexpr (RC > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lds[lpad((tid >> 4) * 256 + (tid & 15) + 16 * k)] = v[k];
+        __syncthreads();
+        constexpr int NB = 16 / RC;  // butterflies per thread
+        cd u[16];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int j = tid + T * q;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+                const cd x = lds[lpad(j + 256 * r)];
+                u[q * RC + r] = r ? cmul(x, tw[r * j]) : x;
+            }
+            dft_small<RC>(&u[q * RC]);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < RC; ++r) v[q + r * NB] = u[q * RC + r];
+    }
+    __syncthreads();
+}
+
+enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
+
+template <int P, class IO>
+__global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, BluesteinDev B) {
+    constexpr int T = R16<P>::T, WG = R16<P>::WG, LINES = R16<P>::LINES, LW = R16<P>::LW;
+    extern __shared__ cd smem[];
+    const int li = threadIdx.x / T, tid = threadIdx.x % T;
+    const int line0 = blockIdx.x * LINES;
+    const int line = line0 + li;
+    cd *lds = smem + li * LW;
+    cd v[16];
+    if constexpr (IO::kLoad == IO_DIRECT) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int t = tid + T * s;
+            v[s] = (t < B.Kin && line < nlines) ? cmul(io.load(line, B.j0 + t), B.pre[t])
+                                                : cd{0.0, 0.0};
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < LINES * B.Kin; idx += WG) {
+            const int l = idx % LINES, t = idx / LINES;
+            const int ln = line0 + l;
+            smem[l * LW + lpad(t)] = ln < nlines ? cmul(io.load(ln, B.j0 + t), B.pre[t])
+                                                 : cd{0.0, 0.0};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int t = tid + T * s;
+            v[s] = t < B.Kin ? lds[lpad(t)] : cd{0.0, 0.0};
+        }
+        __syncthreads();
+    }
+    fft_r16<P>(v, lds, B.tw, tid);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = cconj(cmul(v[s], B.vhat[tid + T * s]));
+    fft_r16<P>(v, lds, B.tw, tid);
+    // v[s] = conj(c[q]), q = tid + T*s; output k = k0 + q - (Kin - 1)
+    const int qlo = B.Kin - 1;
+    if constexpr (IO::kStore == IO_DIRECT) {
+        if (line < nlines) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int q = tid + T * s - qlo;
+                if (q >= 0 && q < B.Kout) io.store(line, B.k0 + q, cmul(cconj(v[s]), B.post[q]));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int q = tid + T * s - qlo;
+            if (q >= 0 && q < B.Kout) lds[lpad(q)] = cmul(cconj(v[s]), B.post[q]);
+        }
+        __syncthreads();
+        if constexpr (IO::kStore == IO_STAGED) {
+            for (int idx = threadIdx.x; idx < LINES * B.Kout; idx += WG) {
+                const int l = idx % LINES, t = idx / LINES;
+                const int ln = line0 + l;
+                if (ln < nlines) io.store(ln, B.k0 + t, smem[l * LW + lpad(t)]);
+            }
+        } else {  // IO_PAIR: outputs k in [-K, K], K = -k0; pairs (k, -k)
+            if (line < nlines) {
+                const int K = -B.k0;
+                for (int k = tid; k <= K; k += T)
+                    io.store_pair(line, k, lds[lpad(k + K)], lds[lpad(K - k)]);
+            }
+        }
+    }
+}
+
+template <int P, class IO>
+static hipError_t launch_r16(const IO &io, int nlines, const BluesteinDev &B, hipStream_t st) {
+    using G = R16<P>;
+    const size_t lds = (size_t)G::LINES * G::LW * sizeof(cd);
+    if (lds > 65536) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_blue_r16<P, IO>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    const int grid = (nlines + G::LINES - 1) / G::LINES;
+    hipLaunchKernelGGL((k_blue_r16<P, IO>), dim3(grid), dim3(G::WG), lds, st, io, nlines, B);
+    return hipGetLastError();
+}
+
+template <class IO>
+static hipError_t run_bluestein_r16(const IO &io, int nlines, const BluesteinDev &B,
+                                    hipStream_t st) {
     if (nlines <= 0) return hipSuccess;
+    switch (B.P) {
+        case 256: return launch_r16<256>(io, nlines, B, st);
+        case 512: return launch_r16<512>(io, nlines, B, st);
+        case 1024: return launch_r16<1024>(io, nlines, B, st);
+        case 2048: return launch_r16<2048>(io, nlines, B, st);
+        case 4096: return launch_r16<4096>(io, nlines, B, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class IO>
+static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B, hipStream_t st) {
+    if (nlines <= 0) return hipSuccess;
+    constexpr bool IN_IL = IO::kLoad == IO_STAGED;
+    constexpr bool OUT_IL = IO::kStore == IO_STAGED;
 #define CVL_BLUE_CASE(PP)                                                              \
     case PP: {                                                                          \
         constexpr int LN = LinesFor<PP>::v;                                             \
@@ -149,11 +394,11 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B,
         CVL_BLUE_CASE(32)
         CVL_BLUE_CASE(64)
         CVL_BLUE_CASE(128)
-        CVL_BLUE_CASE(256)
-        CVL_BLUE_CASE(512)
-        CVL_BLUE_CASE(1024)
-        CVL_BLUE_CASE(2048)
-        CVL_BLUE_CASE(4096)
+        case 256: return launch_r16<256>(io, nlines, B, st);
+        case 512: return launch_r16<512>(io, nlines, B, st);
+        case 1024: return launch_r16<1024>(io, nlines, B, st);
+        case 2048: return launch_r16<2048>(io, nlines, B, st);
+        case 4096: return launch_r16<4096>(io, nlines, B, st);
         default:
             return hipErrorInvalidValue;
     }
@@ -169,6 +414,7 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B,
 // alpha DFT of the analysis: line (b, k >= 0); input over m in (-L, L) with the
 // reality condition W1(b, -m, -n) = conj W1(b, m, n); output a in [0, 2L-1).
 struct InvAlphaIO {
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *W1;
     cd *W2;
     int L, h, Nep, Nm;
@@ -183,30 +429,54 @@ struct InvAlphaIO {
     }
 };
 
-// gamma DFT of the analysis: line (a, b); input over n in (-L, L): even n from
-// W2 (n < 0 by conjugation), odd n zero; output g, written as (re, 0).
+// Coefficient of line (a, b) of the analysis gamma DFT at n (even n from W2,
+// n < 0 by conjugation, odd n zero).
+__device__ __forceinline__ cd inv_gamma_coef(const cd *W2, int L, int h, int Nm, int line, int n) {
+    if (n & 1) return cd{0.0, 0.0};
+    const int a = line / L, b = line % L;
+    const int k = n >= 0 ? n / 2 : -n / 2;
+    const cd v = W2[((size_t)b * Nm + a) * (h + 1) + k];
+    return n >= 0 ? v : cconj(v);
+}
+
+// gamma DFT of the analysis, one real line (a, b) per transform; written as (re, 0).
 struct InvGammaIO {
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *W2;
     cd *grid;
     int L, h, Nm;
-    __device__ cd load(int line, int n) const {
-        if (n & 1) return cd{0.0, 0.0};
-        const int a = line / L, b = line % L;
-        const int k = n >= 0 ? n / 2 : -n / 2;
-        const cd v = W2[((size_t)b * Nm + a) * (h + 1) + k];
-        return n >= 0 ? v : cconj(v);
-    }
+    __device__ cd load(int line, int n) const { return inv_gamma_coef(W2, L, h, Nm, line, n); }
     __device__ void store(int line, int g, cd v) const {
         grid[(size_t)line * Nm + g] = cd{v.x, 0.0};
     }
 };
 
-// gamma DFT of the synthesis: line (a, b) of the complex grid; even n kept.
+// gamma DFT of the analysis, two real lines (2p, 2p+1) per complex transform:
+// z_n = c1_n + i c2_n, line 2p = Re, line 2p+1 = Im of the result.
+struct InvGammaPackIO {
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    const cd *W2;
+    cd *grid;
+    int L, h, Nm, nreal;
+    __device__ cd load(int p, int n) const {
+        const cd c1 = inv_gamma_coef(W2, L, h, Nm, 2 * p, n);
+        const cd c2 = (2 * p + 1 < nreal) ? inv_gamma_coef(W2, L, h, Nm, 2 * p + 1, n)
+                                          : cd{0.0, 0.0};
+        return cd{c1.x - c2.y, c1.y + c2.x};
+    }
+    __device__ void store(int p, int g, cd v) const {
+        grid[(size_t)(2 * p) * Nm + g] = cd{v.x, 0.0};
+        if (2 * p + 1 < nreal) grid[(size_t)(2 * p + 1) * Nm + g] = cd{v.y, 0.0};
+    }
+};
+
+// gamma DFT of the synthesis on the real part of line (a, b); even n kept.
 struct FwdGammaIO {
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *grid;
     cd *V1;
     int L, h, Nm, Nep;
-    __device__ cd load(int line, int g) const { return grid[(size_t)line * Nm + g]; }
+    __device__ cd load(int line, int g) const { return cd{grid[(size_t)line * Nm + g].x, 0.0}; }
     __device__ void store(int line, int n, cd v) const {
         if (n & 1) return;
         const int a = line / L, b = line % L;
@@ -214,8 +484,37 @@ struct FwdGammaIO {
     }
 };
 
+// gamma DFT of the synthesis, real parts of lines (2p, 2p+1) packed as
+// z = w1 + i w2; with Z_n its DFT, c1_n = (Z_n + conj Z_-n)/2 and
+// c2_n = (Z_n - conj Z_-n)/(2i), c_-n = conj c_n.
+struct FwdGammaPackIO {
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
+    const cd *grid;
+    cd *V1;
+    int L, h, Nm, Nep, nreal;
+    __device__ cd load(int p, int g) const {
+        const double w1 = grid[(size_t)(2 * p) * Nm + g].x;
+        const double w2 = (2 * p + 1 < nreal) ? grid[(size_t)(2 * p + 1) * Nm + g].x : 0.0;
+        return cd{w1, w2};
+    }
+    __device__ void put(int line, int n, cd c) const {
+        const int a = line / L, b = line % L;
+        cd *row = V1 + ((size_t)b * Nm + a) * Nep + h;
+        row[n / 2] = c;
+        if (n) row[-n / 2] = cconj(c);
+    }
+    __device__ void store_pair(int p, int n, cd zn, cd zmn) const {
+        if (n & 1) return;
+        const cd czm = cconj(zmn);
+        const cd s = cadd(zn, czm), d = csub(zn, czm);
+        put(2 * p, n, cd{0.5 * s.x, 0.5 * s.y});
+        if (2 * p + 1 < nreal) put(2 * p + 1, n, cd{0.5 * d.y, -0.5 * d.x});
+    }
+};
+
 // alpha DFT of the synthesis: line (b, nn); outputs m in [0, L).
 struct FwdAlphaIO {
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *V1;
     cd *V2;
     int L, Ne, Nm, Nep;
@@ -230,6 +529,7 @@ struct FwdAlphaIO {
 };
 
 struct ShtInvPhiIO {
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *G;
     double *map;
     int L, Nm;
@@ -240,6 +540,7 @@ struct ShtInvPhiIO {
 };
 
 struct ShtFwdPhiIO {
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const double *map;
     cd *F1;
     int L, Nm;
@@ -250,32 +551,42 @@ struct ShtFwdPhiIO {
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
                             cd *W2, hipStream_t st) {
     InvAlphaIO io{W1, W2, g.L, g.h, g.Nep, g.Nm};
-    return run_bluestein<true, true>(io, g.L * (g.h + 1), B, st);
+    return run_bluestein(io, g.L * (g.h + 1), B, st);
 }
 hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
                             cd *grid, hipStream_t st) {
+    const int nreal = g.Nm * g.L;
+    if (B.P >= 256) {
+        InvGammaPackIO io{W2, grid, g.L, g.h, g.Nm, nreal};
+        return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
+    }
     InvGammaIO io{W2, grid, g.L, g.h, g.Nm};
-    return run_bluestein<false, false>(io, g.Nm * g.L, B, st);
+    return run_bluestein(io, nreal, B, st);
 }
 hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
                             cd *V1, hipStream_t st) {
+    const int nreal = g.Nm * g.L;
+    if (B.P >= 256) {
+        FwdGammaPackIO io{grid, V1, g.L, g.h, g.Nm, g.Nep, nreal};
+        return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
+    }
     FwdGammaIO io{grid, V1, g.L, g.h, g.Nm, g.Nep};
-    return run_bluestein<false, false>(io, g.Nm * g.L, B, st);
+    return run_bluestein(io, nreal, B, st);
 }
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
                             cd *V2, hipStream_t st) {
     FwdAlphaIO io{V1, V2, g.L, g.Ne, g.Nm, g.Nep};
-    return run_bluestein<true, true>(io, g.L * g.Ne, B, st);
+    return run_bluestein(io, g.L * g.Ne, B, st);
 }
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,
                               hipStream_t st) {
     ShtInvPhiIO io{G, map, L, 2 * L - 1};
-    return run_bluestein<false, false>(io, L, B, st);
+    return run_bluestein(io, L, B, st);
 }
 hipError_t launch_sht_fwd_phi(int L, const BluesteinDev &B, const double *map, cd *F1,
                               hipStream_t st) {
     ShtFwdPhiIO io{map, F1, L, 2 * L - 1};
-    return run_bluestein<false, false>(io, L, B, st);
+    return run_bluestein(io, L, B, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,6 +596,7 @@ hipError_t launch_sht_fwd_phi(int L, const BluesteinDev &B, const double *map, c
 static inline int nnp_of(int N) { return ((2 * N - 1) + 31) / 32 * 32; }
 
 struct GenInvAlphaIO {  // line (b, n); in m; out a
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *W1;
     cd *W2;
     int L, Nn, Nnp, Nm;
@@ -298,6 +610,7 @@ struct GenInvAlphaIO {  // line (b, n); in m; out a
     }
 };
 struct GenInvGammaIO {  // line (a, b); in n; out g
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *W2;
     cd *grid;
     int L, N, Nnp, Nm, Ng;
@@ -308,6 +621,7 @@ struct GenInvGammaIO {  // line (a, b); in n; out g
     __device__ void store(int line, int g, cd v) const { grid[(size_t)line * Ng + g] = v; }
 };
 struct GenFwdGammaIO {  // line (a, b); in g; out n
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *grid;
     cd *V1;
     int L, N, Nnp, Nm, Ng;
@@ -318,6 +632,7 @@ struct GenFwdGammaIO {  // line (a, b); in g; out n
     }
 };
 struct GenFwdAlphaIO {  // line (b, n); in a; out m
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *V1;
     cd *V2;
     int L, Nn, Nnp, Nm;
@@ -334,22 +649,22 @@ struct GenFwdAlphaIO {  // line (b, n); in a; out m
 hipError_t launch_gen_inv_alpha(int L, int N, const BluesteinDev &B, const cd *W1,
                                 cd *W2, hipStream_t st) {
     GenInvAlphaIO io{W1, W2, L, 2 * N - 1, nnp_of(N), 2 * L - 1};
-    return run_bluestein<true, true>(io, L * (2 * N - 1), B, st);
+    return run_bluestein(io, L * (2 * N - 1), B, st);
 }
 hipError_t launch_gen_inv_gamma(int L, int N, const BluesteinDev &B, const cd *W2,
                                 cd *grid, hipStream_t st) {
     GenInvGammaIO io{W2, grid, L, N, nnp_of(N), 2 * L - 1, 2 * N - 1};
-    return run_bluestein<false, false>(io, (2 * L - 1) * L, B, st);
+    return run_bluestein(io, (2 * L - 1) * L, B, st);
 }
 hipError_t launch_gen_fwd_gamma(int L, int N, const BluesteinDev &B, const cd *grid,
                                 cd *V1, hipStream_t st) {
     GenFwdGammaIO io{grid, V1, L, N, nnp_of(N), 2 * L - 1, 2 * N - 1};
-    return run_bluestein<false, false>(io, (2 * L - 1) * L, B, st);
+    return run_bluestein(io, (2 * L - 1) * L, B, st);
 }
 hipError_t launch_gen_fwd_alpha(int L, int N, const BluesteinDev &B, const cd *V1,
                                 cd *V2, hipStream_t st) {
     GenFwdAlphaIO io{V1, V2, L, 2 * N - 1, nnp_of(N), 2 * L - 1};
-    return run_bluestein<true, true>(io, L * (2 * N - 1), B, st);
+    return run_bluestein(io, L * (2 * N - 1), B, st);
 }
 
 }  // namespace cvl

@@ -150,6 +150,21 @@ def test_curvelet_c1_elementwise_and_deterministic(ctx):
     assert np.array_equal(r1, r2)
 
 
+def test_synthesis_uses_real_part_of_grids(ctx):
+    # synthesis(W1 + i W2) = synthesis(W1) + i synthesis(W2): the real map
+    # returned is the synthesis of W1 (both grids from analyses of real maps).
+    for L in (16, 64):
+        lam, J0 = 2.0, 2
+        say("real-part synthesis L=%d" % L)
+        m1 = osht.inverse(inputs.gaussian_real_flm(L, 1), L).real
+        m2 = osht.inverse(inputs.gaussian_real_flm(L, 2), L).real
+        s1, g1 = ctx.curvelet_analysis(dev(m1), lam, J0)
+        s2, g2 = ctx.curvelet_analysis(dev(m2), lam, J0)
+        mixed = [(a + 1j * b).contiguous() for a, b in zip(g1, g2)]
+        rec = host(ctx.curvelet_synthesis(s1, mixed, L, lam, J0))
+        assert rel_l2(rec, m1) < TOL
+
+
 def test_batch_equals_single(ctx):
     L, lam, J0 = 16, 2.0, 2
     say("batch of 3 vs single")
