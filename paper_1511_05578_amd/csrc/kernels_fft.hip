@@ -1,5 +1,5 @@
 // Odd-length McEwen-Wiaux DFTs (lengths 2L-1) as Bluestein chirp-z transforms
-// over power-of-two Stockham FFTs held in LDS.
+// over power-of-two Stockham FFTs.
 //
 // Every MW DFT is out[k] = scale * sum_j in[j] exp(sigma 2 pi i j k / Nd) for a
 // window of inputs j in [j0, j0+Kin) and outputs k in [k0, k0+Kout).  With
@@ -11,13 +11,17 @@
 //
 // Two engines: for P <= 128 a work-group of 256 threads transforms LINES
 // lines with radix-4 stages in LDS; for P >= 256 a register-resident radix-16
-// engine (below).  The stage IO policies gather / scatter each stage's lines
-// with the symmetries the stage uses (reality of the map, evenness of n) and
-// say whether a line is contiguous in memory (DIRECT) or interleaved with its
-// neighbours (STAGED through LDS for coalescing).
+// engine.  The stage IO policies gather / scatter each stage's lines with the
+// symmetries the stage uses (reality of the map, evenness of n) and say whether
+// a line is contiguous in memory (DIRECT) or interleaved with its neighbours
+// (STAGED through LDS so that global accesses stay coalesced).  Each policy
+// resolves a line to a context (base pointers) once; element accesses are then
+// plain offsets.
 #include "cvl_device.h"
 
 namespace cvl {
+
+enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
 
 // In-place Stockham FFT of one LDS line (forward, tw[x] = e^{-2 pi i x / P}).
 // Radix-4 stages first, then one radix-2 stage when log2 P is odd.  Every
@@ -89,8 +93,9 @@ struct LinesFor {
     static constexpr int v = (4096 / P) > 64 ? 64 : (4096 / P) < 1 ? 1 : (4096 / P);
 };
 
-template <int P, int LINES, bool IN_IL, bool OUT_IL, class IO>
+template <int P, int LINES, class IO>
 __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinDev B) {
+    constexpr bool IN_IL = IO::kLoad == IO_STAGED, OUT_IL = IO::kStore == IO_STAGED;
     extern __shared__ cd smem[];
     constexpr int TPL = 256 / LINES;
     const int tid = threadIdx.x;
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinD
         }
         const int line = line0 + l;
         cd v = cd{0.0, 0.0};
-        if (t < B.Kin && line < nlines) v = cmul(io.load(line, B.j0 + t), B.pre[t]);
+        if (t < B.Kin && line < nlines) v = cmul(io.load(io.at(line), B.j0 + t), B.pre[t]);
         smem[l * P + t] = v;
     }
     __syncthreads();
@@ -116,19 +121,31 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinD
     for (int t = lane; t < P; t += TPL) buf[t] = cconj(cmul(buf[t], B.vhat[t]));
     __syncthreads();
     fft_lds<P, TPL>(buf, B.tw, lane);
-    for (int idx = tid; idx < LINES * B.Kout; idx += 256) {
-        int l, t;
-        if (OUT_IL) {
-            l = idx % LINES;
-            t = idx / LINES;
-        } else {
-            l = idx / B.Kout;
-            t = idx % B.Kout;
-        }
-        const int line = line0 + l;
+    for (int t = lane; t < B.Kout; t += TPL) {
+        const cd c = cconj(buf[t + B.Kin - 1]);
+        buf[t + B.Kin - 1] = cmul(c, B.post[t]);
+    }
+    __syncthreads();
+    if constexpr (IO::kStore == IO_PAIR) {
+        const int line = line0 + li;
         if (line < nlines) {
-            const cd c = cconj(smem[l * P + t + B.Kin - 1]);
-            io.store(line, B.k0 + t, cmul(c, B.post[t]));
+            const auto c = io.at(line);
+            const int K = -B.k0;
+            for (int k = lane; k <= K; k += TPL)
+                io.store_pair(c, k, buf[k + K + B.Kin - 1], buf[K - k + B.Kin - 1]);
+        }
+    } else {
+        for (int idx = tid; idx < LINES * B.Kout; idx += 256) {
+            int l, t;
+            if (OUT_IL) {
+                l = idx % LINES;
+                t = idx / LINES;
+            } else {
+                l = idx / B.Kout;
+                t = idx % B.Kout;
+            }
+            const int line = line0 + l;
+            if (line < nlines) io.store(io.at(line), B.k0 + t, smem[l * P + t + B.Kin - 1]);
         }
     }
 }
@@ -223,6 +240,22 @@ __device__ __forceinline__ void dft_small(cd *v) {
 
 __device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
 
+// Orders one line's LDS exchange.  When a line lives in a single wavefront
+// (P <= 1024) the exchange is wave-local: a wavefront-scope fence keeps the
+// compiler from moving LDS accesses across it, and a wave's LDS instructions
+// complete in order, so no work-group barrier is needed.  Larger lines span
+// several wavefronts and synchronise the work-group.
+template <int P>
+__device__ __forceinline__ void line_sync() {
+    if constexpr (P / 16 <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int P>
 struct R16 {
     static constexpr int T = P / 16;                 // threads per line
@@ -239,30 +272,56 @@ __device__ __forceinline__ void fft_r16(cd v[16], cd *lds, const cd *__restrict_
     dft16(v);  // pass Ns = 1: butterfly tid, no twiddles
 #pragma unroll
     for (int k = 0; k < 16; ++k) lds[lpad(16 * tid + k)] = v[k];
-    __syncthreads();
+    line_sync<P>();
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = lds[lpad(tid + T * r)];
     {
-        const int k16 = tid & 15;
+        // w^{r e0}, r = 1..15, from one table load by a depth-4 product tree
+        cd w[16];
+        w[1] = tw[(tid & 15) * (P / 256)];
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+        w[8] = cmul(w[4], w[4]);
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[r * k16 * (P / 256)]);
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
     }
     dft16(v);  // pass Ns = 16
     if constexpr (RC > 1) {
-        __syncthreads();
+        line_sync<P>();
 #pragma unroll
         for (int k = 0; k < 16; ++k) lds[lpad((tid >> 4) * 256 + (tid & 15) + 16 * k)] = v[k];
-        __syncthreads();
+        line_sync<P>();
         constexpr int NB = 16 / RC;  // butterflies per thread
         cd u[16];
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int j = tid + T * q;
-#pragma unroll
-            for (int r = 0; r < RC; ++r) {
-                const cd x = lds[lpad(j + 256 * r)];
-                u[q * RC + r] = r ? cmul(x, tw[r * j]) : x;
+            cd w[16];
+            w[1] = tw[j];
+            if constexpr (RC > 2) {
+                w[2] = cmul(w[1], w[1]);
+                w[3] = cmul(w[2], w[1]);
             }
+            if constexpr (RC > 4) {
+                w[4] = cmul(w[2], w[2]);
+                w[5] = cmul(w[4], w[1]);
+                w[6] = cmul(w[4], w[2]);
+                w[7] = cmul(w[4], w[3]);
+            }
+            if constexpr (RC > 8) {
+                w[8] = cmul(w[4], w[4]);
+#pragma unroll
+                for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+            }
+            u[q * RC] = lds[lpad(j)];
+#pragma unroll
+            for (int r = 1; r < RC; ++r) u[q * RC + r] = cmul(lds[lpad(j + 256 * r)], w[r]);
             dft_small<RC>(&u[q * RC]);
         }
 #pragma unroll
@@ -270,10 +329,8 @@ __device__ __forceinline__ void fft_r16(cd v[16], cd *lds, const cd *__restrict_
 #pragma unroll
             for (int r = 0; r < RC; ++r) v[q + r * NB] = u[q * RC + r];
     }
-    __syncthreads();
+    line_sync<P>();
 }
-
-enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
 
 template <int P, class IO>
 __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, BluesteinDev B) {
@@ -285,18 +342,27 @@ __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, Blue
     cd *lds = smem + li * LW;
     cd v[16];
     if constexpr (IO::kLoad == IO_DIRECT) {
+        if (line < nlines) {
+            const auto c = io.at(line);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int t = tid + T * s;
-            v[s] = (t < B.Kin && line < nlines) ? cmul(io.load(line, B.j0 + t), B.pre[t])
-                                                : cd{0.0, 0.0};
+            for (int s = 0; s < 16; ++s) {
+                const int t = tid + T * s;
+                v[s] = t < B.Kin ? cmul(io.load(c, B.j0 + t), B.pre[t]) : cd{0.0, 0.0};
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = cd{0.0, 0.0};
         }
     } else {
-        for (int idx = threadIdx.x; idx < LINES * B.Kin; idx += WG) {
-            const int l = idx % LINES, t = idx / LINES;
-            const int ln = line0 + l;
-            smem[l * LW + lpad(t)] = ln < nlines ? cmul(io.load(ln, B.j0 + t), B.pre[t])
-                                                 : cd{0.0, 0.0};
+        // WG is a multiple of LINES, so each thread always stages the same line.
+        const int ls = threadIdx.x % LINES, lns = line0 + ls;
+        cd *dst = smem + ls * LW;
+        if (lns < nlines) {
+            const auto c = io.at(lns);
+            for (int t = threadIdx.x / LINES; t < B.Kin; t += WG / LINES)
+                dst[lpad(t)] = cmul(io.load(c, B.j0 + t), B.pre[t]);
+        } else {
+            for (int t = threadIdx.x / LINES; t < B.Kin; t += WG / LINES) dst[lpad(t)] = cd{0.0, 0.0};
         }
         __syncthreads();
 #pragma unroll
@@ -314,10 +380,11 @@ __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, Blue
     const int qlo = B.Kin - 1;
     if constexpr (IO::kStore == IO_DIRECT) {
         if (line < nlines) {
+            const auto c = io.at(line);
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const int q = tid + T * s - qlo;
-                if (q >= 0 && q < B.Kout) io.store(line, B.k0 + q, cmul(cconj(v[s]), B.post[q]));
+                if (q >= 0 && q < B.Kout) io.store(c, B.k0 + q, cmul(cconj(v[s]), B.post[q]));
             }
         }
     } else {
@@ -328,16 +395,19 @@ __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, Blue
         }
         __syncthreads();
         if constexpr (IO::kStore == IO_STAGED) {
-            for (int idx = threadIdx.x; idx < LINES * B.Kout; idx += WG) {
-                const int l = idx % LINES, t = idx / LINES;
-                const int ln = line0 + l;
-                if (ln < nlines) io.store(ln, B.k0 + t, smem[l * LW + lpad(t)]);
+            const int ls = threadIdx.x % LINES, lns = line0 + ls;
+            if (lns < nlines) {
+                const auto c = io.at(lns);
+                const cd *src = smem + ls * LW;
+                for (int t = threadIdx.x / LINES; t < B.Kout; t += WG / LINES)
+                    io.store(c, B.k0 + t, src[lpad(t)]);
             }
         } else {  // IO_PAIR: outputs k in [-K, K], K = -k0; pairs (k, -k)
             if (line < nlines) {
+                const auto c = io.at(line);
                 const int K = -B.k0;
                 for (int k = tid; k <= K; k += T)
-                    io.store_pair(line, k, lds[lpad(k + K)], lds[lpad(K - k)]);
+                    io.store_pair(c, k, lds[lpad(k + K)], lds[lpad(K - k)]);
             }
         }
     }
@@ -378,14 +448,12 @@ static hipError_t run_bluestein_r16(const IO &io, int nlines, const BluesteinDev
 template <class IO>
 static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B, hipStream_t st) {
     if (nlines <= 0) return hipSuccess;
-    constexpr bool IN_IL = IO::kLoad == IO_STAGED;
-    constexpr bool OUT_IL = IO::kStore == IO_STAGED;
 #define CVL_BLUE_CASE(PP)                                                              \
     case PP: {                                                                          \
         constexpr int LN = LinesFor<PP>::v;                                             \
         const int grid = (nlines + LN - 1) / LN;                                        \
-        hipLaunchKernelGGL((k_bluestein<PP, LN, IN_IL, OUT_IL, IO>), dim3(grid),        \
-                           dim3(256), LN * PP * sizeof(cd), st, io, nlines, B);         \
+        hipLaunchKernelGGL((k_bluestein<PP, LN, IO>), dim3(grid), dim3(256),            \
+                           LN * PP * sizeof(cd), st, io, nlines, B);                    \
         return hipGetLastError();                                                       \
     }
     switch (B.P) {
@@ -394,13 +462,8 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B,
         CVL_BLUE_CASE(32)
         CVL_BLUE_CASE(64)
         CVL_BLUE_CASE(128)
-        case 256: return launch_r16<256>(io, nlines, B, st);
-        case 512: return launch_r16<512>(io, nlines, B, st);
-        case 1024: return launch_r16<1024>(io, nlines, B, st);
-        case 2048: return launch_r16<2048>(io, nlines, B, st);
-        case 4096: return launch_r16<4096>(io, nlines, B, st);
         default:
-            return hipErrorInvalidValue;
+            return run_bluestein_r16(io, nlines, B, st);
     }
 #undef CVL_BLUE_CASE
 }
@@ -418,55 +481,77 @@ struct InvAlphaIO {
     const cd *W1;
     cd *W2;
     int L, h, Nep, Nm;
-    __device__ cd load(int line, int m) const {
+    struct Ctx {
+        const cd *pos, *neg;  // W1[b][m][h+k], W1[b][m][h-k] at m = 0
+        cd *out;              // W2[b][a][k] at a = 0
+    };
+    __device__ Ctx at(int line) const {
         const int b = line / (h + 1), k = line % (h + 1);
-        if (m >= 0) return W1[((size_t)b * L + m) * Nep + h + k];
-        return cconj(W1[((size_t)b * L - m) * Nep + h - k]);
+        const cd *base = W1 + (size_t)b * L * Nep + h;
+        return Ctx{base + k, base - k, W2 + (size_t)b * Nm * (h + 1) + k};
     }
-    __device__ void store(int line, int a, cd v) const {
-        const int b = line / (h + 1), k = line % (h + 1);
-        W2[((size_t)b * Nm + a) * (h + 1) + k] = v;
+    __device__ cd load(const Ctx &c, int m) const {
+        return m >= 0 ? c.pos[(size_t)m * Nep] : cconj(c.neg[(size_t)(-m) * Nep]);
     }
+    __device__ void store(const Ctx &c, int a, cd v) const { c.out[(size_t)a * (h + 1)] = v; }
 };
 
-// Coefficient of line (a, b) of the analysis gamma DFT at n (even n from W2,
-// n < 0 by conjugation, odd n zero).
-__device__ __forceinline__ cd inv_gamma_coef(const cd *W2, int L, int h, int Nm, int line, int n) {
-    if (n & 1) return cd{0.0, 0.0};
-    const int a = line / L, b = line % L;
-    const int k = n >= 0 ? n / 2 : -n / 2;
-    const cd v = W2[((size_t)b * Nm + a) * (h + 1) + k];
-    return n >= 0 ? v : cconj(v);
-}
-
 // gamma DFT of the analysis, one real line (a, b) per transform; written as (re, 0).
+// Coefficients: even n from W2 (n < 0 by conjugation), odd n zero.
 struct InvGammaIO {
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *W2;
     cd *grid;
     int L, h, Nm;
-    __device__ cd load(int line, int n) const { return inv_gamma_coef(W2, L, h, Nm, line, n); }
-    __device__ void store(int line, int g, cd v) const {
-        grid[(size_t)line * Nm + g] = cd{v.x, 0.0};
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        return Ctx{W2 + ((size_t)b * Nm + a) * (h + 1), grid + (size_t)line * Nm};
     }
+    __device__ cd load(const Ctx &c, int n) const {
+        if (n & 1) return cd{0.0, 0.0};
+        return n >= 0 ? c.src[n / 2] : cconj(c.src[-n / 2]);
+    }
+    __device__ void store(const Ctx &c, int g, cd v) const { c.dst[g] = cd{v.x, 0.0}; }
 };
 
 // gamma DFT of the analysis, two real lines (2p, 2p+1) per complex transform:
-// z_n = c1_n + i c2_n, line 2p = Re, line 2p+1 = Im of the result.
+// z_n = c1_n + i c2_n; line 2p is the real, line 2p+1 the imaginary part.
 struct InvGammaPackIO {
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *W2;
     cd *grid;
     int L, h, Nm, nreal;
-    __device__ cd load(int p, int n) const {
-        const cd c1 = inv_gamma_coef(W2, L, h, Nm, 2 * p, n);
-        const cd c2 = (2 * p + 1 < nreal) ? inv_gamma_coef(W2, L, h, Nm, 2 * p + 1, n)
-                                          : cd{0.0, 0.0};
+    struct Ctx {
+        const cd *s1, *s2;
+        cd *d1, *d2;
+        bool two;
+    };
+    __device__ Ctx at(int p) const {
+        const int l1 = 2 * p, l2 = 2 * p + 1;
+        const bool two = l2 < nreal;
+        const int a1 = l1 / L, b1 = l1 % L;
+        const int a2 = two ? l2 / L : a1, b2 = two ? l2 % L : b1;
+        return Ctx{W2 + ((size_t)b1 * Nm + a1) * (h + 1), W2 + ((size_t)b2 * Nm + a2) * (h + 1),
+                   grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm, two};
+    }
+    __device__ cd load(const Ctx &c, int n) const {
+        if (n & 1) return cd{0.0, 0.0};
+        const int k = n >= 0 ? n / 2 : -n / 2;
+        cd c1 = c.s1[k];
+        cd c2 = c.two ? c.s2[k] : cd{0.0, 0.0};
+        if (n < 0) {
+            c1 = cconj(c1);
+            c2 = cconj(c2);
+        }
         return cd{c1.x - c2.y, c1.y + c2.x};
     }
-    __device__ void store(int p, int g, cd v) const {
-        grid[(size_t)(2 * p) * Nm + g] = cd{v.x, 0.0};
-        if (2 * p + 1 < nreal) grid[(size_t)(2 * p + 1) * Nm + g] = cd{v.y, 0.0};
+    __device__ void store(const Ctx &c, int g, cd v) const {
+        c.d1[g] = cd{v.x, 0.0};
+        if (c.two) c.d2[g] = cd{v.y, 0.0};
     }
 };
 
@@ -476,11 +561,18 @@ struct FwdGammaIO {
     const cd *grid;
     cd *V1;
     int L, h, Nm, Nep;
-    __device__ cd load(int line, int g) const { return cd{grid[(size_t)line * Nm + g].x, 0.0}; }
-    __device__ void store(int line, int n, cd v) const {
-        if (n & 1) return;
+    struct Ctx {
+        const cd *src;
+        cd *dst;  // V1[b][a][h]
+    };
+    __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
-        V1[((size_t)b * Nm + a) * Nep + (n / 2 + h)] = v;
+        return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * Nep + h};
+    }
+    __device__ cd load(const Ctx &c, int g) const { return cd{c.src[g].x, 0.0}; }
+    __device__ void store(const Ctx &c, int n, cd v) const {
+        if (n & 1) return;
+        c.dst[n / 2] = v;
     }
 };
 
@@ -492,23 +584,35 @@ struct FwdGammaPackIO {
     const cd *grid;
     cd *V1;
     int L, h, Nm, Nep, nreal;
-    __device__ cd load(int p, int g) const {
-        const double w1 = grid[(size_t)(2 * p) * Nm + g].x;
-        const double w2 = (2 * p + 1 < nreal) ? grid[(size_t)(2 * p + 1) * Nm + g].x : 0.0;
-        return cd{w1, w2};
+    struct Ctx {
+        const cd *s1, *s2;
+        cd *d1, *d2;  // V1[b][a][h] of both lines
+        bool two;
+    };
+    __device__ Ctx at(int p) const {
+        const int l1 = 2 * p, l2 = 2 * p + 1;
+        const bool two = l2 < nreal;
+        const int a1 = l1 / L, b1 = l1 % L;
+        const int a2 = two ? l2 / L : a1, b2 = two ? l2 % L : b1;
+        return Ctx{grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm,
+                   V1 + ((size_t)b1 * Nm + a1) * Nep + h, V1 + ((size_t)b2 * Nm + a2) * Nep + h,
+                   two};
     }
-    __device__ void put(int line, int n, cd c) const {
-        const int a = line / L, b = line % L;
-        cd *row = V1 + ((size_t)b * Nm + a) * Nep + h;
-        row[n / 2] = c;
-        if (n) row[-n / 2] = cconj(c);
+    __device__ cd load(const Ctx &c, int g) const {
+        return cd{c.s1[g].x, c.two ? c.s2[g].x : 0.0};
     }
-    __device__ void store_pair(int p, int n, cd zn, cd zmn) const {
+    __device__ void store_pair(const Ctx &c, int n, cd zn, cd zmn) const {
         if (n & 1) return;
         const cd czm = cconj(zmn);
         const cd s = cadd(zn, czm), d = csub(zn, czm);
-        put(2 * p, n, cd{0.5 * s.x, 0.5 * s.y});
-        if (2 * p + 1 < nreal) put(2 * p + 1, n, cd{0.5 * d.y, -0.5 * d.x});
+        const cd c1 = cd{0.5 * s.x, 0.5 * s.y};
+        c.d1[n / 2] = c1;
+        if (n) c.d1[-n / 2] = cconj(c1);
+        if (c.two) {
+            const cd c2 = cd{0.5 * d.y, -0.5 * d.x};
+            c.d2[n / 2] = c2;
+            if (n) c.d2[-n / 2] = cconj(c2);
+        }
     }
 };
 
@@ -518,14 +622,16 @@ struct FwdAlphaIO {
     const cd *V1;
     cd *V2;
     int L, Ne, Nm, Nep;
-    __device__ cd load(int line, int a) const {
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int line) const {
         const int b = line / Ne, nn = line % Ne;
-        return V1[((size_t)b * Nm + a) * Nep + nn];
+        return Ctx{V1 + (size_t)b * Nm * Nep + nn, V2 + (size_t)b * L * Nep + nn};
     }
-    __device__ void store(int line, int m, cd v) const {
-        const int b = line / Ne, nn = line % Ne;
-        V2[((size_t)b * L + m) * Nep + nn] = v;
-    }
+    __device__ cd load(const Ctx &c, int a) const { return c.src[(size_t)a * Nep]; }
+    __device__ void store(const Ctx &c, int m, cd v) const { c.dst[(size_t)m * Nep] = v; }
 };
 
 struct ShtInvPhiIO {
@@ -533,10 +639,15 @@ struct ShtInvPhiIO {
     const cd *G;
     double *map;
     int L, Nm;
-    __device__ cd load(int t, int m) const {
-        return m >= 0 ? G[(size_t)t * L + m] : cconj(G[(size_t)t * L - m]);
+    struct Ctx {
+        const cd *src;
+        double *dst;
+    };
+    __device__ Ctx at(int t) const { return Ctx{G + (size_t)t * L, map + (size_t)t * Nm}; }
+    __device__ cd load(const Ctx &c, int m) const {
+        return m >= 0 ? c.src[m] : cconj(c.src[-m]);
     }
-    __device__ void store(int t, int p, cd v) const { map[(size_t)t * Nm + p] = v.x; }
+    __device__ void store(const Ctx &c, int p, cd v) const { c.dst[p] = v.x; }
 };
 
 struct ShtFwdPhiIO {
@@ -544,8 +655,13 @@ struct ShtFwdPhiIO {
     const double *map;
     cd *F1;
     int L, Nm;
-    __device__ cd load(int t, int p) const { return cd{map[(size_t)t * Nm + p], 0.0}; }
-    __device__ void store(int t, int m, cd v) const { F1[(size_t)t * L + m] = v; }
+    struct Ctx {
+        const double *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int t) const { return Ctx{map + (size_t)t * Nm, F1 + (size_t)t * L}; }
+    __device__ cd load(const Ctx &c, int p) const { return cd{c.src[p], 0.0}; }
+    __device__ void store(const Ctx &c, int m, cd v) const { c.dst[m] = v; }
 };
 
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
@@ -600,50 +716,64 @@ struct GenInvAlphaIO {  // line (b, n); in m; out a
     const cd *W1;
     cd *W2;
     int L, Nn, Nnp, Nm;
-    __device__ cd load(int line, int m) const {
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int line) const {
         const int b = line / Nn, n = line % Nn;
-        return W1[((size_t)b * Nm + (m + L - 1)) * Nnp + n];
+        return Ctx{W1 + ((size_t)b * Nm + (L - 1)) * Nnp + n, W2 + (size_t)b * Nm * Nnp + n};
     }
-    __device__ void store(int line, int a, cd v) const {
-        const int b = line / Nn, n = line % Nn;
-        W2[((size_t)b * Nm + a) * Nnp + n] = v;
-    }
+    __device__ cd load(const Ctx &c, int m) const { return c.src[(ptrdiff_t)m * Nnp]; }
+    __device__ void store(const Ctx &c, int a, cd v) const { c.dst[(size_t)a * Nnp] = v; }
 };
 struct GenInvGammaIO {  // line (a, b); in n; out g
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *W2;
     cd *grid;
     int L, N, Nnp, Nm, Ng;
-    __device__ cd load(int line, int n) const {
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
-        return W2[((size_t)b * Nm + a) * Nnp + (n + N - 1)];
+        return Ctx{W2 + ((size_t)b * Nm + a) * Nnp + (N - 1), grid + (size_t)line * Ng};
     }
-    __device__ void store(int line, int g, cd v) const { grid[(size_t)line * Ng + g] = v; }
+    __device__ cd load(const Ctx &c, int n) const { return c.src[n]; }
+    __device__ void store(const Ctx &c, int g, cd v) const { c.dst[g] = v; }
 };
 struct GenFwdGammaIO {  // line (a, b); in g; out n
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *grid;
     cd *V1;
     int L, N, Nnp, Nm, Ng;
-    __device__ cd load(int line, int g) const { return grid[(size_t)line * Ng + g]; }
-    __device__ void store(int line, int n, cd v) const {
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
-        V1[((size_t)b * Nm + a) * Nnp + (n + N - 1)] = v;
+        return Ctx{grid + (size_t)line * Ng, V1 + ((size_t)b * Nm + a) * Nnp + (N - 1)};
     }
+    __device__ cd load(const Ctx &c, int g) const { return c.src[g]; }
+    __device__ void store(const Ctx &c, int n, cd v) const { c.dst[n] = v; }
 };
 struct GenFwdAlphaIO {  // line (b, n); in a; out m
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *V1;
     cd *V2;
     int L, Nn, Nnp, Nm;
-    __device__ cd load(int line, int a) const {
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int line) const {
         const int b = line / Nn, n = line % Nn;
-        return V1[((size_t)b * Nm + a) * Nnp + n];
+        return Ctx{V1 + (size_t)b * Nm * Nnp + n, V2 + ((size_t)b * Nm + (L - 1)) * Nnp + n};
     }
-    __device__ void store(int line, int m, cd v) const {
-        const int b = line / Nn, n = line % Nn;
-        V2[((size_t)b * Nm + (m + L - 1)) * Nnp + n] = v;
-    }
+    __device__ cd load(const Ctx &c, int a) const { return c.src[(size_t)a * Nnp]; }
+    __device__ void store(const Ctx &c, int m, cd v) const { c.dst[(ptrdiff_t)m * Nnp] = v; }
 };
 
 hipError_t launch_gen_inv_alpha(int L, int N, const BluesteinDev &B, const cd *W1,

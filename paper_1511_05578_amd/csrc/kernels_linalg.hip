@@ -174,9 +174,100 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
     }
 }
 
+// MFMA version for the curvelet layout (every 32-complex-column tile inside one
+// m, so one parity per tile).  Tile 128 rows x 64 real columns x 16 k; wave w
+// owns rows [32w, 32w+32) as 2 x 4 blocks of v_mfma_f64_16x16x4f64, whose lane
+// layout is A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].  The factor i of
+// odd parity is applied while staging B: (re, im) -> (-im, re).
+typedef double cvl_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_beta_mfma(int M, int K, int ncols, int Nep,
+                                                   const double *__restrict__ Ae,
+                                                   const double *__restrict__ Ao,
+                                                   const double *__restrict__ in,
+                                                   double *__restrict__ out) {
+    __shared__ double As[128][17];
+    __shared__ double Bs[16][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.y * 128;
+    const int c0 = blockIdx.x * 32;  // complex column base
+    const size_t ld = 2 * (size_t)ncols;
+    const int par = (c0 / Nep) & 1;
+    const double *A = par ? Ao : Ae;
+    cvl_d4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = cvl_d4{0.0, 0.0, 0.0, 0.0};
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int rr = idx >> 4, kk = idx & 15;
+            const int r = r0 + rr, k = k0 + kk;
+            As[rr][kk] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.0;
+        }
+        {
+            const int kk = tid >> 4, cc = (tid & 15) * 4;  // 4 doubles = 2 complex
+            const int k = k0 + kk;
+            const size_t col = 2 * (size_t)c0 + cc;
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+            if (k < K && col + 3 < ld) {
+                const double *src = in + (size_t)k * ld + col;
+                x0 = src[0];
+                x1 = src[1];
+                x2 = src[2];
+                x3 = src[3];
+            }
+            if (par) {
+                Bs[kk][cc] = -x1;
+                Bs[kk][cc + 1] = x0;
+                Bs[kk][cc + 2] = -x3;
+                Bs[kk][cc + 3] = x2;
+            } else {
+                Bs[kk][cc] = x0;
+                Bs[kk][cc + 1] = x1;
+                Bs[kk][cc + 2] = x2;
+                Bs[kk][cc + 3] = x3;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lk;
+            const double a0 = As[32 * w + lr][k];
+            const double a1 = As[32 * w + 16 + lr][k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double b = Bs[k][16 * j + lr];
+                acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 32 * w + 16 * i + 4 * r + lk;
+                const size_t col = 2 * (size_t)c0 + 16 * j + lr;
+                if (row < M && col < ld) out[(size_t)row * ld + col] = acc[i][j][r];
+            }
+}
+
 hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0,
                             const double *Aeven, const double *Aodd, const cd *in, cd *out,
                             hipStream_t st) {
+    if (mode == 0 && Nep % 32 == 0) {
+        dim3 g((ncols + 31) / 32, (M + 127) / 128);
+        hipLaunchKernelGGL(k_beta_mfma, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
+                           (const double *)in, (double *)out);
+        return hipGetLastError();
+    }
     dim3 grid((ncols + 31) / 32, (M + 63) / 64);
     if (mode == 0 && Nep % 32 == 0)
         hipLaunchKernelGGL(k_beta_gemm<true>, grid, dim3(256), 0, st, M, K, ncols, Nep, mode,
