@@ -170,6 +170,9 @@ int get_bluestein(cvl_ctx *c, int Nd, int Kin, int j0, int Kout, int k0, int sig
     const double scale = sigma < 0 ? 1.0 / Nd : 1.0;
     host::Bluestein B = host::make_bluestein(Nd, Kin, j0, Kout, k0, sigma, scale);
     if (B.P > 4096) return fail(CVL_EUNSUPPORTED, "DFT length %d needs FFT size %d > 4096", Nd, B.P);
+    if (B.P >= 256 && 2 * std::max(Kin, Kout) > B.P + B.P / 16)
+        return fail(CVL_EUNSUPPORTED, "DFT window (%d in, %d out) too wide for FFT size %d", Kin,
+                    Kout, B.P);
     auto cv = [](const std::vector<std::complex<double>> &s) {
         std::vector<cd> v(s.size());
         for (size_t i = 0; i < s.size(); ++i) v[i] = cd{s[i].real(), s[i].imag()};
@@ -807,7 +810,7 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
             const ScaleGeom &g = S.g;
             const cd *grid = (const cd *)grids[(size_t)bi * nJ + s];
             LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, B.b0, st));
-            LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_half, B.b0, B.b1, st));
+            LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, B.b0, B.b1, st));
             LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
                                                  S.beta.Qs, B.b1, B.b0, st));
             LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd(g, L, ctx->delta, B.b0, S.psi, B.b1,

@@ -262,84 +262,113 @@ struct R16 {
     static constexpr int WG = T < 128 ? 128 : T;     // threads per work-group
     static constexpr int LINES = WG / T;             // lines per work-group
     static constexpr int RC = P / 256;               // radix of the last pass (1: none)
-    static constexpr int LW = P + P / 16;            // padded LDS line length
+    static constexpr int LW = P + P / 16 + 4;        // doubles per LDS line (padded)
 };
 
-// Forward FFT of one line; v[s] = element tid + T*s on entry and on exit.
-template <int P>
-__device__ __forceinline__ void fft_r16(cd v[16], cd *lds, const cd *__restrict__ tw, int tid) {
-    constexpr int T = R16<P>::T, RC = R16<P>::RC;
-    dft16(v);  // pass Ns = 1: butterfly tid, no twiddles
+// Moves one line between passes through LDS, one real component at a time
+// (the LDS line holds P doubles): element wpos(k) leaves v[k], element rpos(r)
+// arrives in v[r].
+template <int P, class WP, class RP>
+__device__ __forceinline__ void exchange(cd v[16], double *lds, WP wpos, RP rpos) {
+    double nx[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) lds[lpad(16 * tid + k)] = v[k];
+    for (int k = 0; k < 16; ++k) lds[lpad(wpos(k))] = v[k].x;
     line_sync<P>();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = lds[lpad(tid + T * r)];
-    {
-        // w^{r e0}, r = 1..15, from one table load by a depth-4 product tree
-        cd w[16];
-        w[1] = tw[(tid & 15) * (P / 256)];
-        w[2] = cmul(w[1], w[1]);
-        w[3] = cmul(w[2], w[1]);
-        w[4] = cmul(w[2], w[2]);
-        w[5] = cmul(w[4], w[1]);
-        w[6] = cmul(w[4], w[2]);
-        w[7] = cmul(w[4], w[3]);
-        w[8] = cmul(w[4], w[4]);
+    for (int r = 0; r < 16; ++r) nx[r] = lds[lpad(rpos(r))];
+    line_sync<P>();
 #pragma unroll
-        for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    for (int k = 0; k < 16; ++k) lds[lpad(wpos(k))] = v[k].y;
+    line_sync<P>();
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
-    }
-    dft16(v);  // pass Ns = 16
-    if constexpr (RC > 1) {
-        line_sync<P>();
-#pragma unroll
-        for (int k = 0; k < 16; ++k) lds[lpad((tid >> 4) * 256 + (tid & 15) + 16 * k)] = v[k];
-        line_sync<P>();
-        constexpr int NB = 16 / RC;  // butterflies per thread
-        cd u[16];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int j = tid + T * q;
-            cd w[16];
-            w[1] = tw[j];
-            if constexpr (RC > 2) {
-                w[2] = cmul(w[1], w[1]);
-                w[3] = cmul(w[2], w[1]);
-            }
-            if constexpr (RC > 4) {
-                w[4] = cmul(w[2], w[2]);
-                w[5] = cmul(w[4], w[1]);
-                w[6] = cmul(w[4], w[2]);
-                w[7] = cmul(w[4], w[3]);
-            }
-            if constexpr (RC > 8) {
-                w[8] = cmul(w[4], w[4]);
-#pragma unroll
-                for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
-            }
-            u[q * RC] = lds[lpad(j)];
-#pragma unroll
-            for (int r = 1; r < RC; ++r) u[q * RC + r] = cmul(lds[lpad(j + 256 * r)], w[r]);
-            dft_small<RC>(&u[q * RC]);
-        }
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-#pragma unroll
-            for (int r = 0; r < RC; ++r) v[q + r * NB] = u[q * RC + r];
-    }
+    for (int r = 0; r < 16; ++r) v[r] = cd{nx[r], lds[lpad(rpos(r))]};
     line_sync<P>();
 }
 
+// v[r] *= w^r for r = 1..15 (w^r from w by a product tree, used as produced).
+__device__ __forceinline__ void twiddle16(cd v[16], cd w1) {
+    const cd w2 = cmul(w1, w1), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+    const cd w3 = cmul(w2, w1);
+    v[1] = cmul(v[1], w1);
+    v[2] = cmul(v[2], w2);
+    v[3] = cmul(v[3], w3);
+    v[4] = cmul(v[4], w4);
+    v[5] = cmul(v[5], cmul(w4, w1));
+    v[6] = cmul(v[6], cmul(w4, w2));
+    v[7] = cmul(v[7], cmul(w4, w3));
+    v[8] = cmul(v[8], w8);
+    v[9] = cmul(v[9], cmul(w8, w1));
+    v[10] = cmul(v[10], cmul(w8, w2));
+    v[11] = cmul(v[11], cmul(w8, w3));
+    const cd w12 = cmul(w8, w4);
+    v[12] = cmul(v[12], w12);
+    v[13] = cmul(v[13], cmul(w12, w1));
+    v[14] = cmul(v[14], cmul(w12, w2));
+    v[15] = cmul(v[15], cmul(w12, w3));
+}
+
+// Forward FFT of one line; v[s] = element tid + T*s on entry and on exit.
+template <int P>
+__device__ __forceinline__ void fft_r16(cd v[16], double *lds, const cd *__restrict__ tw, int tid) {
+    constexpr int T = R16<P>::T, RC = R16<P>::RC;
+    dft16(v);  // pass Ns = 1: butterfly tid, no twiddles
+    exchange<P>(v, lds, [&](int k) { return 16 * tid + k; }, [&](int r) { return tid + T * r; });
+    twiddle16(v, tw[(tid & 15) * (P / 256)]);
+    dft16(v);  // pass Ns = 16
+    if constexpr (RC > 1) {
+        constexpr int NB = 16 / RC;  // butterflies per thread
+        exchange<P>(
+            v, lds, [&](int k) { return (tid >> 4) * 256 + (tid & 15) + 16 * k; },
+            [&](int idx) { return tid + T * (idx / RC) + 256 * (idx % RC); });
+        // v[q*RC + r] = element j + 256 r, j = tid + T q
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int j = tid + T * q;
+            cd *u = &v[q * RC];
+            const cd w1 = tw[j];
+            if constexpr (RC == 2) {
+                u[1] = cmul(u[1], w1);
+            } else if constexpr (RC == 4) {
+                const cd w2 = cmul(w1, w1);
+                u[1] = cmul(u[1], w1);
+                u[2] = cmul(u[2], w2);
+                u[3] = cmul(u[3], cmul(w2, w1));
+            } else if constexpr (RC == 8) {
+                const cd w2 = cmul(w1, w1), w4 = cmul(w2, w2), w3 = cmul(w2, w1);
+                u[1] = cmul(u[1], w1);
+                u[2] = cmul(u[2], w2);
+                u[3] = cmul(u[3], w3);
+                u[4] = cmul(u[4], w4);
+                u[5] = cmul(u[5], cmul(w4, w1));
+                u[6] = cmul(u[6], cmul(w4, w2));
+                u[7] = cmul(u[7], cmul(w4, w3));
+            } else {
+                twiddle16(u, w1);
+            }
+            dft_small<RC>(u);
+        }
+        // element j + 256 r = tid + T (q + r NB): reorder to v[q + r NB]
+        cd t[16];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < RC; ++r) t[q + r * NB] = v[q * RC + r];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = t[k];
+    }
+}
+
+// Three waves per SIMD for lines that fit one wavefront (the kernel is latency
+// bound; the register cap costs at most a few spilled dwords).
 template <int P, class IO>
-__global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, BluesteinDev B) {
+__global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(IO io, int nlines,
+                                                                             BluesteinDev B) {
     constexpr int T = R16<P>::T, WG = R16<P>::WG, LINES = R16<P>::LINES, LW = R16<P>::LW;
-    extern __shared__ cd smem[];
+    extern __shared__ double smem_d[];
     const int li = threadIdx.x / T, tid = threadIdx.x % T;
     const int line0 = blockIdx.x * LINES;
     const int line = line0 + li;
-    cd *lds = smem + li * LW;
+    double *lds = smem_d + li * LW;
     cd v[16];
     if constexpr (IO::kLoad == IO_DIRECT) {
         if (line < nlines) {
@@ -354,21 +383,21 @@ __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, Blue
             for (int s = 0; s < 16; ++s) v[s] = cd{0.0, 0.0};
         }
     } else {
+        // Staged through the LDS lines viewed as complex (Kin <= P/2 fits).
         // WG is a multiple of LINES, so each thread always stages the same line.
         const int ls = threadIdx.x % LINES, lns = line0 + ls;
-        cd *dst = smem + ls * LW;
+        cd *dst = reinterpret_cast<cd *>(smem_d + ls * LW);
         if (lns < nlines) {
             const auto c = io.at(lns);
             for (int t = threadIdx.x / LINES; t < B.Kin; t += WG / LINES)
-                dst[lpad(t)] = cmul(io.load(c, B.j0 + t), B.pre[t]);
-        } else {
-            for (int t = threadIdx.x / LINES; t < B.Kin; t += WG / LINES) dst[lpad(t)] = cd{0.0, 0.0};
+                dst[t] = cmul(io.load(c, B.j0 + t), B.pre[t]);
         }
         __syncthreads();
+        const cd *src = reinterpret_cast<const cd *>(lds);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const int t = tid + T * s;
-            v[s] = t < B.Kin ? lds[lpad(t)] : cd{0.0, 0.0};
+            v[s] = (t < B.Kin && line < nlines) ? src[t] : cd{0.0, 0.0};
         }
         __syncthreads();
     }
@@ -388,26 +417,28 @@ __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, Blue
             }
         }
     } else {
+        // Kout <= P/2 complex fit in the line viewed as complex.
+        cd *buf = reinterpret_cast<cd *>(lds);
+        line_sync<P>();
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const int q = tid + T * s - qlo;
-            if (q >= 0 && q < B.Kout) lds[lpad(q)] = cmul(cconj(v[s]), B.post[q]);
+            if (q >= 0 && q < B.Kout) buf[q] = cmul(cconj(v[s]), B.post[q]);
         }
         __syncthreads();
         if constexpr (IO::kStore == IO_STAGED) {
             const int ls = threadIdx.x % LINES, lns = line0 + ls;
             if (lns < nlines) {
                 const auto c = io.at(lns);
-                const cd *src = smem + ls * LW;
+                const cd *src = reinterpret_cast<const cd *>(smem_d + ls * LW);
                 for (int t = threadIdx.x / LINES; t < B.Kout; t += WG / LINES)
-                    io.store(c, B.k0 + t, src[lpad(t)]);
+                    io.store(c, B.k0 + t, src[t]);
             }
         } else {  // IO_PAIR: outputs k in [-K, K], K = -k0; pairs (k, -k)
             if (line < nlines) {
                 const auto c = io.at(line);
                 const int K = -B.k0;
-                for (int k = tid; k <= K; k += T)
-                    io.store_pair(c, k, lds[lpad(k + K)], lds[lpad(K - k)]);
+                for (int k = tid; k <= K; k += T) io.store_pair(c, k, buf[k + K], buf[K - k]);
             }
         }
     }
@@ -416,7 +447,7 @@ __global__ __launch_bounds__(R16<P>::WG) void k_blue_r16(IO io, int nlines, Blue
 template <int P, class IO>
 static hipError_t launch_r16(const IO &io, int nlines, const BluesteinDev &B, hipStream_t st) {
     using G = R16<P>;
-    const size_t lds = (size_t)G::LINES * G::LW * sizeof(cd);
+    const size_t lds = (size_t)G::LINES * G::LW * sizeof(double);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -555,38 +586,39 @@ struct InvGammaPackIO {
     }
 };
 
-// gamma DFT of the synthesis on the real part of line (a, b); even n kept.
+// gamma DFT of the synthesis on the real part of line (a, b).  The line is
+// real, so c_-n = conj c_n: only even n >= 0 are kept, V1[b][a][n/2].
 struct FwdGammaIO {
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *grid;
     cd *V1;
-    int L, h, Nm, Nep;
+    int L, h, Nm;
     struct Ctx {
         const cd *src;
-        cd *dst;  // V1[b][a][h]
+        cd *dst;  // V1[b][a][0]
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
-        return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * Nep + h};
+        return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * (h + 1)};
     }
     __device__ cd load(const Ctx &c, int g) const { return cd{c.src[g].x, 0.0}; }
     __device__ void store(const Ctx &c, int n, cd v) const {
-        if (n & 1) return;
+        if ((n & 1) || n < 0) return;
         c.dst[n / 2] = v;
     }
 };
 
 // gamma DFT of the synthesis, real parts of lines (2p, 2p+1) packed as
 // z = w1 + i w2; with Z_n its DFT, c1_n = (Z_n + conj Z_-n)/2 and
-// c2_n = (Z_n - conj Z_-n)/(2i), c_-n = conj c_n.
+// c2_n = (Z_n - conj Z_-n)/(2i); even n >= 0 kept.
 struct FwdGammaPackIO {
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
     const cd *grid;
     cd *V1;
-    int L, h, Nm, Nep, nreal;
+    int L, h, Nm, nreal;
     struct Ctx {
         const cd *s1, *s2;
-        cd *d1, *d2;  // V1[b][a][h] of both lines
+        cd *d1, *d2;  // V1[b][a][0] of both lines
         bool two;
     };
     __device__ Ctx at(int p) const {
@@ -595,7 +627,7 @@ struct FwdGammaPackIO {
         const int a1 = l1 / L, b1 = l1 % L;
         const int a2 = two ? l2 / L : a1, b2 = two ? l2 % L : b1;
         return Ctx{grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm,
-                   V1 + ((size_t)b1 * Nm + a1) * Nep + h, V1 + ((size_t)b2 * Nm + a2) * Nep + h,
+                   V1 + ((size_t)b1 * Nm + a1) * (h + 1), V1 + ((size_t)b2 * Nm + a2) * (h + 1),
                    two};
     }
     __device__ cd load(const Ctx &c, int g) const {
@@ -605,33 +637,35 @@ struct FwdGammaPackIO {
         if (n & 1) return;
         const cd czm = cconj(zmn);
         const cd s = cadd(zn, czm), d = csub(zn, czm);
-        const cd c1 = cd{0.5 * s.x, 0.5 * s.y};
-        c.d1[n / 2] = c1;
-        if (n) c.d1[-n / 2] = cconj(c1);
-        if (c.two) {
-            const cd c2 = cd{0.5 * d.y, -0.5 * d.x};
-            c.d2[n / 2] = c2;
-            if (n) c.d2[-n / 2] = cconj(c2);
-        }
+        c.d1[n / 2] = cd{0.5 * s.x, 0.5 * s.y};
+        if (c.two) c.d2[n / 2] = cd{0.5 * d.y, -0.5 * d.x};
     }
 };
 
-// alpha DFT of the synthesis: line (b, nn); outputs m in [0, L).
+// alpha DFT of the synthesis: line (b, k), k = n/2 >= 0, all m in (-L, L).
+// The grid is real, so the line of -n is the conjugate of the line of n and
+// its transform at m is the conjugate of this one's at -m:
+//   V2[b][m][h+k] = out(m),  V2[b][m][h-k] = conj out(-m),  m >= 0.
 struct FwdAlphaIO {
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *V1;
     cd *V2;
-    int L, Ne, Nm, Nep;
+    int L, h, Nm, Nep;
     struct Ctx {
         const cd *src;
-        cd *dst;
+        cd *pos, *neg;  // V2[b][0][h+k], V2[b][0][h-k]
+        bool mirror;
     };
     __device__ Ctx at(int line) const {
-        const int b = line / Ne, nn = line % Ne;
-        return Ctx{V1 + (size_t)b * Nm * Nep + nn, V2 + (size_t)b * L * Nep + nn};
+        const int b = line / (h + 1), k = line % (h + 1);
+        cd *base = V2 + (size_t)b * L * Nep + h;
+        return Ctx{V1 + (size_t)b * Nm * (h + 1) + k, base + k, base - k, k > 0};
     }
-    __device__ cd load(const Ctx &c, int a) const { return c.src[(size_t)a * Nep]; }
-    __device__ void store(const Ctx &c, int m, cd v) const { c.dst[(size_t)m * Nep] = v; }
+    __device__ cd load(const Ctx &c, int a) const { return c.src[(size_t)a * (h + 1)]; }
+    __device__ void store(const Ctx &c, int m, cd v) const {
+        if (m >= 0) c.pos[(size_t)m * Nep] = v;
+        if (m <= 0 && c.mirror) c.neg[(size_t)(-m) * Nep] = cconj(v);
+    }
 };
 
 struct ShtInvPhiIO {
@@ -683,16 +717,16 @@ hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd 
                             cd *V1, hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
-        FwdGammaPackIO io{grid, V1, g.L, g.h, g.Nm, g.Nep, nreal};
+        FwdGammaPackIO io{grid, V1, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
     }
-    FwdGammaIO io{grid, V1, g.L, g.h, g.Nm, g.Nep};
+    FwdGammaIO io{grid, V1, g.L, g.h, g.Nm};
     return run_bluestein(io, nreal, B, st);
 }
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
                             cd *V2, hipStream_t st) {
-    FwdAlphaIO io{V1, V2, g.L, g.Ne, g.Nm, g.Nep};
-    return run_bluestein(io, g.L * g.Ne, B, st);
+    FwdAlphaIO io{V1, V2, g.L, g.h, g.Nm, g.Nep};
+    return run_bluestein(io, g.L * (g.h + 1), B, st);
 }
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,
                               hipStream_t st) {
