@@ -39,6 +39,7 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kGroups = 32;  // m' groups of the synthesis contraction
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Stage {
@@ -277,7 +278,7 @@ size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int ngroups) {
         ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
         size_t cube = (size_t)g.L * g.L * g.Nep;
         size_t w2 = (size_t)g.L * g.Nm * (g.h + 1);
-        size_t v1 = (size_t)g.L * g.Nm * g.Nep;
+        size_t v1 = (size_t)g.L * g.Nm * (g.h + 1);
         size_t part = (size_t)ngroups * g.L * g.L;
         b0 = std::max({b0, cube, w2, v1});
         b1 = std::max({b1, cube, part});
@@ -305,7 +306,7 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
     P->J = J;
     P->lambda = p->lambda;
     P->Lphi = scaling_bandlimit(p->L, p->lambda, p->J0);
-    P->ngroups = 32;
+    P->ngroups = kGroups;
     const int L = p->L;
     std::vector<double> kap = host::kappa_table(L, p->lambda, p->J0, J);
     std::vector<double> phi = host::phi_table(L, p->lambda, p->J0);
@@ -526,7 +527,7 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
     if (rc) return rc;
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, 32);
+    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, kGroups);
     return CVL_OK;
 }
 
@@ -735,8 +736,7 @@ static CurveletBufs carve_curvelet(const Plan *P, void *ws, size_t ws_bytes) {
     size_t b0 = 0, b1 = 0;
     for (const ScaleRt &S : P->scales) {
         const ScaleGeom &g = S.g;
-        b0 = std::max({b0, (size_t)g.L * g.L * g.Nep, (size_t)g.L * g.Nm * (g.h + 1),
-                       (size_t)g.L * g.Nm * g.Nep});
+        b0 = std::max({b0, (size_t)g.L * g.L * g.Nep, (size_t)g.L * g.Nm * (g.h + 1)});
         b1 = std::max({b1, (size_t)g.L * g.L * g.Nep, (size_t)P->ngroups * g.L * g.L});
     }
     Carver cv{(char *)ws, ws_bytes};

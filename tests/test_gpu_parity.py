@@ -208,3 +208,66 @@ def test_c2_sampled_rows_and_round_trip(ctx):
     e = rel_l2(rec, fmap)
     say("  round trip rel L2 %.2e" % e)
     assert e < TOL
+
+
+def test_l512_sampled_rows_and_round_trip():
+    # L = 512 (the precision-path configuration's band-limit), FP64 path.
+    L, lam, J0 = 512, 2.0, 2
+    say("L=512: context + oracle plan")
+    c = api.Context(L, 0)
+    try:
+        plan = ocurv.Plan(L, lam, J0)
+        f = inputs.gaussian_real_flm(L, seed=3)
+        fmap = c.sht_inverse(dev(f), L)
+        scal, grids = c.curvelet_analysis(fmap, lam, J0)
+        for s, j in enumerate(plan.scales):
+            if plan.Lj[j] < L:
+                continue
+            say("L=512: oracle row 300 of scale %d" % j)
+            ref = ocurv.analysis_scale(plan, f, j, rows=[300])
+            g = grids[s][:, 300:301, :].cpu().numpy()
+            e = rel_l2(g, ref)
+            say("  scale %d row rel L2 %.2e" % (j, e))
+            assert e < TOL
+        rec = c.curvelet_synthesis(scal, grids, L, lam, J0)
+        e = (torch.linalg.norm(rec - fmap) / torch.linalg.norm(fmap)).item()
+        say("  L=512 round trip rel L2 %.2e" % e)
+        assert e < TOL
+        del grids, scal, rec
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+        torch.cuda.empty_cache()
+
+
+def test_l1024_round_trip():
+    # L = 1024 (the large configuration's band-limit), FP64 path: complex128
+    # grids of all 9 scales (147 GB) resident at once, exact reconstruction.
+    L, lam, J0 = 1024, 2.0, 2
+    free, total = torch.cuda.mem_get_info()
+    if free < 200 * 2**30:
+        pytest.skip("needs about 190 GB of free device memory")
+    say("L=1024: context")
+    c = api.Context(L, 0)
+    try:
+        f = inputs.gaussian_real_flm(L, seed=5)
+        fmap = c.sht_inverse(dev(f), L)
+        f2 = c.sht_forward(fmap)
+        e0 = rel_l2(host(f2), f)
+        say("  L=1024 SHT round trip rel L2 %.2e" % e0)
+        assert e0 < TOL
+        say("L=1024: analysis")
+        scal, grids = c.curvelet_analysis(fmap, lam, J0)
+        torch.cuda.synchronize()
+        for g in grids:
+            assert torch.count_nonzero(g.imag).item() == 0
+        say("L=1024: synthesis")
+        rec = c.curvelet_synthesis(scal, grids, L, lam, J0)
+        e = (torch.linalg.norm(rec - fmap) / torch.linalg.norm(fmap)).item()
+        say("  L=1024 round trip rel L2 %.2e" % e)
+        assert e < TOL
+        del grids, scal, rec
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+        torch.cuda.empty_cache()
