@@ -59,6 +59,11 @@ SIGNATURES = {
     "cvl_last_error": (ctypes.c_char_p, []),
 }
 
+# torch ships its own HIP runtime under the same soname as the system one; load
+# it first so that the library and torch share one runtime in the process
+# (two runtimes in one process do not see the same devices).
+import torch  # noqa: E402,F401
+
 if not os.path.exists(_LIB_PATH):
     raise ImportError("libcurvelet.so is not built: run `python -m paper_1511_05578_amd.build`")
 lib = ctypes.CDLL(_LIB_PATH)
