@@ -32,7 +32,13 @@
  *   before anything is enqueued; on error nothing is written to any output and
  *   cvl_last_error() (thread-local) describes the failure.  NaN/Inf inputs are
  *   not checked: they propagate to the outputs.
- * - Precision: every step is IEEE FP64 (round to nearest, FMA contraction).
+ * - Precision: by default every step is IEEE FP64 (round to nearest, FMA
+ *   contraction).  The curvelet calls also offer a reduced-precision path
+ *   (cvl_params.precision): complex64 coefficient grids, the two
+ *   l-contractions on the matrix cores in FP32 or in split bfloat16 ("BF16x3",
+ *   a*b = hi*hi + hi*lo + lo*hi) with FP32 accumulation, the beta stage and the
+ *   FFTs in FP32, while the Delta table, the SHTs, the scaling part and the
+ *   final accumulation of the synthesis over scales stay FP64.
  *   Results are bitwise run-to-run deterministic (no atomics, fixed orders).
  */
 #ifndef CURVELET_H
@@ -55,7 +61,13 @@ enum {
 /* Flags of cvl_params. */
 #define CVL_REAL 1u        /* real map (f_{l,-m} = (-1)^m conj f_lm); required */
 
+/* Precision of the curvelet calls (cvl_params.precision). */
+#define CVL_FP64 0         /* everything FP64, complex128 grids */
+#define CVL_FP32 1         /* FP32 MFMA contractions, FP32 FFT/beta, complex64 grids */
+#define CVL_BF16X3 2       /* split-bfloat16 MFMA contractions, otherwise as CVL_FP32 */
+
 typedef struct { double re, im; } cvl_c128;   /* layout of torch.complex128 */
+typedef struct { float re, im; } cvl_c64;     /* layout of torch.complex64 */
 
 typedef struct cvl_ctx cvl_ctx;
 
@@ -63,13 +75,15 @@ typedef struct cvl_ctx cvl_ctx;
  * N: azimuthal band-limit of the curvelets; curvelets have none, so N must be
  * 0 or L (each scale then uses N_j = L_j).  lambda > 1: dilation.  J0 >= 1:
  * lowest curvelet scale, J0 <= J where J = ceil(log_lambda L).  spin: must
- * be 0.  flags: CVL_REAL. */
+ * be 0.  precision: CVL_FP64, CVL_FP32 or CVL_BF16X3 (curvelet calls only;
+ * it selects the grid element type).  flags: CVL_REAL. */
 typedef struct {
     int L;
     int N;
     double lambda;
     int J0;
     int spin;
+    int precision;
     unsigned flags;
 } cvl_params;
 
@@ -132,13 +146,14 @@ int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid,
  * batch x L x (2L-1) doubles).  Outputs per map i:
  *   scal_maps + i * L_Phi * (2L_Phi-1): the scaling coefficients as a real MW
  *     map of band-limit L_Phi;
- *   grids[i * nJ + (j - J0)], nJ = J - J0 + 1: complex128 SO(3) grid
- *     W^(j)[a][b][g] of scale j, (2L_j-1) x L_j x (2L_j-1).  For a real map the
- *     curvelet coefficients are real: the imaginary parts are written as 0.
+ *   grids[i * nJ + (j - J0)], nJ = J - J0 + 1: SO(3) grid W^(j)[a][b][g] of
+ *     scale j, (2L_j-1) x L_j x (2L_j-1), of cvl_c128 (CVL_FP64) or cvl_c64
+ *     (CVL_FP32, CVL_BF16X3) elements.  For a real map the curvelet
+ *     coefficients are real: the imaginary parts are written as 0.
  * `grids` is a HOST array of batch * nJ device pointers. */
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
                           const double *maps, double *scal_maps,
-                          cvl_c128 *const *grids, void *ws, size_t ws_bytes,
+                          void *const *grids, void *ws, size_t ws_bytes,
                           void *stream);
 
 /* Curvelet synthesis (Sec. II-D-2, exact reconstruction): the inverse of
@@ -148,7 +163,7 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
  * parts are not used).  Writes `batch` real maps.  Same layouts as
  * cvl_curvelet_analysis. */
 int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
-                           const double *scal_maps, const cvl_c128 *const *grids,
+                           const double *scal_maps, const void *const *grids,
                            double *maps, void *ws, size_t ws_bytes, void *stream);
 
 /* Host copy of the kernel tables of `p` (no device work; usable without a

@@ -14,6 +14,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcurvele
 
 CVL_OK, CVL_EINVAL, CVL_ENOMEM, CVL_EDEVICE, CVL_EUNSUPPORTED = 0, -1, -2, -3, -4
 CVL_REAL = 1
+CVL_FP64, CVL_FP32, CVL_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": CVL_FP64, "fp32": CVL_FP32, "bf16x3": CVL_BF16X3}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_size_p = ctypes.POINTER(ctypes.c_size_t)
@@ -22,7 +24,8 @@ _c_double_p = ctypes.POINTER(ctypes.c_double)
 
 class CvlParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("N", ctypes.c_int), ("lambda_", ctypes.c_double),
-                ("J0", ctypes.c_int), ("spin", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("J0", ctypes.c_int), ("spin", ctypes.c_int), ("precision", ctypes.c_int),
+                ("flags", ctypes.c_uint)]
 
 
 # name -> (restype, argtypes)
@@ -84,8 +87,14 @@ def _check(rc):
         raise CvlError(rc, lib.cvl_last_error().decode())
 
 
-def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL):
-    return CvlParams(L, N, float(lam), J0, spin, flags)
+def _prec(precision):
+    if isinstance(precision, str):
+        return PRECISIONS[precision.lower()]
+    return int(precision)
+
+
+def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL, precision=CVL_FP64):
+    return CvlParams(L, N, float(lam), J0, spin, _prec(precision), flags)
 
 
 def num_scales(L, lam=2.0, J0=2):
@@ -219,16 +228,22 @@ class Context:
             out.append((2 * Lj - 1, Lj, 2 * Nj - 1))
         return out
 
-    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1):
+    def grid_dtype(self, precision=CVL_FP64):
+        t = self.torch
+        return t.complex128 if _prec(precision) == CVL_FP64 else t.complex64
+
+    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1, precision=CVL_FP64):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
         scal = t.empty((batch, Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
-        grids = [[t.empty(s, dtype=t.complex128, device=self.device)
+        dt = self.grid_dtype(precision)
+        grids = [[t.empty(s, dtype=dt, device=self.device)
                   for s in self.grid_shapes(L, lam, J0)] for _ in range(batch)]
         return scal, grids
 
-    def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None):
-        """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids)."""
+    def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None, precision=CVL_FP64):
+        """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids);
+        grids are complex128 (precision "fp64") or complex64 ("fp32", "bf16x3")."""
         t = self.torch
         single = maps.dim() == 2
         if single:
@@ -236,19 +251,23 @@ class Context:
         assert maps.dtype == t.float64 and maps.is_contiguous()
         batch, L = maps.shape[0], maps.shape[1]
         if out is None:
-            out = self.alloc_outputs(L, lam, J0, batch)
+            out = self.alloc_outputs(L, lam, J0, batch, precision)
         scal, grids = out
         flat = [g for per in grids for g in per]
+        dt = self.grid_dtype(precision)
+        for g in flat:
+            assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
         ws = self.workspace(workspace_bytes(L, lam, J0, batch))
-        _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(params(L, lam, J0)), batch,
+        p = params(L, lam, J0, precision=precision)
+        _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(p), batch,
                                          maps.data_ptr(), scal.data_ptr(), arr, ws.data_ptr(),
                                          ws.numel(), _stream(t)))
         if single:
             return scal[0], grids[0]
         return scal, grids
 
-    def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None):
+    def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None, precision=CVL_FP64):
         t = self.torch
         single = scal.dim() == 2
         if single:
@@ -258,11 +277,13 @@ class Context:
         if out is None:
             out = t.empty((batch, L, 2 * L - 1), dtype=t.float64, device=self.device)
         flat = [g for per in grids for g in per]
+        dt = self.grid_dtype(precision)
         for g in flat:
-            assert g.dtype == t.complex128 and g.is_contiguous()
+            assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
         ws = self.workspace(workspace_bytes(L, lam, J0, batch))
-        _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(params(L, lam, J0)), batch,
+        p = params(L, lam, J0, precision=precision)
+        _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(p), batch,
                                           scal.data_ptr(), arr, out.data_ptr(), ws.data_ptr(),
                                           ws.numel(), _stream(t)))
         return out[0] if single else out

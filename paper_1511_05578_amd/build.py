@@ -6,16 +6,19 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcurvelet.so")
 
-SOURCES = ["api.hip", "kernels_fft.hip", "kernels_linalg.hip", "host_tables.cpp"]
+SOURCES = ["api.hip", "kernels_fft.hip", "kernels_linalg.hip", "kernels_mixed.hip",
+           "host_tables.cpp"]
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,16 +33,29 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs + ["-lpthread"]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed (exit %d)" % r.returncode)
+        raise RuntimeError("hipcc failed (exit %d): %s" % (r.returncode, cmd[-1]))
+
+
+def build(verbose=False, jobs=None):
+    """Compile every source to an object (in parallel), then link the library."""
+    cc = hipcc()
+    inc = ["-I", os.path.join(ROOT, "include")]
+    jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
+    with tempfile.TemporaryDirectory(prefix="cvl_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[cc] + FLAGS + inc + ["-c", "-o", o, os.path.join(CSRC, s)]
+                for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(jobs) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run([cc] + FLAGS + ["-shared", "-o", tmp] + objs + ["-lpthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

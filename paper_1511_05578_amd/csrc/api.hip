@@ -89,6 +89,9 @@ struct DeviceArena {
 struct BetaTabs {  // parity-folded beta matrices of one band-limit
     double *Cinv = nullptr, *Sinv = nullptr, *Qp = nullptr, *Qs = nullptr;
 };
+struct BetaTabsF {  // the same, rounded to FP32 (reduced-precision path)
+    float *Cinv = nullptr, *Sinv = nullptr, *Qp = nullptr, *Qs = nullptr;
+};
 
 struct ScaleRt {
     int j;
@@ -96,6 +99,8 @@ struct ScaleRt {
     double *psi;  // [l][k]: Psi^(j)_{l,2k}
     BetaTabs beta;
     BluesteinDev inv_full, fwd_full, fwd_half;
+    BetaTabsF betaf;
+    BluesteinF inv_full_f, fwd_full_f;
 };
 
 struct Plan {
@@ -128,8 +133,11 @@ struct cvl_ctx {
     std::mutex mu;
     DeviceArena arena;
     std::map<int, cd *> tw;
+    std::map<int, cf *> tw_f;
     std::map<std::tuple<int, int, int, int, int, int, int>, BluesteinDev> blue;
+    std::map<std::tuple<int, int, int, int, int, int, int>, BluesteinF> blue_f;
     std::map<std::pair<int, int>, BetaTabs> beta;  // (L, factor id)
+    std::map<std::pair<int, int>, BetaTabsF> beta_f;
     std::map<std::tuple<int, double, int>, std::unique_ptr<Plan>> plans;
     std::map<int, std::unique_ptr<ShtRt>> sht;
     std::map<std::pair<int, int>, std::unique_ptr<GenRt>> gen;
@@ -224,6 +232,75 @@ int get_beta(cvl_ctx *c, int L, int fid, BetaTabs *out) {
     return CVL_OK;
 }
 
+// FP32 copies of the DFT tables (computed in extended precision, rounded once).
+int get_bluestein_f(cvl_ctx *c, int Nd, int Kin, int j0, int Kout, int k0, int sigma,
+                    BluesteinF *out) {
+    auto key = std::make_tuple(Nd, Kin, j0, Kout, k0, sigma, 0);
+    auto it = c->blue_f.find(key);
+    if (it != c->blue_f.end()) {
+        *out = it->second;
+        return CVL_OK;
+    }
+    const double scale = sigma < 0 ? 1.0 / Nd : 1.0;
+    host::Bluestein B = host::make_bluestein(Nd, Kin, j0, Kout, k0, sigma, scale);
+    if (B.P > 4096) return fail(CVL_EUNSUPPORTED, "DFT length %d needs FFT size %d > 4096", Nd, B.P);
+    if (B.P >= 256 && 2 * std::max(Kin, Kout) > B.P + B.P / 16)
+        return fail(CVL_EUNSUPPORTED, "DFT window (%d in, %d out) too wide for FFT size %d", Kin,
+                    Kout, B.P);
+    auto cv = [](const std::vector<std::complex<double>> &v) {
+        std::vector<cf> o(v.size());
+        for (size_t i = 0; i < v.size(); ++i) o[i] = cf{(float)v[i].real(), (float)v[i].imag()};
+        return o;
+    };
+    BluesteinF D{};
+    D.Nd = Nd;
+    D.P = B.P;
+    D.Kin = Kin;
+    D.j0 = j0;
+    D.Kout = Kout;
+    D.k0 = k0;
+    cf *pre, *post, *vhat;
+    int rc;
+    if ((rc = c->arena.upload(cv(B.pre), &pre))) return rc;
+    if ((rc = c->arena.upload(cv(B.post), &post))) return rc;
+    if ((rc = c->arena.upload(cv(B.vhat), &vhat))) return rc;
+    auto tw = c->tw_f.find(B.P);
+    if (tw == c->tw_f.end()) {
+        cf *d;
+        if ((rc = c->arena.upload(cv(host::twiddles(B.P)), &d))) return rc;
+        tw = c->tw_f.emplace(B.P, d).first;
+    }
+    D.pre = pre;
+    D.post = post;
+    D.vhat = vhat;
+    D.tw = tw->second;
+    c->blue_f[key] = D;
+    *out = D;
+    return CVL_OK;
+}
+
+int get_beta_f(cvl_ctx *c, int L, int fid, BetaTabsF *out) {
+    auto key = std::make_pair(L, fid);
+    auto it = c->beta_f.find(key);
+    if (it != c->beta_f.end()) {
+        *out = it->second;
+        return CVL_OK;
+    }
+    std::vector<double> C, S, Qp, Qs;
+    host::beta_inverse_mats(L, C, S);
+    host::beta_forward_mats(L, fid == 0 ? 4.0 * M_PI * M_PI : 2.0 * M_PI, Qp, Qs);
+    auto cv = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
+    BetaTabsF T;
+    int rc;
+    if ((rc = c->arena.upload(cv(C), &T.Cinv))) return rc;
+    if ((rc = c->arena.upload(cv(S), &T.Sinv))) return rc;
+    if ((rc = c->arena.upload(cv(Qp), &T.Qp))) return rc;
+    if ((rc = c->arena.upload(cv(Qs), &T.Qs))) return rc;
+    c->beta_f[key] = T;
+    *out = T;
+    return CVL_OK;
+}
+
 int num_scales(int L, double lam) {
     int J = 0;
     double p = 1.0;
@@ -256,6 +333,9 @@ int check_params(const cvl_params *p, int *J) {
     if (p->spin != 0) return fail(CVL_EUNSUPPORTED, "spin=%d: only spin 0 is implemented", p->spin);
     if (!(p->flags & CVL_REAL))
         return fail(CVL_EUNSUPPORTED, "complex maps are not implemented: set CVL_REAL");
+    if (p->precision != CVL_FP64 && p->precision != CVL_FP32 && p->precision != CVL_BF16X3)
+        return fail(CVL_EINVAL, "precision=%d is not CVL_FP64, CVL_FP32 or CVL_BF16X3",
+                    p->precision);
     if (J) *J = JJ;
     return CVL_OK;
 }
@@ -337,6 +417,9 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
         if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full))) return rc;
         if ((rc = get_bluestein(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full))) return rc;
         if ((rc = get_bluestein(c, Nm, Nm, 0, Lj, 0, -1, &S.fwd_half))) return rc;
+        if ((rc = get_beta_f(c, Lj, 0, &S.betaf))) return rc;
+        if ((rc = get_bluestein_f(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full_f))) return rc;
+        if ((rc = get_bluestein_f(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full_f))) return rc;
         P->scales.push_back(S);
     }
     std::vector<double> pf(P->Lphi);
@@ -753,7 +836,7 @@ static CurveletBufs carve_curvelet(const Plan *P, void *ws, size_t ws_bytes) {
 }
 
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *maps,
-                          double *scal_maps, cvl_c128 *const *grids, void *ws, size_t ws_bytes,
+                          double *scal_maps, void *const *grids, void *ws, size_t ws_bytes,
                           void *stream) {
     g_err.clear();
     Plan *P;
@@ -775,6 +858,17 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         for (int s = 0; s < nJ; ++s) {
             const ScaleRt &S = P->scales[s];
             const ScaleGeom &g = S.g;
+            if (p->precision != CVL_FP64) {
+                cf *grid = (cf *)grids[(size_t)bi * nJ + s];
+                cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
+                LAUNCH(ST_CONTRACT_INV, launch_contract_inv_mx(p->precision, g, L, ctx->delta,
+                                                               B.fpad, S.psi, b0, st));
+                LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep,
+                                                         S.betaf.Cinv, S.betaf.Sinv, b0, b1, st));
+                LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
+                LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
+                continue;
+            }
             cd *grid = (cd *)grids[(size_t)bi * nJ + s];
             LAUNCH(ST_CONTRACT_INV,
                    launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, B.b0, st));
@@ -788,7 +882,7 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
 }
 
 int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *scal_maps,
-                           const cvl_c128 *const *grids, double *maps, void *ws, size_t ws_bytes,
+                           const void *const *grids, double *maps, void *ws, size_t ws_bytes,
                            void *stream) {
     g_err.clear();
     Plan *P;
@@ -808,6 +902,19 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
         for (int s = 0; s < nJ; ++s) {
             const ScaleRt &S = P->scales[s];
             const ScaleGeom &g = S.g;
+            if (p->precision != CVL_FP64) {
+                const cf *grid = (const cf *)grids[(size_t)bi * nJ + s];
+                cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
+                LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full_f, grid, b0, st));
+                LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
+                LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep,
+                                                         S.betaf.Qp, S.betaf.Qs, b1, b0, st));
+                LAUNCH(ST_CONTRACT_FWD,
+                       launch_contract_fwd_mx(p->precision, g, L, ctx->delta, b0, S.psi, b1,
+                                              P->ngroups, st));
+                LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, P->ngroups, B.facc, st));
+                continue;
+            }
             const cd *grid = (const cd *)grids[(size_t)bi * nJ + s];
             LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, B.b0, st));
             LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, B.b0, B.b1, st));

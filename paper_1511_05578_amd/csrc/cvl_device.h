@@ -17,26 +17,59 @@ __host__ __device__ __forceinline__ cd cmul(cd a, cd b) {
 }
 __host__ __device__ __forceinline__ cd cconj(cd a) { return cd{a.x, -a.y}; }
 __host__ __device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.x * s, a.y * s}; }
+// Single-precision complex (the reduced-precision path: complex64 grids and
+// cubes).  The same operations as cd, so templated code works on both.
+struct __align__(8) cf {
+    float x, y;
+};
+__host__ __device__ __forceinline__ cf cadd(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
+__host__ __device__ __forceinline__ cf csub(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
+__host__ __device__ __forceinline__ cf cmul(cf a, cf b) {
+    return cf{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ __forceinline__ cf cconj(cf a) { return cf{a.x, -a.y}; }
+__host__ __device__ __forceinline__ cf cscale(cf a, float s) { return cf{a.x * s, a.y * s}; }
+
 // multiply by i^q (q taken mod 4, may be negative)
-__host__ __device__ __forceinline__ cd ipow(cd a, int q) {
+template <class C>
+__host__ __device__ __forceinline__ C ipow(C a, int q) {
     switch (q & 3) {
         case 0: return a;
-        case 1: return cd{-a.y, a.x};
-        case 2: return cd{-a.x, -a.y};
-        default: return cd{a.y, -a.x};
+        case 1: return C{-a.y, a.x};
+        case 2: return C{-a.x, -a.y};
+        default: return C{a.y, -a.x};
     }
 }
+
+// Real component type of a complex type.
+template <class C> struct RealOf;
+template <> struct RealOf<cd> { using T = double; };
+template <> struct RealOf<cf> { using T = float; };
+template <class C> using real_t = typename RealOf<C>::T;
+
+// Complex constant of type C from double components.
+template <class C>
+__host__ __device__ __forceinline__ C cmk(double x, double y) {
+    return C{(real_t<C>)x, (real_t<C>)y};
+}
+
+// Precision of a curvelet call (values of cvl_params.precision).
+enum Precision { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
 // Offset of block l in the quarter Delta table: sum_{k<l} (k+1)^2.
 __host__ __device__ __forceinline__ int64_t delta_off(int l) {
     return (int64_t)l * (l + 1) * (2 * l + 1) / 6;
 }
 
-// Device tables of one Bluestein DFT configuration (see host::Bluestein).
-struct BluesteinDev {
+// Device tables of one Bluestein DFT configuration (see host::Bluestein), in
+// the working precision of the transform.
+template <class C>
+struct BlueT {
     int Nd, P, Kin, j0, Kout, k0;
-    const cd *pre, *post, *vhat, *tw;
+    const C *pre, *post, *vhat, *tw;
 };
+using BluesteinDev = BlueT<cd>;
+using BluesteinF = BlueT<cf>;
 
 // Geometry of one curvelet scale (or one SHT / Wigner band-limit).
 struct ScaleGeom {
@@ -61,6 +94,15 @@ hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd 
                             cd *V1, hipStream_t st);
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
                             cd *V2, hipStream_t st);
+// The same four stages in single precision (complex64 cubes and grids).
+hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1, cf *W2,
+                            hipStream_t st);
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2, cf *grid,
+                            hipStream_t st);
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid, cf *V1,
+                            hipStream_t st);
+hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1, cf *V2,
+                            hipStream_t st);
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,
                               hipStream_t st);
 hipError_t launch_sht_fwd_phi(int L, const BluesteinDev &B, const double *map, cd *F1,
@@ -83,6 +125,17 @@ hipError_t launch_gen_fwd_alpha(int L, int N, const BluesteinDev &B, const cd *V
 hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0,
                             const double *Aeven, const double *Aodd, const cd *in,
                             cd *out, hipStream_t st);
+
+// Reduced-precision dense stages (FP32 data; see kernels_mixed.hip).
+hipError_t launch_beta_gemm_f32(int M, int K, int ncols, int Nep, const float *Aeven,
+                                const float *Aodd, const cf *in, cf *out, hipStream_t st);
+hipError_t launch_contract_inv_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
+                                  const cd *fpad, const double *psi, cf *X, hipStream_t st);
+hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
+                                  const cf *Z, const double *psi, cf *part, int ngroups,
+                                  hipStream_t st);
+hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int ngroups,
+                                cd *facc, hipStream_t st);
 
 // Curvelet contractions.
 hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta,

@@ -26,13 +26,13 @@ enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
 // In-place Stockham FFT of one LDS line (forward, tw[x] = e^{-2 pi i x / P}).
 // Radix-4 stages first, then one radix-2 stage when log2 P is odd.  Every
 // thread of the work-group must call it (it synchronises the work-group).
-template <int P, int TPL>
-__device__ __forceinline__ void fft_lds(cd *buf, const cd *__restrict__ tw, int lane) {
+template <int P, int TPL, class C>
+__device__ __forceinline__ void fft_lds(C *buf, const C *__restrict__ tw, int lane) {
     constexpr int Q = P / 4;
     constexpr int B4 = (Q + TPL - 1) / TPL;
     int Ns = 1;
     for (; Ns * 4 <= P; Ns *= 4) {
-        cd v[B4][4];
+        C v[B4][4];
         const int step = P / (4 * Ns);
 #pragma unroll
         for (int i = 0; i < B4; ++i) {
@@ -51,9 +51,9 @@ __device__ __forceinline__ void fft_lds(cd *buf, const cd *__restrict__ tw, int 
             const int j = lane + i * TPL;
             if (j < Q) {
                 const int k = j & (Ns - 1);
-                const cd a0 = cadd(v[i][0], v[i][2]), a1 = csub(v[i][0], v[i][2]);
-                const cd b0 = cadd(v[i][1], v[i][3]), b1 = csub(v[i][1], v[i][3]);
-                const cd mib1 = cd{b1.y, -b1.x};  // -i * b1
+                const C a0 = cadd(v[i][0], v[i][2]), a1 = csub(v[i][0], v[i][2]);
+                const C b0 = cadd(v[i][1], v[i][3]), b1 = csub(v[i][1], v[i][3]);
+                const C mib1 = C{b1.y, -b1.x};  // -i * b1
                 const int d = (j / Ns) * Ns * 4 + k;
                 buf[d] = cadd(a0, b0);
                 buf[d + Ns] = cadd(a1, mib1);
@@ -66,7 +66,7 @@ __device__ __forceinline__ void fft_lds(cd *buf, const cd *__restrict__ tw, int 
     if (Ns < P) {  // radix-2, Ns = P/2
         constexpr int H = P / 2;
         constexpr int B2 = (H + TPL - 1) / TPL;
-        cd v[B2][2];
+        C v[B2][2];
 #pragma unroll
         for (int i = 0; i < B2; ++i) {
             const int j = lane + i * TPL;
@@ -94,9 +94,11 @@ struct LinesFor {
 };
 
 template <int P, int LINES, class IO>
-__global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinDev B) {
+__global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BlueT<typename IO::C> B) {
+    using C = typename IO::C;
     constexpr bool IN_IL = IO::kLoad == IO_STAGED, OUT_IL = IO::kStore == IO_STAGED;
-    extern __shared__ cd smem[];
+    extern __shared__ __align__(16) char smem_raw[];
+    C *smem = reinterpret_cast<C *>(smem_raw);
     constexpr int TPL = 256 / LINES;
     const int tid = threadIdx.x;
     const int li = tid / TPL, lane = tid % TPL;
@@ -111,18 +113,18 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinD
             t = idx % P;
         }
         const int line = line0 + l;
-        cd v = cd{0.0, 0.0};
+        C v = C{0, 0};
         if (t < B.Kin && line < nlines) v = cmul(io.load(io.at(line), B.j0 + t), B.pre[t]);
         smem[l * P + t] = v;
     }
     __syncthreads();
-    cd *buf = smem + li * P;
+    C *buf = smem + li * P;
     fft_lds<P, TPL>(buf, B.tw, lane);
     for (int t = lane; t < P; t += TPL) buf[t] = cconj(cmul(buf[t], B.vhat[t]));
     __syncthreads();
     fft_lds<P, TPL>(buf, B.tw, lane);
     for (int t = lane; t < B.Kout; t += TPL) {
-        const cd c = cconj(buf[t + B.Kin - 1]);
+        const C c = cconj(buf[t + B.Kin - 1]);
         buf[t + B.Kin - 1] = cmul(c, B.post[t]);
     }
     __syncthreads();
@@ -161,18 +163,21 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BluesteinD
 // layout the next FFT's first pass reads, the chirp-spectrum multiply and the
 // second FFT need no exchange in between.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ cd mul_mi(cd a) { return cd{a.y, -a.x}; }  // -i * a
+template <class C>
+__device__ __forceinline__ C mul_mi(C a) { return C{a.y, -a.x}; }  // -i * a
 
-__device__ __forceinline__ void bfly4(cd &x0, cd &x1, cd &x2, cd &x3) {
-    const cd a0 = cadd(x0, x2), a1 = csub(x0, x2);
-    const cd b0 = cadd(x1, x3), b1 = mul_mi(csub(x1, x3));
+template <class C>
+__device__ __forceinline__ void bfly4(C &x0, C &x1, C &x2, C &x3) {
+    const C a0 = cadd(x0, x2), a1 = csub(x0, x2);
+    const C b0 = cadd(x1, x3), b1 = mul_mi(csub(x1, x3));
     x0 = cadd(a0, b0);
     x2 = csub(a0, b0);
     x1 = cadd(a1, b1);
     x3 = csub(a1, b1);
 }
-__device__ __forceinline__ void bfly2(cd &x0, cd &x1) {
-    const cd a = cadd(x0, x1);
+template <class C>
+__device__ __forceinline__ void bfly2(C &x0, C &x1) {
+    const C a = cadd(x0, x1);
     x1 = csub(x0, x1);
     x0 = a;
 }
@@ -183,21 +188,22 @@ __device__ __forceinline__ void bfly2(cd &x0, cd &x1) {
 #define CVL_R2 0.70710678118654752440
 
 // 16-point forward DFT, natural order in and out (4 x 4 split).
-__device__ __forceinline__ void dft16(cd v[16]) {
+template <class C>
+__device__ __forceinline__ void dft16(C v[16]) {
 #pragma unroll
     for (int r0 = 0; r0 < 4; ++r0) bfly4(v[r0], v[r0 + 4], v[r0 + 8], v[r0 + 12]);
-    v[5] = cmul(v[5], cd{CVL_C1, -CVL_S1});
-    v[9] = cmul(v[9], cd{CVL_R2, -CVL_R2});
-    v[13] = cmul(v[13], cd{CVL_S1, -CVL_C1});
-    v[6] = cmul(v[6], cd{CVL_R2, -CVL_R2});
+    v[5] = cmul(v[5], cmk<C>(CVL_C1, -CVL_S1));
+    v[9] = cmul(v[9], cmk<C>(CVL_R2, -CVL_R2));
+    v[13] = cmul(v[13], cmk<C>(CVL_S1, -CVL_C1));
+    v[6] = cmul(v[6], cmk<C>(CVL_R2, -CVL_R2));
     v[10] = mul_mi(v[10]);
-    v[14] = cmul(v[14], cd{-CVL_R2, -CVL_R2});
-    v[7] = cmul(v[7], cd{CVL_S1, -CVL_C1});
-    v[11] = cmul(v[11], cd{-CVL_R2, -CVL_R2});
-    v[15] = cmul(v[15], cd{-CVL_C1, CVL_S1});
+    v[14] = cmul(v[14], cmk<C>(-CVL_R2, -CVL_R2));
+    v[7] = cmul(v[7], cmk<C>(CVL_S1, -CVL_C1));
+    v[11] = cmul(v[11], cmk<C>(-CVL_R2, -CVL_R2));
+    v[15] = cmul(v[15], cmk<C>(-CVL_C1, CVL_S1));
 #pragma unroll
     for (int k0 = 0; k0 < 4; ++k0) bfly4(v[4 * k0], v[4 * k0 + 1], v[4 * k0 + 2], v[4 * k0 + 3]);
-    cd t[16];
+    C t[16];
 #pragma unroll
     for (int k0 = 0; k0 < 4; ++k0)
 #pragma unroll
@@ -207,15 +213,16 @@ __device__ __forceinline__ void dft16(cd v[16]) {
 }
 
 // 8-point forward DFT (4 x 2 split), natural order.
-__device__ __forceinline__ void dft8(cd *v) {
+template <class C>
+__device__ __forceinline__ void dft8(C *v) {
     bfly4(v[0], v[2], v[4], v[6]);
     bfly4(v[1], v[3], v[5], v[7]);
-    v[3] = cmul(v[3], cd{CVL_R2, -CVL_R2});
+    v[3] = cmul(v[3], cmk<C>(CVL_R2, -CVL_R2));
     v[5] = mul_mi(v[5]);
-    v[7] = cmul(v[7], cd{-CVL_R2, -CVL_R2});
+    v[7] = cmul(v[7], cmk<C>(-CVL_R2, -CVL_R2));
 #pragma unroll
     for (int k0 = 0; k0 < 4; ++k0) bfly2(v[2 * k0], v[2 * k0 + 1]);
-    cd t[8];
+    C t[8];
 #pragma unroll
     for (int k0 = 0; k0 < 4; ++k0) {
         t[k0] = v[2 * k0];
@@ -225,8 +232,8 @@ __device__ __forceinline__ void dft8(cd *v) {
     for (int k = 0; k < 8; ++k) v[k] = t[k];
 }
 
-template <int R>
-__device__ __forceinline__ void dft_small(cd *v) {
+template <int R, class C>
+__device__ __forceinline__ void dft_small(C *v) {
     if constexpr (R == 2) {
         bfly2(v[0], v[1]);
     } else if constexpr (R == 4) {
@@ -262,15 +269,15 @@ struct R16 {
     static constexpr int WG = T < 128 ? 128 : T;     // threads per work-group
     static constexpr int LINES = WG / T;             // lines per work-group
     static constexpr int RC = P / 256;               // radix of the last pass (1: none)
-    static constexpr int LW = P + P / 16 + 4;        // doubles per LDS line (padded)
+    static constexpr int LW = P + P / 16 + 4;        // reals per LDS line (padded)
 };
 
 // Moves one line between passes through LDS, one real component at a time
-// (the LDS line holds P doubles): element wpos(k) leaves v[k], element rpos(r)
+// (the LDS line holds P reals): element wpos(k) leaves v[k], element rpos(r)
 // arrives in v[r].
-template <int P, class WP, class RP>
-__device__ __forceinline__ void exchange(cd v[16], double *lds, WP wpos, RP rpos) {
-    double nx[16];
+template <int P, class C, class WP, class RP>
+__device__ __forceinline__ void exchange(C v[16], real_t<C> *lds, WP wpos, RP rpos) {
+    real_t<C> nx[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) lds[lpad(wpos(k))] = v[k].x;
     line_sync<P>();
@@ -281,14 +288,15 @@ __device__ __forceinline__ void exchange(cd v[16], double *lds, WP wpos, RP rpos
     for (int k = 0; k < 16; ++k) lds[lpad(wpos(k))] = v[k].y;
     line_sync<P>();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cd{nx[r], lds[lpad(rpos(r))]};
+    for (int r = 0; r < 16; ++r) v[r] = C{nx[r], lds[lpad(rpos(r))]};
     line_sync<P>();
 }
 
 // v[r] *= w^r for r = 1..15 (w^r from w by a product tree, used as produced).
-__device__ __forceinline__ void twiddle16(cd v[16], cd w1) {
-    const cd w2 = cmul(w1, w1), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
-    const cd w3 = cmul(w2, w1);
+template <class C>
+__device__ __forceinline__ void twiddle16(C v[16], C w1) {
+    const C w2 = cmul(w1, w1), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+    const C w3 = cmul(w2, w1);
     v[1] = cmul(v[1], w1);
     v[2] = cmul(v[2], w2);
     v[3] = cmul(v[3], w3);
@@ -300,7 +308,7 @@ __device__ __forceinline__ void twiddle16(cd v[16], cd w1) {
     v[9] = cmul(v[9], cmul(w8, w1));
     v[10] = cmul(v[10], cmul(w8, w2));
     v[11] = cmul(v[11], cmul(w8, w3));
-    const cd w12 = cmul(w8, w4);
+    const C w12 = cmul(w8, w4);
     v[12] = cmul(v[12], w12);
     v[13] = cmul(v[13], cmul(w12, w1));
     v[14] = cmul(v[14], cmul(w12, w2));
@@ -308,8 +316,9 @@ __device__ __forceinline__ void twiddle16(cd v[16], cd w1) {
 }
 
 // Forward FFT of one line; v[s] = element tid + T*s on entry and on exit.
-template <int P>
-__device__ __forceinline__ void fft_r16(cd v[16], double *lds, const cd *__restrict__ tw, int tid) {
+template <int P, class C>
+__device__ __forceinline__ void fft_r16(C v[16], real_t<C> *lds, const C *__restrict__ tw,
+                                        int tid) {
     constexpr int T = R16<P>::T, RC = R16<P>::RC;
     dft16(v);  // pass Ns = 1: butterfly tid, no twiddles
     exchange<P>(v, lds, [&](int k) { return 16 * tid + k; }, [&](int r) { return tid + T * r; });
@@ -324,17 +333,17 @@ __device__ __forceinline__ void fft_r16(cd v[16], double *lds, const cd *__restr
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int j = tid + T * q;
-            cd *u = &v[q * RC];
-            const cd w1 = tw[j];
+            C *u = &v[q * RC];
+            const C w1 = tw[j];
             if constexpr (RC == 2) {
                 u[1] = cmul(u[1], w1);
             } else if constexpr (RC == 4) {
-                const cd w2 = cmul(w1, w1);
+                const C w2 = cmul(w1, w1);
                 u[1] = cmul(u[1], w1);
                 u[2] = cmul(u[2], w2);
                 u[3] = cmul(u[3], cmul(w2, w1));
             } else if constexpr (RC == 8) {
-                const cd w2 = cmul(w1, w1), w4 = cmul(w2, w2), w3 = cmul(w2, w1);
+                const C w2 = cmul(w1, w1), w4 = cmul(w2, w2), w3 = cmul(w2, w1);
                 u[1] = cmul(u[1], w1);
                 u[2] = cmul(u[2], w2);
                 u[3] = cmul(u[3], w3);
@@ -348,7 +357,7 @@ __device__ __forceinline__ void fft_r16(cd v[16], double *lds, const cd *__restr
             dft_small<RC>(u);
         }
         // element j + 256 r = tid + T (q + r NB): reorder to v[q + r NB]
-        cd t[16];
+        C t[16];
 #pragma unroll
         for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -361,43 +370,46 @@ __device__ __forceinline__ void fft_r16(cd v[16], double *lds, const cd *__restr
 // Three waves per SIMD for lines that fit one wavefront (the kernel is latency
 // bound; the register cap costs at most a few spilled dwords).
 template <int P, class IO>
-__global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(IO io, int nlines,
-                                                                             BluesteinDev B) {
+__global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
+    IO io, int nlines, BlueT<typename IO::C> B) {
+    using C = typename IO::C;
+    using R = real_t<C>;
     constexpr int T = R16<P>::T, WG = R16<P>::WG, LINES = R16<P>::LINES, LW = R16<P>::LW;
-    extern __shared__ double smem_d[];
+    extern __shared__ __align__(16) char smem_raw[];
+    R *smem_d = reinterpret_cast<R *>(smem_raw);
     const int li = threadIdx.x / T, tid = threadIdx.x % T;
     const int line0 = blockIdx.x * LINES;
     const int line = line0 + li;
-    double *lds = smem_d + li * LW;
-    cd v[16];
+    R *lds = smem_d + li * LW;
+    C v[16];
     if constexpr (IO::kLoad == IO_DIRECT) {
         if (line < nlines) {
             const auto c = io.at(line);
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const int t = tid + T * s;
-                v[s] = t < B.Kin ? cmul(io.load(c, B.j0 + t), B.pre[t]) : cd{0.0, 0.0};
+                v[s] = t < B.Kin ? cmul(io.load(c, B.j0 + t), B.pre[t]) : C{0, 0};
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 16; ++s) v[s] = cd{0.0, 0.0};
+            for (int s = 0; s < 16; ++s) v[s] = C{0, 0};
         }
     } else {
         // Staged through the LDS lines viewed as complex (Kin <= P/2 fits).
         // WG is a multiple of LINES, so each thread always stages the same line.
         const int ls = threadIdx.x % LINES, lns = line0 + ls;
-        cd *dst = reinterpret_cast<cd *>(smem_d + ls * LW);
+        C *dst = reinterpret_cast<C *>(smem_d + ls * LW);
         if (lns < nlines) {
             const auto c = io.at(lns);
             for (int t = threadIdx.x / LINES; t < B.Kin; t += WG / LINES)
                 dst[t] = cmul(io.load(c, B.j0 + t), B.pre[t]);
         }
         __syncthreads();
-        const cd *src = reinterpret_cast<const cd *>(lds);
+        const C *src = reinterpret_cast<const C *>(lds);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const int t = tid + T * s;
-            v[s] = (t < B.Kin && line < nlines) ? src[t] : cd{0.0, 0.0};
+            v[s] = (t < B.Kin && line < nlines) ? src[t] : C{0, 0};
         }
         __syncthreads();
     }
@@ -418,7 +430,7 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(IO
         }
     } else {
         // Kout <= P/2 complex fit in the line viewed as complex.
-        cd *buf = reinterpret_cast<cd *>(lds);
+        C *buf = reinterpret_cast<C *>(lds);
         line_sync<P>();
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
@@ -430,7 +442,7 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(IO
             const int ls = threadIdx.x % LINES, lns = line0 + ls;
             if (lns < nlines) {
                 const auto c = io.at(lns);
-                const cd *src = reinterpret_cast<const cd *>(smem_d + ls * LW);
+                const C *src = reinterpret_cast<const C *>(smem_d + ls * LW);
                 for (int t = threadIdx.x / LINES; t < B.Kout; t += WG / LINES)
                     io.store(c, B.k0 + t, src[t]);
             }
@@ -445,9 +457,10 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(IO
 }
 
 template <int P, class IO>
-static hipError_t launch_r16(const IO &io, int nlines, const BluesteinDev &B, hipStream_t st) {
+static hipError_t launch_r16(const IO &io, int nlines, const BlueT<typename IO::C> &B,
+                             hipStream_t st) {
     using G = R16<P>;
-    const size_t lds = (size_t)G::LINES * G::LW * sizeof(double);
+    const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -463,7 +476,7 @@ static hipError_t launch_r16(const IO &io, int nlines, const BluesteinDev &B, hi
 }
 
 template <class IO>
-static hipError_t run_bluestein_r16(const IO &io, int nlines, const BluesteinDev &B,
+static hipError_t run_bluestein_r16(const IO &io, int nlines, const BlueT<typename IO::C> &B,
                                     hipStream_t st) {
     if (nlines <= 0) return hipSuccess;
     switch (B.P) {
@@ -477,14 +490,15 @@ static hipError_t run_bluestein_r16(const IO &io, int nlines, const BluesteinDev
 }
 
 template <class IO>
-static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B, hipStream_t st) {
+static hipError_t run_bluestein(const IO &io, int nlines, const BlueT<typename IO::C> &B,
+                                hipStream_t st) {
     if (nlines <= 0) return hipSuccess;
 #define CVL_BLUE_CASE(PP)                                                              \
     case PP: {                                                                          \
         constexpr int LN = LinesFor<PP>::v;                                             \
         const int grid = (nlines + LN - 1) / LN;                                        \
         hipLaunchKernelGGL((k_bluestein<PP, LN, IO>), dim3(grid), dim3(256),            \
-                           LN * PP * sizeof(cd), st, io, nlines, B);                    \
+                           LN * PP * sizeof(typename IO::C), st, io, nlines, B);        \
         return hipGetLastError();                                                       \
     }
     switch (B.P) {
@@ -507,58 +521,64 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BluesteinDev &B,
 
 // alpha DFT of the analysis: line (b, k >= 0); input over m in (-L, L) with the
 // reality condition W1(b, -m, -n) = conj W1(b, m, n); output a in [0, 2L-1).
+template <class C_>
 struct InvAlphaIO {
+    using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    const cd *W1;
-    cd *W2;
+    const C *W1;
+    C *W2;
     int L, h, Nep, Nm;
     struct Ctx {
-        const cd *pos, *neg;  // W1[b][m][h+k], W1[b][m][h-k] at m = 0
-        cd *out;              // W2[b][a][k] at a = 0
+        const C *pos, *neg;  // W1[b][m][h+k], W1[b][m][h-k] at m = 0
+        C *out;              // W2[b][a][k] at a = 0
     };
     __device__ Ctx at(int line) const {
         const int b = line / (h + 1), k = line % (h + 1);
-        const cd *base = W1 + (size_t)b * L * Nep + h;
+        const C *base = W1 + (size_t)b * L * Nep + h;
         return Ctx{base + k, base - k, W2 + (size_t)b * Nm * (h + 1) + k};
     }
-    __device__ cd load(const Ctx &c, int m) const {
+    __device__ C load(const Ctx &c, int m) const {
         return m >= 0 ? c.pos[(size_t)m * Nep] : cconj(c.neg[(size_t)(-m) * Nep]);
     }
-    __device__ void store(const Ctx &c, int a, cd v) const { c.out[(size_t)a * (h + 1)] = v; }
+    __device__ void store(const Ctx &c, int a, C v) const { c.out[(size_t)a * (h + 1)] = v; }
 };
 
 // gamma DFT of the analysis, one real line (a, b) per transform; written as (re, 0).
 // Coefficients: even n from W2 (n < 0 by conjugation), odd n zero.
+template <class C_>
 struct InvGammaIO {
+    using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    const cd *W2;
-    cd *grid;
+    const C *W2;
+    C *grid;
     int L, h, Nm;
     struct Ctx {
-        const cd *src;
-        cd *dst;
+        const C *src;
+        C *dst;
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
         return Ctx{W2 + ((size_t)b * Nm + a) * (h + 1), grid + (size_t)line * Nm};
     }
-    __device__ cd load(const Ctx &c, int n) const {
-        if (n & 1) return cd{0.0, 0.0};
+    __device__ C load(const Ctx &c, int n) const {
+        if (n & 1) return C{0, 0};
         return n >= 0 ? c.src[n / 2] : cconj(c.src[-n / 2]);
     }
-    __device__ void store(const Ctx &c, int g, cd v) const { c.dst[g] = cd{v.x, 0.0}; }
+    __device__ void store(const Ctx &c, int g, C v) const { c.dst[g] = C{v.x, 0}; }
 };
 
 // gamma DFT of the analysis, two real lines (2p, 2p+1) per complex transform:
 // z_n = c1_n + i c2_n; line 2p is the real, line 2p+1 the imaginary part.
+template <class C_>
 struct InvGammaPackIO {
+    using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    const cd *W2;
-    cd *grid;
+    const C *W2;
+    C *grid;
     int L, h, Nm, nreal;
     struct Ctx {
-        const cd *s1, *s2;
-        cd *d1, *d2;
+        const C *s1, *s2;
+        C *d1, *d2;
         bool two;
     };
     __device__ Ctx at(int p) const {
@@ -569,40 +589,42 @@ struct InvGammaPackIO {
         return Ctx{W2 + ((size_t)b1 * Nm + a1) * (h + 1), W2 + ((size_t)b2 * Nm + a2) * (h + 1),
                    grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm, two};
     }
-    __device__ cd load(const Ctx &c, int n) const {
-        if (n & 1) return cd{0.0, 0.0};
+    __device__ C load(const Ctx &c, int n) const {
+        if (n & 1) return C{0, 0};
         const int k = n >= 0 ? n / 2 : -n / 2;
-        cd c1 = c.s1[k];
-        cd c2 = c.two ? c.s2[k] : cd{0.0, 0.0};
+        C c1 = c.s1[k];
+        C c2 = c.two ? c.s2[k] : C{0, 0};
         if (n < 0) {
             c1 = cconj(c1);
             c2 = cconj(c2);
         }
-        return cd{c1.x - c2.y, c1.y + c2.x};
+        return C{c1.x - c2.y, c1.y + c2.x};
     }
-    __device__ void store(const Ctx &c, int g, cd v) const {
-        c.d1[g] = cd{v.x, 0.0};
-        if (c.two) c.d2[g] = cd{v.y, 0.0};
+    __device__ void store(const Ctx &c, int g, C v) const {
+        c.d1[g] = C{v.x, 0};
+        if (c.two) c.d2[g] = C{v.y, 0};
     }
 };
 
 // gamma DFT of the synthesis on the real part of line (a, b).  The line is
 // real, so c_-n = conj c_n: only even n >= 0 are kept, V1[b][a][n/2].
+template <class C_>
 struct FwdGammaIO {
+    using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    const cd *grid;
-    cd *V1;
+    const C *grid;
+    C *V1;
     int L, h, Nm;
     struct Ctx {
-        const cd *src;
-        cd *dst;  // V1[b][a][0]
+        const C *src;
+        C *dst;  // V1[b][a][0]
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
         return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * (h + 1)};
     }
-    __device__ cd load(const Ctx &c, int g) const { return cd{c.src[g].x, 0.0}; }
-    __device__ void store(const Ctx &c, int n, cd v) const {
+    __device__ C load(const Ctx &c, int g) const { return C{c.src[g].x, 0}; }
+    __device__ void store(const Ctx &c, int n, C v) const {
         if ((n & 1) || n < 0) return;
         c.dst[n / 2] = v;
     }
@@ -611,14 +633,16 @@ struct FwdGammaIO {
 // gamma DFT of the synthesis, real parts of lines (2p, 2p+1) packed as
 // z = w1 + i w2; with Z_n its DFT, c1_n = (Z_n + conj Z_-n)/2 and
 // c2_n = (Z_n - conj Z_-n)/(2i); even n >= 0 kept.
+template <class C_>
 struct FwdGammaPackIO {
+    using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
-    const cd *grid;
-    cd *V1;
+    const C *grid;
+    C *V1;
     int L, h, Nm, nreal;
     struct Ctx {
-        const cd *s1, *s2;
-        cd *d1, *d2;  // V1[b][a][0] of both lines
+        const C *s1, *s2;
+        C *d1, *d2;  // V1[b][a][0] of both lines
         bool two;
     };
     __device__ Ctx at(int p) const {
@@ -630,15 +654,15 @@ struct FwdGammaPackIO {
                    V1 + ((size_t)b1 * Nm + a1) * (h + 1), V1 + ((size_t)b2 * Nm + a2) * (h + 1),
                    two};
     }
-    __device__ cd load(const Ctx &c, int g) const {
-        return cd{c.s1[g].x, c.two ? c.s2[g].x : 0.0};
+    __device__ C load(const Ctx &c, int g) const {
+        return C{c.s1[g].x, c.two ? c.s2[g].x : (real_t<C>)0};
     }
-    __device__ void store_pair(const Ctx &c, int n, cd zn, cd zmn) const {
+    __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
         if (n & 1) return;
-        const cd czm = cconj(zmn);
-        const cd s = cadd(zn, czm), d = csub(zn, czm);
-        c.d1[n / 2] = cd{0.5 * s.x, 0.5 * s.y};
-        if (c.two) c.d2[n / 2] = cd{0.5 * d.y, -0.5 * d.x};
+        const C czm = cconj(zmn);
+        const C s = cadd(zn, czm), d = csub(zn, czm);
+        c.d1[n / 2] = C{s.x * (real_t<C>)0.5, s.y * (real_t<C>)0.5};
+        if (c.two) c.d2[n / 2] = C{d.y * (real_t<C>)0.5, d.x * (real_t<C>)-0.5};
     }
 };
 
@@ -646,29 +670,32 @@ struct FwdGammaPackIO {
 // The grid is real, so the line of -n is the conjugate of the line of n and
 // its transform at m is the conjugate of this one's at -m:
 //   V2[b][m][h+k] = out(m),  V2[b][m][h-k] = conj out(-m),  m >= 0.
+template <class C_>
 struct FwdAlphaIO {
+    using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    const cd *V1;
-    cd *V2;
+    const C *V1;
+    C *V2;
     int L, h, Nm, Nep;
     struct Ctx {
-        const cd *src;
-        cd *pos, *neg;  // V2[b][0][h+k], V2[b][0][h-k]
+        const C *src;
+        C *pos, *neg;  // V2[b][0][h+k], V2[b][0][h-k]
         bool mirror;
     };
     __device__ Ctx at(int line) const {
         const int b = line / (h + 1), k = line % (h + 1);
-        cd *base = V2 + (size_t)b * L * Nep + h;
+        C *base = V2 + (size_t)b * L * Nep + h;
         return Ctx{V1 + (size_t)b * Nm * (h + 1) + k, base + k, base - k, k > 0};
     }
-    __device__ cd load(const Ctx &c, int a) const { return c.src[(size_t)a * (h + 1)]; }
-    __device__ void store(const Ctx &c, int m, cd v) const {
+    __device__ C load(const Ctx &c, int a) const { return c.src[(size_t)a * (h + 1)]; }
+    __device__ void store(const Ctx &c, int m, C v) const {
         if (m >= 0) c.pos[(size_t)m * Nep] = v;
         if (m <= 0 && c.mirror) c.neg[(size_t)(-m) * Nep] = cconj(v);
     }
 };
 
 struct ShtInvPhiIO {
+    using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *G;
     double *map;
@@ -685,6 +712,7 @@ struct ShtInvPhiIO {
 };
 
 struct ShtFwdPhiIO {
+    using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const double *map;
     cd *F1;
@@ -698,35 +726,72 @@ struct ShtFwdPhiIO {
     __device__ void store(const Ctx &c, int m, cd v) const { c.dst[m] = v; }
 };
 
-hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
-                            cd *W2, hipStream_t st) {
-    InvAlphaIO io{W1, W2, g.L, g.h, g.Nep, g.Nm};
+template <class C>
+static hipError_t inv_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *W1, C *W2,
+                              hipStream_t st) {
+    InvAlphaIO<C> io{W1, W2, g.L, g.h, g.Nep, g.Nm};
     return run_bluestein(io, g.L * (g.h + 1), B, st);
 }
-hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
-                            cd *grid, hipStream_t st) {
+template <class C>
+static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2, C *grid,
+                              hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
-        InvGammaPackIO io{W2, grid, g.L, g.h, g.Nm, nreal};
+        InvGammaPackIO<C> io{W2, grid, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
     }
-    InvGammaIO io{W2, grid, g.L, g.h, g.Nm};
+    InvGammaIO<C> io{W2, grid, g.L, g.h, g.Nm};
     return run_bluestein(io, nreal, B, st);
 }
-hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
-                            cd *V1, hipStream_t st) {
+template <class C>
+static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *grid, C *V1,
+                              hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
-        FwdGammaPackIO io{grid, V1, g.L, g.h, g.Nm, nreal};
+        FwdGammaPackIO<C> io{grid, V1, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
     }
-    FwdGammaIO io{grid, V1, g.L, g.h, g.Nm};
+    FwdGammaIO<C> io{grid, V1, g.L, g.h, g.Nm};
     return run_bluestein(io, nreal, B, st);
 }
-hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
-                            cd *V2, hipStream_t st) {
-    FwdAlphaIO io{V1, V2, g.L, g.h, g.Nm, g.Nep};
+template <class C>
+static hipError_t fwd_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *V1, C *V2,
+                              hipStream_t st) {
+    FwdAlphaIO<C> io{V1, V2, g.L, g.h, g.Nm, g.Nep};
     return run_bluestein(io, g.L * (g.h + 1), B, st);
+}
+
+hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1, cd *W2,
+                            hipStream_t st) {
+    return inv_alpha_t(g, B, W1, W2, st);
+}
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2, cd *grid,
+                            hipStream_t st) {
+    return inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid, cd *V1,
+                            hipStream_t st) {
+    return fwd_gamma_t(g, B, grid, V1, st);
+}
+hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1, cd *V2,
+                            hipStream_t st) {
+    return fwd_alpha_t(g, B, V1, V2, st);
+}
+hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1, cf *W2,
+                            hipStream_t st) {
+    return inv_alpha_t(g, B, W1, W2, st);
+}
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2, cf *grid,
+                            hipStream_t st) {
+    return inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid, cf *V1,
+                            hipStream_t st) {
+    return fwd_gamma_t(g, B, grid, V1, st);
+}
+hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1, cf *V2,
+                            hipStream_t st) {
+    return fwd_alpha_t(g, B, V1, V2, st);
 }
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,
                               hipStream_t st) {
@@ -746,6 +811,7 @@ hipError_t launch_sht_fwd_phi(int L, const BluesteinDev &B, const double *map, c
 static inline int nnp_of(int N) { return ((2 * N - 1) + 31) / 32 * 32; }
 
 struct GenInvAlphaIO {  // line (b, n); in m; out a
+    using C = cd;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *W1;
     cd *W2;
@@ -762,6 +828,7 @@ struct GenInvAlphaIO {  // line (b, n); in m; out a
     __device__ void store(const Ctx &c, int a, cd v) const { c.dst[(size_t)a * Nnp] = v; }
 };
 struct GenInvGammaIO {  // line (a, b); in n; out g
+    using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *W2;
     cd *grid;
@@ -778,6 +845,7 @@ struct GenInvGammaIO {  // line (a, b); in n; out g
     __device__ void store(const Ctx &c, int g, cd v) const { c.dst[g] = v; }
 };
 struct GenFwdGammaIO {  // line (a, b); in g; out n
+    using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     const cd *grid;
     cd *V1;
@@ -794,6 +862,7 @@ struct GenFwdGammaIO {  // line (a, b); in g; out n
     __device__ void store(const Ctx &c, int n, cd v) const { c.dst[n] = v; }
 };
 struct GenFwdAlphaIO {  // line (b, n); in a; out m
+    using C = cd;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     const cd *V1;
     cd *V2;

@@ -410,7 +410,7 @@ __global__ void k_reduce_fwd(ScaleGeom g, int Lf, const cd *__restrict__ part, i
 //   acc[l][m] += Delta^l_{m'm} T[l][m]   (applied in the MFMA output layout; the
 //   Delta row of each l is contiguous in m, so those loads coalesce).
 // Wave (wp, wm): parity wp, 32 l x 32 m, [2 l blocks][2 m blocks][re/im].
-__global__ __launch_bounds__(256) void k_contract_fwd_mfma(ScaleGeom g, int Lf,
+__global__ __launch_bounds__(256, 2) void k_contract_fwd_mfma(ScaleGeom g, int Lf,
                                                            const double *__restrict__ delta,
                                                            const cd *__restrict__ Z,
                                                            const double *__restrict__ psi,
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_contract_fwd_mfma(ScaleGeom g, int Lf,
                 for (int c = 0; c < 2; ++c) t[a][b][c] = cvl_d4{0.0, 0.0, 0.0, 0.0};
         for (int kb = 0; kb <= kmax; kb += 16) {
             // B'^T rows l = l0 + par + 2i, columns k = kb + kk (k fastest across threads)
-#pragma unroll
+#pragma unroll 2
             for (int q = 0; q < 4; ++q) {
                 const int idx = tid + 256 * q;
                 const int kk = idx & 15, i = (idx >> 4) & 31, par = idx >> 9;
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256) void k_contract_fwd_mfma(ScaleGeom g, int Lf,
                 Bt[par][kk][i] = v;
             }
             // Z^{+/-}[m][k] for m = m0 + mm (k fastest across threads)
-#pragma unroll
+#pragma unroll 2
             for (int q = 0; q < 4; ++q) {
                 const int idx = tid + 256 * q;
                 const int kk = idx & 15, mm = idx >> 4;

@@ -1,0 +1,479 @@
+// Reduced-precision dense kernels of the curvelet transform on gfx950.
+//
+// The l-contractions of the analysis and of the synthesis run on the matrix
+// cores with FP32 accumulation, in one of two operand precisions:
+//   * FP32: v_mfma_f32_16x16x4_f32;
+//   * BF16x3: each FP32 operand split as x = hi + lo (two bfloat16, hi the
+//     nearest bfloat16 to x, lo the nearest to x - hi) and a*b taken as
+//     hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 (the lo*lo term,
+//     relative size 2^-16, is dropped).
+// Delta stays FP64 in HBM; each element is multiplied by its FP64 partner
+// (f_lm, or Psi) before rounding to FP32, so the operands carry one rounding.
+// The beta stage is an FP32 MFMA GEMM; the FFT stages run in FP32 elsewhere.
+//
+// Lane layouts (16 x 16 output block, 64 lanes, lane = 16 q + i, i < 16):
+//   f32 16x16x4:   A[i][q], B[q][i];           D[4q + r][i] in result reg r
+//   bf16 16x16x32: A[i][8q + e], B[8q + e][i]; D[4q + r][i]
+// For K = 32 both modes give lane (q, i) the operand elements k = 8q + e,
+// e < 8 (the FP32 mode issues one K = 4 product per e; the order of the
+// terms of a sum over k does not change the sum's definition).
+#include "cvl_device.h"
+
+namespace cvl {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// One lane's eight K-elements of an MFMA operand, in the working format.
+template <int MODE>
+struct Op;
+template <>
+struct Op<PREC_FP32> {
+    float v[8];
+    __device__ __forceinline__ void set(const float x[8]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = x[e];
+    }
+};
+template <>
+struct Op<PREC_BF16X3> {
+    bf8v hi, lo;
+    __device__ __forceinline__ void set(const float x[8]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)x[e];
+            hi[e] = h;
+            lo[e] = (__bf16)(x[e] - (float)h);
+        }
+    }
+};
+
+// acc += A B over the 32 K-elements of a chunk.
+__device__ __forceinline__ f4v mma32(const Op<PREC_FP32> &a, const Op<PREC_FP32> &b, f4v acc) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[e], b.v[e], acc, 0, 0, 0);
+    return acc;
+}
+__device__ __forceinline__ f4v mma32(const Op<PREC_BF16X3> &a, const Op<PREC_BF16X3> &b,
+                                     f4v acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Parity-folded beta stage in FP32 (curvelet layout, Nep % 32 == 0):
+//   out[r][c] = (i^par(c)) sum_k A^{par(c)}[r][k] in[k][c].
+// Tile 128 rows x 64 real columns x 32 k; wave w owns rows [32w, 32w+32) as
+// 2 x 4 blocks of v_mfma_f32_16x16x4_f32.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, int Nep,
+                                                       const float *__restrict__ Ae,
+                                                       const float *__restrict__ Ao,
+                                                       const float *__restrict__ in,
+                                                       float *__restrict__ out) {
+    __shared__ float As[128][33];
+    __shared__ float Bs[32][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.y * 128;
+    const int c0 = blockIdx.x * 32;  // complex column base
+    const size_t ld = 2 * (size_t)ncols;
+    const int par = (c0 / Nep) & 1;
+    const float *A = par ? Ao : Ae;
+    f4v acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int li = lane & 15, lq = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = tid + 256 * q;
+            const int rr = idx >> 5, kk = idx & 31;
+            const int r = r0 + rr, k = k0 + kk;
+            As[rr][kk] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx >> 4, cc = (idx & 15) * 4;  // 4 floats = 2 complex
+            const int k = k0 + kk;
+            const size_t col = 2 * (size_t)c0 + cc;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < K && col + 3 < ld) x = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
+            if (par) {
+                Bs[kk][cc] = -x.y;
+                Bs[kk][cc + 1] = x.x;
+                Bs[kk][cc + 2] = -x.w;
+                Bs[kk][cc + 3] = x.z;
+            } else {
+                Bs[kk][cc] = x.x;
+                Bs[kk][cc + 1] = x.y;
+                Bs[kk][cc + 2] = x.z;
+                Bs[kk][cc + 3] = x.w;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int k = 4 * ks + lq;
+            const float a0 = As[32 * w + li][k];
+            const float a1 = As[32 * w + 16 + li][k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float b = Bs[k][16 * j + li];
+                acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 32 * w + 16 * i + 4 * lq + r;
+                const size_t col = 2 * (size_t)c0 + 16 * j + li;
+                if (row < M && col < ld) out[(size_t)row * ld + col] = acc[i][j][r];
+            }
+}
+
+hipError_t launch_beta_gemm_f32(int M, int K, int ncols, int Nep, const float *Aeven,
+                                const float *Aodd, const cf *in, cf *out, hipStream_t st) {
+    if (Nep % 32 != 0) return hipErrorInvalidValue;
+    dim3 g((ncols + 31) / 32, (M + 127) / 128);
+    hipLaunchKernelGGL(k_beta_mfma_f32, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
+                       (const float *)in, (float *)out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Analysis contraction of one scale, reduced precision (cube X in complex64):
+//   P_e/o[m][k] = sum_{l even/odd} (Delta^l_{m'm} f_lm) (Delta^l_{m',2k} Psi_{l,2k})
+//   X[m'][m][h+k] = (-1)^k i^{-m} (P_e + P_o)
+//   X[m'][m][h-k] = (-1)^k i^{-m} (-1)^{m'} (P_e - P_o)
+// for l in [max(llo, m', m, 2k), lhi].  Work-group: one m', 64 m x 32 k.  The
+// GEMM rows are (component c, m): A[(c, m)][l] = c-part of Delta f, B[l][k].
+// A chunk covers 64 consecutive l (32 of each parity = one K = 32 step).
+// Wave w: parity p = w & 1, component c = w >> 1; 64 rows x 32 columns as
+// 4 x 2 blocks.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
+                                                         const double *__restrict__ delta,
+                                                         const cd *__restrict__ fpad,
+                                                         const double *__restrict__ psi,
+                                                         cf *__restrict__ X) {
+    // As[p][c][i][mm] (l = lb + p + 2i), Bs[p][i][kk]; reused for the results
+    // R[p][c][mm][kk] after the l loop.
+    // Row pads (66, 34) put the four 16-lane groups of an operand read on
+    // disjoint LDS banks.
+    __shared__ float smem[2 * 2 * 32 * 66 + 2 * 32 * 34];
+    float(*As)[2][32][66] = reinterpret_cast<float(*)[2][32][66]>(smem);
+    float(*Bs)[32][34] = reinterpret_cast<float(*)[32][34]>(smem + 2 * 2 * 32 * 66);
+    const int L = g.L, h = g.h;
+    const int mp = blockIdx.y;
+    const int nkt = (h + 1 + 31) / 32;
+    const int m0 = (blockIdx.x / nkt) * 64, k0 = (blockIdx.x % nkt) * 32;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int p = w & 1, c = w >> 1;
+    const int li = lane & 15, lq = lane >> 4;
+    f4v acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+    int lstart = g.llo;
+    if (mp > lstart) lstart = mp;
+    if (m0 > lstart) lstart = m0;
+    if (2 * k0 > lstart) lstart = 2 * k0;
+    const int lend = g.lhi;
+    for (int lb = lstart & ~1; lb <= lend; lb += 64) {
+        // A: 2 parities x 32 l x 64 m complex, 16 per thread (m fastest)
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+            const int idx = tid + 256 * q;
+            const int mm = idx & 63, i = (idx >> 6) & 31, pp = idx >> 11;
+            const int l = lb + pp + 2 * i, m = m0 + mm;
+            float re = 0.f, im = 0.f;
+            if (l >= lstart && l <= lend && m <= l && m < L) {
+                const double d = delta[delta_off(l) + (int64_t)mp * (l + 1) + m];
+                const cd f = fpad[(size_t)l * Lf + m];
+                re = (float)(d * f.x);
+                im = (float)(d * f.y);
+            }
+            As[pp][0][i][mm] = re;
+            As[pp][1][i][mm] = im;
+        }
+        // B: 2 parities x 32 l x 32 k, 8 per thread (k fastest)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, i = (idx >> 5) & 31, pp = idx >> 10;
+            const int l = lb + pp + 2 * i, k = k0 + kk;
+            float v = 0.f;
+            if (l >= lstart && l <= lend && k <= h && 2 * k <= l)
+                v = (float)(delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] *
+                            psi[(size_t)l * (h + 1) + k]);
+            Bs[pp][i][kk] = v;
+        }
+        __syncthreads();
+        Op<MODE> bop[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = Bs[p][8 * lq + e][16 * cb + li];
+            bop[cb].set(x);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = As[p][c][8 * lq + e][16 * rb + li];
+            Op<MODE> aop;
+            aop.set(x);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mma32(aop, bop[cb], acc[rb][cb]);
+        }
+        __syncthreads();
+    }
+    // results to LDS: R[p][c][mm][kk]
+    float(*R)[2][64][33] = reinterpret_cast<float(*)[2][64][33]>(smem);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) R[p][c][16 * rb + 4 * lq + r][16 * cb + li] = acc[rb][cb][r];
+    __syncthreads();
+    const int Nep = g.Nep;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int idx = tid + 256 * q;
+        const int kk = idx & 31, mm = idx >> 5;
+        const int m = m0 + mm, k = k0 + kk;
+        if (m >= L || k > h) continue;
+        const cf pe = cf{R[0][0][mm][kk], R[0][1][mm][kk]};
+        const cf po = cf{R[1][0][mm][kk], R[1][1][mm][kk]};
+        const float sk = (k & 1) ? -1.f : 1.f;
+        cf *row = X + ((size_t)mp * L + m) * Nep;
+        row[h + k] = ipow(cscale(cadd(pe, po), sk), -m);
+        if (k > 0) {
+            const float sm = (mp & 1) ? -sk : sk;
+            row[h - k] = ipow(cscale(csub(pe, po), sm), -m);
+        }
+    }
+}
+
+hipError_t launch_contract_inv_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
+                                  const cd *fpad, const double *psi, cf *X, hipStream_t st) {
+    const int nkt = (g.h + 1 + 31) / 32;
+    dim3 grid(((g.L + 63) / 64) * nkt, g.L);
+    if (mode == PREC_FP32)
+        hipLaunchKernelGGL(k_contract_inv_mx<PREC_FP32>, grid, dim3(256), 0, st, g, Lf, delta,
+                           fpad, psi, X);
+    else
+        hipLaunchKernelGGL(k_contract_inv_mx<PREC_BF16X3>, grid, dim3(256), 0, st, g, Lf, delta,
+                           fpad, psi, X);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis contraction of one scale, reduced precision (cube Z in complex64):
+//   f_lm = i^m sum_{m'} Delta^l_{m'm} sum_k Z^{par(l)}[m'][m][k] B'[k][l],
+//   B'[k][l] = (-1)^k Delta^l_{m',2k} Psi_{l,2k},
+//   Z^{+/-}[m'][m][k] = Z[m'][m][h+k] +/- (-1)^{m'} Z[m'][m][h-k]  (k > 0),
+//   Z^{+/-}[m'][m][0] = Z[m'][m][h].
+// Work-group tile: 64 l (32 of each parity, l = l0 + par + 2i) x 64 m over
+// one group of m'.  Per m': T[l][m] = sum_k B'[k][l] Z^par[m][k] on the
+// matrix cores (K chunks of 32), then acc[l][m] += Delta^l_{m'm} T[l][m] in
+// the output layout.  Wave (wp, wm): parity wp, 32 l x 32 m, [2 l blocks]
+// [2 m blocks][re/im].  The group partials part[grp][l][m] (complex64) are
+// summed in FP64 afterwards.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_contract_fwd_mx(ScaleGeom g, int Lf,
+                                                         const double *__restrict__ delta,
+                                                         const cf *__restrict__ Z,
+                                                         const double *__restrict__ psi,
+                                                         cf *__restrict__ part, int ngroups) {
+    __shared__ float Bt[2][32][34];       // [par][k][i]
+    __shared__ float Zs[2][2][32][66];    // [par][re/im][k][mm]
+    const int L = g.L, h = g.h, Nep = g.Nep;
+    const int lbase = g.llo & ~1;
+    const int nl = g.lhi - lbase + 1;
+    const int nlt = (nl + 63) / 64;
+    const int m0 = (blockIdx.x / nlt) * 64;
+    const int l0 = lbase + (blockIdx.x % nlt) * 64;
+    const int grp = blockIdx.y;
+    const int gsz = (L + ngroups - 1) / ngroups;
+    const int mpa = grp * gsz;
+    int mpb = mpa + gsz;
+    if (mpb > L) mpb = L;
+    int ltop = l0 + 63;
+    if (ltop > g.lhi) ltop = g.lhi;
+    if (mpb > ltop + 1) mpb = ltop + 1;
+    int kmax = ltop / 2;
+    if (kmax > h) kmax = h;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wp = w & 1, wm = w >> 1;
+    const int li = lane & 15, lq = lane >> 4;
+    f4v acc[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) acc[a][b][cc] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int mp = mpa; mp < mpb; ++mp) {
+        const float smp = (mp & 1) ? -1.f : 1.f;
+        f4v t[2][2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) t[a][b][cc] = f4v{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb <= kmax; kb += 32) {
+            // B'^T: [par][k][i], l = l0 + par + 2i (k fastest across threads)
+#pragma unroll 2
+            for (int q = 0; q < 8; ++q) {
+                const int idx = tid + 256 * q;
+                const int kk = idx & 31, i = (idx >> 5) & 31, par = idx >> 10;
+                const int l = l0 + par + 2 * i, k = kb + kk;
+                float v = 0.f;
+                if (k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l) {
+                    double dv = delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] *
+                                psi[(size_t)l * (h + 1) + k];
+                    v = (float)((k & 1) ? -dv : dv);
+                }
+                Bt[par][kk][i] = v;
+            }
+            // Z^{+/-}[m][k], m = m0 + mm (k fastest across threads)
+#pragma unroll 2
+            for (int q = 0; q < 8; ++q) {
+                const int idx = tid + 256 * q;
+                const int kk = idx & 31, mm = idx >> 5;
+                const int k = kb + kk, m = m0 + mm;
+                cf vp = cf{0.f, 0.f}, vm = cf{0.f, 0.f};
+                if (k <= kmax && m < L) {
+                    const cf *row = Z + ((size_t)mp * L + m) * Nep;
+                    const cf zp = row[h + k];
+                    if (k == 0) {
+                        vp = vm = zp;
+                    } else {
+                        const cf zn = cscale(row[h - k], smp);
+                        vp = cadd(zp, zn);
+                        vm = csub(zp, zn);
+                    }
+                }
+                Zs[0][0][kk][mm] = vp.x;
+                Zs[0][1][kk][mm] = vp.y;
+                Zs[1][0][kk][mm] = vm.x;
+                Zs[1][1][kk][mm] = vm.y;
+            }
+            __syncthreads();
+            Op<MODE> aop[2];
+#pragma unroll
+            for (int lf = 0; lf < 2; ++lf) {
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = Bt[wp][8 * lq + e][16 * lf + li];
+                aop[lf].set(x);
+            }
+#pragma unroll
+            for (int mj = 0; mj < 2; ++mj)
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    float x[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) x[e] = Zs[wp][cc][8 * lq + e][32 * wm + 16 * mj + li];
+                    Op<MODE> bop;
+                    bop.set(x);
+#pragma unroll
+                    for (int lf = 0; lf < 2; ++lf) t[lf][mj][cc] = mma32(aop[lf], bop, t[lf][mj][cc]);
+                }
+            __syncthreads();
+        }
+        // acc += Delta^l_{m'm} T: output row 4 lq + r of block lf, column li
+#pragma unroll
+        for (int lf = 0; lf < 2; ++lf)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
+                const bool lok = l <= g.lhi && mp <= l;
+                const double *drow = delta + (lok ? delta_off(l) + (int64_t)mp * (l + 1) : 0);
+#pragma unroll
+                for (int mj = 0; mj < 2; ++mj) {
+                    const int m = m0 + 32 * wm + 16 * mj + li;
+                    const float d = (lok && m <= l) ? (float)drow[m] : 0.f;
+                    acc[lf][mj][0][r] += d * t[lf][mj][0][r];
+                    acc[lf][mj][1][r] += d * t[lf][mj][1][r];
+                }
+            }
+    }
+#pragma unroll
+    for (int lf = 0; lf < 2; ++lf)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
+            if (l > g.lhi) continue;
+#pragma unroll
+            for (int mj = 0; mj < 2; ++mj) {
+                const int m = m0 + 32 * wm + 16 * mj + li;
+                if (m >= L) continue;
+                part[((size_t)grp * L + l) * L + m] = cf{acc[lf][mj][0][r], acc[lf][mj][1][r]};
+            }
+        }
+}
+
+hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
+                                  const cf *Z, const double *psi, cf *part, int ngroups,
+                                  hipStream_t st) {
+    if (g.lhi < g.llo) return hipSuccess;
+    const int nl = g.lhi - (g.llo & ~1) + 1;
+    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64), ngroups);
+    if (mode == PREC_FP32)
+        hipLaunchKernelGGL(k_contract_fwd_mx<PREC_FP32>, grid, dim3(256), 0, st, g, Lf, delta, Z,
+                           psi, part, ngroups);
+    else
+        hipLaunchKernelGGL(k_contract_fwd_mx<PREC_BF16X3>, grid, dim3(256), 0, st, g, Lf, delta,
+                           Z, psi, part, ngroups);
+    return hipGetLastError();
+}
+
+// FP64 sum of the complex64 group partials into the FP64 accumulator:
+//   facc[l][m] += i^m sum_grp part[grp][l][m].
+__global__ void k_reduce_fwd_mx(ScaleGeom g, int Lf, const cf *__restrict__ part, int ngroups,
+                                cd *__restrict__ facc) {
+    const int L = g.L;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nl = g.lhi - g.llo + 1;
+    if (idx >= nl * L) return;
+    const int l = g.llo + idx / L, m = idx % L;
+    if (m > l) return;
+    cd s = cd{0.0, 0.0};
+    for (int grp = 0; grp < ngroups; ++grp) {
+        const cf v = part[((size_t)grp * L + l) * L + m];
+        s = cadd(s, cd{(double)v.x, (double)v.y});
+    }
+    cd *o = facc + (size_t)l * Lf + m;
+    *o = cadd(*o, ipow(s, m));
+}
+
+hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int ngroups,
+                                cd *facc, hipStream_t st) {
+    const int nl = g.lhi - g.llo + 1;
+    if (nl <= 0) return hipSuccess;
+    const int n = nl * g.L;
+    hipLaunchKernelGGL(k_reduce_fwd_mx, dim3((n + 255) / 256), dim3(256), 0, st, g, Lf, part,
+                       ngroups, facc);
+    return hipGetLastError();
+}
+
+}  // namespace cvl
