@@ -1,16 +1,21 @@
 """Benchmark: spin-0 curvelet analysis + synthesis round trips on one MI355X.
 
-Workload (one step): one real map at L = 256, lambda = 2, J0 = 2 (J = 8, scales
-j = 2..8 with L_j = 8, 16, 32, 64, 128, 256, 256), complex128 SO(3) grids,
-FP64 throughout: curvelet analysis (map -> scaling map + 7 grids) followed by
-curvelet synthesis (-> map).  Inputs are resident in HBM before timing.
+Default workload (one step): one real map at L = 256, lambda = 2, J0 = 2 (J = 8,
+scales j = 2..8 with L_j = 8, 16, 32, 64, 128, 256, 256), complex128 SO(3)
+grids, FP64 throughout: curvelet analysis (map -> scaling map + 7 grids)
+followed by curvelet synthesis (-> map).  Inputs are resident in HBM before
+timing.  Other workloads: --L, --batch (maps per call) and --precision
+(fp64 | fp32 | bf16x3: complex64 grids, reduced-precision contractions).
 
-Prints ONE JSON line.  `value` is round trips per second.  `roofline` is for
-the kernel stage with the largest device time, timed live with HIP events
+Prints ONE JSON line.  `value` is round trips (maps) per second.  `roofline` is
+for the kernel stage with the largest device time, timed live with HIP events
 recorded by the library on the launch stream; `cpu_baseline` is the CPU FP64
-oracle timed on a bounded sample of the same workload and extrapolated.
+oracle timed on a bounded sample of the same workload and extrapolated.  For
+the reduced precisions the grids and the round trip are compared with the
+FP64 path (itself held to the oracle by the parity tests).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--L 256] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--L 256] [--batch 1]
+                       [--precision fp64] [--no-cpu]
 """
 import argparse
 import json
@@ -25,6 +30,17 @@ sys.path.insert(0, ROOT)
 METRIC = "curvelet fwd+inv transforms/s at L=256,1024; rel-L2 err vs FP64; p99 latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def stage_peak(stage, precision):
+    """Compute peak (TFLOP/s) of a stage's arithmetic in a given precision."""
+    if precision == "fp64":
+        return FP64_PEAK_TFLOPS
+    if precision == "bf16x3" and stage.startswith("contract"):
+        return BF16_MFMA_PEAK_TFLOPS
+    return FP32_PEAK_TFLOPS
 
 
 def scale_geoms(L, lam=2.0, J0=2):
@@ -40,16 +56,16 @@ def scale_geoms(L, lam=2.0, J0=2):
     return out
 
 
-def stage_models(L, lam=2.0, J0=2):
+def stage_models(L, lam=2.0, J0=2, B=16.0):
     """Algorithmic bytes / flops per round trip of each kernel stage.
 
-    bytes: each stage's input read once and output written once (16 B per
-    complex128).  flops: contractions 4 per (l, m, m', n>=0) term of the
+    bytes: each stage's input read once and output written once (B = 16 bytes
+    per complex128, 8 per complex64).  flops: contractions 4 per
+    (l, m, m', n>=0) term of the
     parity-folded sums (complex x real multiply-add); beta GEMMs 2 per
     multiply-add of the L_j x L_j real matrix on the 2*L_j*Ne real columns;
     DFT stages 5 n log2 n per complex line of length n = 2L_j - 1.
     """
-    B = 16.0
     m = {}
 
     def add(name, nbytes, flops):
@@ -75,8 +91,8 @@ def stage_models(L, lam=2.0, J0=2):
     return m
 
 
-def grid_bytes(L, lam=2.0, J0=2):
-    return sum(g["Nm"] * g["L"] * g["Nm"] * 16.0 for g in scale_geoms(L, lam, J0))
+def grid_bytes(L, lam=2.0, J0=2, B=16.0):
+    return sum(g["Nm"] * g["L"] * g["Nm"] * B for g in scale_geoms(L, lam, J0))
 
 
 def cpu_baseline(L, lam=2.0, J0=2):
@@ -129,6 +145,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--point-sources", type=int, default=0,
+                    help="add this many point sources to each map (projected onto band-limit L)")
+    ap.add_argument("--stream", action="store_true",
+                    help="one scale at a time through the streaming interface (batch 1)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -139,23 +161,42 @@ def main():
     import torch
     from paper_1511_05578_amd import api, inputs
 
-    L, lam, J0 = args.L, 2.0, 2
+    L, lam, J0, NB, prec = args.L, 2.0, 2, args.batch, args.precision
+    EB = 16.0 if prec == "fp64" else 8.0
     ctx = api.Context(L, 0)
     ctx.prepare(L, lam, J0)
-    f = torch.from_numpy(inputs.gaussian_real_flm(L, seed=0)).cuda()
-    fmap = ctx.sht_inverse(f, L)
-    scal, grids = ctx.alloc_outputs(L, lam, J0, 1)
-    rec = torch.empty((1, L, 2 * L - 1), dtype=torch.float64, device="cuda")
-    fmap1 = fmap.unsqueeze(0).contiguous()
+    if args.stream and NB != 1:
+        print("--stream runs one map per step (--batch 1)", file=sys.stderr)
+        sys.exit(2)
 
-    def step():
-        ctx.curvelet_analysis(fmap1, lam, J0, out=(scal, grids))
-        ctx.curvelet_synthesis(scal, grids, L, lam, J0, out=rec)
+    def make_map(s):
+        m = ctx.sht_inverse(torch.from_numpy(inputs.gaussian_real_flm(L, seed=s)).cuda(), L)
+        if args.point_sources:
+            raw = inputs.add_point_sources(m.cpu().numpy(),
+                                           inputs.point_sources(L, args.point_sources, seed=100 + s))
+            m = ctx.sht_inverse(ctx.sht_forward(torch.from_numpy(raw).cuda()), L)
+        return m
+
+    maps = torch.stack([make_map(s) for s in range(NB)]).contiguous()
+    rec = torch.empty((NB, L, 2 * L - 1), dtype=torch.float64, device="cuda")
+    if args.stream:
+        grids = None
+
+        def step():
+            r, _ = ctx.round_trip_streamed(maps[0], lam, J0, precision=prec)
+            rec[0].copy_(r)
+    else:
+        scal, grids = ctx.alloc_outputs(L, lam, J0, NB, precision=prec)
+
+        def step():
+            ctx.curvelet_analysis(maps, lam, J0, out=(scal, grids), precision=prec)
+            ctx.curvelet_synthesis(scal, grids, L, lam, J0, out=rec, precision=prec)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    err = (torch.linalg.norm(rec[0] - fmap) / torch.linalg.norm(fmap)).item()
+    err = (torch.linalg.norm(rec - maps) / torch.linalg.norm(maps)).item()
+    print("warm-up done, round trip rel L2 %.3e" % err, file=sys.stderr, flush=True)
 
     ctx.profile_enable(True)
     torch.cuda.synchronize()
@@ -166,32 +207,62 @@ def main():
     dt = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile_enable(False)
+    print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
+
+    vs64 = None
+    if prec != "fp64" and grids is not None:
+        # the first map's grids against the FP64 path's (complex128)
+        s64, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64")
+        num = den = 0.0
+        mx = mref = 0.0
+        for a, b in zip(grids[0], g64[0]):
+            for i0 in range(0, a.shape[0], 64):  # in slabs: bounded temporaries
+                d = a[i0:i0 + 64].to(torch.complex128) - b[i0:i0 + 64]
+                num += torch.linalg.norm(d).item() ** 2
+                den += torch.linalg.norm(b[i0:i0 + 64]).item() ** 2
+                mx = max(mx, d.abs().max().item())
+                mref = max(mref, b[i0:i0 + 64].abs().max().item())
+                del d
+        vs64 = {"grids_rel_l2": math.sqrt(num / den), "grids_max_abs_rel": mx / mref}
+        del s64, g64
 
     ms = dt * 1e3 / args.steps
-    models = stage_models(L, lam, J0)
+    models = stage_models(L, lam, J0, EB)
     stages = {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in prof.items() if v[0]}
     top = max((k for k in stages if k in models), key=lambda k: stages[k]["ms_per_step"])
-    t_top = stages[top]["ms_per_step"] * 1e-3 / (stages[top]["launches"] / args.steps)  # s per launch
-    nb, nf = models[top]
     launches_per_step = stages[top]["launches"] / args.steps
+    t_top = stages[top]["ms_per_step"] * 1e-3 / launches_per_step  # s per launch
+    nb, nf = models[top]
+    nb *= NB
+    nf *= NB
     bytes_per_launch = nb / launches_per_step
     flops_per_launch = nf / launches_per_step
+    peak_tf = stage_peak(top, prec)
     ai = nf / max(nb, 1.0)
-    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai < ridge:
         roof = {"bound": "hbm", "achieved": bytes_per_launch / t_top / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     else:
-        roof = {"bound": "alu", "achieved": flops_per_launch / t_top / 1e12,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        roof = {"bound": "mfma" if top.startswith(("contract", "beta")) else "alu",
+                "achieved": flops_per_launch / t_top / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["kernel"] = top
     roof["algorithmic_per_launch"] = {"bytes": bytes_per_launch, "flops": flops_per_launch}
 
+    gname = "complex128" if prec == "fp64" else "complex64"
+    work = ("%d real spin-0 map%s%s, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, %s grids%s, %s, "
+            "analysis+synthesis round trip" % (
+                NB, "" if NB == 1 else "s",
+                " with %d point sources" % args.point_sources if args.point_sources else "",
+                L, api.num_scales(L), gname, " streamed one scale at a time" if args.stream else "",
+                {"fp64": "FP64 throughout",
+                 "fp32": "FP32 MFMA contractions, FP32 FFT/beta",
+                 "bf16x3": "split-BF16 MFMA contractions, FP32 FFT/beta"}[prec]))
     out = {
         "metric": METRIC,
-        "value": 1e3 / ms,
+        "value": NB * 1e3 / ms,
         "unit": "transforms/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -200,16 +271,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic: f_lm ~ N(0,(l+1)^-2) real-map coefficients, seed 0",
-        "config": {"workload": "C2: one real spin-0 map, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, "
-                               "complex128 grids, analysis+synthesis round trip" % (L, api.num_scales(L)),
-                   "L": L, "lambda": lam, "J0": J0, "grid_bytes": grid_bytes(L, lam, J0)},
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[prec],
+        "data": "synthetic: f_lm ~ N(0,(l+1)^-2) real-map coefficients, seeds 0..%d" % (NB - 1),
+        "config": {"workload": work, "L": L, "lambda": lam, "J0": J0, "batch": NB,
+                   "precision": prec, "stream": bool(args.stream),
+                   "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, EB)},
         "round_trip_rel_l2": err,
-        "hbm_roofline_ms": 2 * grid_bytes(L, lam, J0) / (HBM_PEAK_GBS * 1e9) * 1e3,
+        "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, EB) / (HBM_PEAK_GBS * 1e9) * 1e3,
         "roofline": roof,
         "stages": stages,
     }
+    if vs64 is not None:
+        out["vs_fp64_path"] = vs64
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, lam, J0)
     ctx.close()

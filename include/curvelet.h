@@ -166,6 +166,39 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
                            const double *scal_maps, const void *const *grids,
                            double *maps, void *ws, size_t ws_bytes, void *stream);
 
+/* Streaming interface: the same transform one scale at a time, so that only
+ * one scale's grid need be resident (Sec. II-D; the synthesis is a sum over
+ * scales in harmonic space, Sec. II-D-2).  flm / flm_acc are L^2 complex128
+ * harmonic coefficients in the layout of cvl_sht_forward (negative m by the
+ * reality condition).  Workspace: cvl_workspace_bytes(p, 1).  A round trip is
+ *   cvl_sht_forward(map) -> flm;  cvl_curvelet_scaling_analysis(flm) -> scal;
+ *   per scale j: cvl_curvelet_analysis_scale(flm, j) -> grid,
+ *                cvl_curvelet_synthesis_scale(grid, j) adds into flm_acc;
+ *   cvl_curvelet_scaling_synthesis(scal) adds into flm_acc;
+ *   cvl_sht_inverse(flm_acc) -> map
+ * with flm_acc zeroed by the caller first.  The sum is the one
+ * cvl_curvelet_synthesis forms (in another order: equal up to rounding). */
+
+/* Grid of scale j (same layout and element type as cvl_curvelet_analysis). */
+int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j,
+                                const cvl_c128 *flm, void *grid, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* flm_acc += f^(j)_lm, the synthesis of the real part of scale j's grid. */
+int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j,
+                                 const void *grid, cvl_c128 *flm_acc, void *ws,
+                                 size_t ws_bytes, void *stream);
+
+/* Scaling coefficients: real MW map of band-limit L_Phi (Sec. II-D-1). */
+int cvl_curvelet_scaling_analysis(cvl_ctx *ctx, const cvl_params *p,
+                                  const cvl_c128 *flm, double *scal_map,
+                                  void *ws, size_t ws_bytes, void *stream);
+
+/* flm_acc += the scaling part of the synthesis (Sec. II-D-2). */
+int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p,
+                                   const double *scal_map, cvl_c128 *flm_acc,
+                                   void *ws, size_t ws_bytes, void *stream);
+
 /* Host copy of the kernel tables of `p` (no device work; usable without a
  * GPU): kappa[(j - J0) * L + l] = kappa^(j)(l) for J0 <= j <= J, and
  * phi[l] = Phi_l0 (Sec. II-B).  kappa needs (J - J0 + 1) * L doubles, phi L. */

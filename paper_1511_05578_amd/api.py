@@ -54,6 +54,18 @@ SIGNATURES = {
                                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                               ctypes.c_void_p]),
+    "cvl_curvelet_analysis_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams), ctypes.c_int,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_curvelet_synthesis_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams), ctypes.c_int,
+                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_curvelet_scaling_analysis": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams),
+                                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                     ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_curvelet_scaling_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams),
+                                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_size_t, ctypes.c_void_p]),
     "cvl_kernel_tables": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_double_p, _c_double_p]),
     "cvl_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "cvl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p,
@@ -115,9 +127,10 @@ def scaling_bandlimit(L, lam=2.0, J0=2):
     return v.value
 
 
-def workspace_bytes(L, lam=2.0, J0=2, batch=1):
+def workspace_bytes(L, lam=2.0, J0=2, batch=1, precision=CVL_FP64):
     v = ctypes.c_size_t()
-    _check(lib.cvl_workspace_bytes(ctypes.byref(params(L, lam, J0)), batch, ctypes.byref(v)))
+    _check(lib.cvl_workspace_bytes(ctypes.byref(params(L, lam, J0, precision=precision)), batch,
+                                   ctypes.byref(v)))
     return v.value
 
 
@@ -258,7 +271,7 @@ class Context:
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
-        ws = self.workspace(workspace_bytes(L, lam, J0, batch))
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision))
         p = params(L, lam, J0, precision=precision)
         _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(p), batch,
                                          maps.data_ptr(), scal.data_ptr(), arr, ws.data_ptr(),
@@ -281,12 +294,81 @@ class Context:
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
-        ws = self.workspace(workspace_bytes(L, lam, J0, batch))
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision))
         p = params(L, lam, J0, precision=precision)
         _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(p), batch,
                                           scal.data_ptr(), arr, out.data_ptr(), ws.data_ptr(),
                                           ws.numel(), _stream(t)))
         return out[0] if single else out
+
+    # ---- streaming (one scale at a time) ----
+    def analysis_scale(self, flm, L, j, lam=2.0, J0=2, out=None, precision=CVL_FP64):
+        """Grid of scale j from harmonic coefficients flm (L^2 complex128)."""
+        t = self.torch
+        assert flm.dtype == t.complex128 and flm.is_contiguous() and flm.numel() == L * L
+        if out is None:
+            Lj, _ = scale_shape(L, j, lam, J0)
+            out = t.empty((2 * Lj - 1, Lj, 2 * Lj - 1), dtype=self.grid_dtype(precision),
+                          device=self.device)
+        assert out.dtype == self.grid_dtype(precision) and out.is_contiguous()
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
+        p = params(L, lam, J0, precision=precision)
+        _check(lib.cvl_curvelet_analysis_scale(self.h, ctypes.byref(p), j, flm.data_ptr(),
+                                               out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(t)))
+        return out
+
+    def synthesis_scale(self, grid, L, j, flm_acc, lam=2.0, J0=2, precision=CVL_FP64):
+        """flm_acc += f^(j)_lm from scale j's grid."""
+        t = self.torch
+        assert grid.dtype == self.grid_dtype(precision) and grid.is_contiguous()
+        assert flm_acc.dtype == t.complex128 and flm_acc.numel() == L * L
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
+        p = params(L, lam, J0, precision=precision)
+        _check(lib.cvl_curvelet_synthesis_scale(self.h, ctypes.byref(p), j, grid.data_ptr(),
+                                                flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                _stream(t)))
+        return flm_acc
+
+    def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None):
+        t = self.torch
+        Lp = scaling_bandlimit(L, lam, J0)
+        if out is None:
+            out = t.empty((Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1))
+        _check(lib.cvl_curvelet_scaling_analysis(self.h, ctypes.byref(params(L, lam, J0)),
+                                                 flm.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                                 ws.numel(), _stream(t)))
+        return out
+
+    def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2):
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1))
+        _check(lib.cvl_curvelet_scaling_synthesis(self.h, ctypes.byref(params(L, lam, J0)),
+                                                  scal.data_ptr(), flm_acc.data_ptr(), ws.data_ptr(),
+                                                  ws.numel(), _stream(self.torch)))
+        return flm_acc
+
+    def round_trip_streamed(self, fmap, lam=2.0, J0=2, precision=CVL_FP64, on_grid=None):
+        """Analysis + synthesis of one real map, one scale at a time (a single
+        grid buffer of the largest scale is reused).  on_grid(j, grid), if
+        given, sees each scale's grid between its analysis and synthesis."""
+        t = self.torch
+        L = fmap.shape[-2]
+        flm = self.sht_forward(fmap)
+        acc = t.zeros(L * L, dtype=t.complex128, device=self.device)
+        scal = self.scaling_analysis(flm, L, lam, J0)
+        J = num_scales(L, lam, J0)
+        Lt, _ = scale_shape(L, J, lam, J0)
+        buf = t.empty((2 * Lt - 1) * Lt * (2 * Lt - 1), dtype=self.grid_dtype(precision),
+                      device=self.device)
+        for j in range(J0, J + 1):
+            Lj, _ = scale_shape(L, j, lam, J0)
+            g = buf[:(2 * Lj - 1) * Lj * (2 * Lj - 1)].view(2 * Lj - 1, Lj, 2 * Lj - 1)
+            self.analysis_scale(flm, L, j, lam, J0, out=g, precision=precision)
+            if on_grid is not None:
+                on_grid(j, g)
+            self.synthesis_scale(g, L, j, acc, lam, J0, precision=precision)
+        self.scaling_synthesis(scal, L, acc, lam, J0)
+        return self.sht_inverse(acc, L), scal
 
     def delta_block(self, l):
         out = np.zeros((l + 1, l + 1))

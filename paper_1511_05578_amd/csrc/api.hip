@@ -109,7 +109,6 @@ struct Plan {
     std::vector<ScaleRt> scales;
     double *phifac;  // [Lphi]: sqrt(4pi/(2l+1)) Phi_l0
     int ngroups;
-    size_t ws_per_map;  // bytes
 };
 
 struct ShtRt {
@@ -352,20 +351,28 @@ ScaleGeom geom_of(int Lj) {
     return g;
 }
 
-size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int ngroups) {
-    size_t b0 = 0, b1 = 0;
+// Element counts of the two cube-sized workspace buffers of a curvelet call.
+void curvelet_buf_elems(int L, double lam, int J0, int J, int ngroups, size_t *b0, size_t *b1) {
+    *b0 = *b1 = 0;
     for (int j = J0; j <= J; ++j) {
         ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
         size_t cube = (size_t)g.L * g.L * g.Nep;
         size_t w2 = (size_t)g.L * g.Nm * (g.h + 1);
-        size_t v1 = (size_t)g.L * g.Nm * (g.h + 1);
         size_t part = (size_t)ngroups * g.L * g.L;
-        b0 = std::max({b0, cube, w2, v1});
-        b1 = std::max({b1, cube, part});
+        *b0 = std::max({*b0, cube, w2});
+        *b1 = std::max({*b1, cube, part});
     }
+}
+
+// Workspace bytes of a curvelet call: two cube buffers (complex128, or
+// complex64 in reduced precision) and five L x L complex128 planes.
+size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int ngroups, int precision) {
+    size_t b0, b1;
+    curvelet_buf_elems(L, lam, J0, J, ngroups, &b0, &b1);
+    const size_t esz = precision == CVL_FP64 ? 16 : 8;
     const int Lphi = scaling_bandlimit(L, lam, J0);
     size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
-    return align_up(b0 * 16) + align_up(b1 * 16) + align_up(small * 16) + 4 * kAlign;
+    return align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) + 8 * kAlign;
 }
 
 int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
@@ -425,7 +432,6 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
     std::vector<double> pf(P->Lphi);
     for (int l = 0; l < P->Lphi; ++l) pf[l] = std::sqrt(4.0 * M_PI / (2.0 * l + 1.0)) * phi[l];
     if ((rc = c->arena.upload(pf, &P->phifac))) return rc;
-    P->ws_per_map = curvelet_ws_bytes(L, p->lambda, p->J0, J, P->ngroups);
     *out = P.get();
     c->plans[key] = std::move(P);
     return CVL_OK;
@@ -610,7 +616,7 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
     if (rc) return rc;
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, kGroups);
+    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, kGroups, p->precision);
     return CVL_OK;
 }
 
@@ -681,7 +687,7 @@ int cvl_sht_forward(cvl_ctx *ctx, int L, int spin, const double *map, cvl_c128 *
     cd *F1 = cv.take<cd>((size_t)L * L);
     cd *Zs = cv.take<cd>((size_t)L * L);
     if ((rc = sht_forward_run(ctx, S, map, fpad, L, F1, Zs, st))) return rc;
-    LAUNCH(ST_MISC, launch_flm_unpack(L, fpad, (cd *)flm, st));
+    LAUNCH(ST_MISC, launch_flm_unpack(L, fpad, (cd *)flm, 0, st));
     return CVL_OK;
 }
 
@@ -802,8 +808,10 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
     if (!a || !b || !grids || !ws) return fail(CVL_EINVAL, "NULL pointer argument");
     if ((rc = set_device(ctx))) return rc;
     if ((rc = get_plan(ctx, p, P))) return rc;
-    if (ws_bytes < (*P)->ws_per_map)
-        return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, (*P)->ws_per_map);
+    const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, (*P)->ngroups,
+                                          p->precision);
+    if (ws_bytes < need)
+        return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ShtRt *S;
     if ((rc = get_sht(ctx, (*P)->L, &S))) return rc;
@@ -812,20 +820,18 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
 }
 
 struct CurveletBufs {
-    cd *b0, *b1, *fpad, *facc, *s0, *s1, *fphi;
+    void *b0, *b1;
+    cd *fpad, *facc, *s0, *s1, *fphi;
 };
 
-static CurveletBufs carve_curvelet(const Plan *P, void *ws, size_t ws_bytes) {
-    size_t b0 = 0, b1 = 0;
-    for (const ScaleRt &S : P->scales) {
-        const ScaleGeom &g = S.g;
-        b0 = std::max({b0, (size_t)g.L * g.L * g.Nep, (size_t)g.L * g.Nm * (g.h + 1)});
-        b1 = std::max({b1, (size_t)g.L * g.L * g.Nep, (size_t)P->ngroups * g.L * g.L});
-    }
+static CurveletBufs carve_curvelet(const Plan *P, int precision, void *ws, size_t ws_bytes) {
+    size_t b0, b1;
+    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, P->ngroups, &b0, &b1);
+    const size_t esz = precision == CVL_FP64 ? 16 : 8;
     Carver cv{(char *)ws, ws_bytes};
     CurveletBufs B;
-    B.b0 = cv.take<cd>(b0);
-    B.b1 = cv.take<cd>(b1);
+    B.b0 = cv.take<char>(b0 * esz);
+    B.b1 = cv.take<char>(b1 * esz);
     const size_t L2 = (size_t)P->L * P->L;
     B.fpad = cv.take<cd>(L2);
     B.facc = cv.take<cd>(L2);
@@ -833,6 +839,61 @@ static CurveletBufs carve_curvelet(const Plan *P, void *ws, size_t ws_bytes) {
     B.s1 = cv.take<cd>(L2);
     B.fphi = cv.take<cd>((size_t)P->Lphi * P->Lphi);
     return B;
+}
+
+// Analysis of one scale from the padded harmonic coefficients B.fpad.
+static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                              const CurveletBufs &B, void *grid_out, hipStream_t st) {
+    const ScaleGeom &g = S.g;
+    const int L = P->L;
+    if (precision != CVL_FP64) {
+        cf *grid = (cf *)grid_out;
+        cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
+        LAUNCH(ST_CONTRACT_INV,
+               launch_contract_inv_mx(precision, g, L, ctx->delta, B.fpad, S.psi, b0, st));
+        LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Cinv,
+                                                 S.betaf.Sinv, b0, b1, st));
+        LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
+        LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
+        return CVL_OK;
+    }
+    cd *grid = (cd *)grid_out;
+    cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
+    LAUNCH(ST_CONTRACT_INV, launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, b0, st));
+    LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Cinv,
+                                         S.beta.Sinv, b0, b1, st));
+    LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full, b1, b0, st));
+    LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, b0, grid, st));
+    return CVL_OK;
+}
+
+// Synthesis of one scale: adds f^(j)_lm into the padded accumulator B.facc.
+static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                               const CurveletBufs &B, const void *grid_in, hipStream_t st) {
+    const ScaleGeom &g = S.g;
+    const int L = P->L;
+    if (precision != CVL_FP64) {
+        const cf *grid = (const cf *)grid_in;
+        cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
+        LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full_f, grid, b0, st));
+        LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
+        LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Qp,
+                                                 S.betaf.Qs, b1, b0, st));
+        LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd_mx(precision, g, L, ctx->delta, b0, S.psi,
+                                                       b1, P->ngroups, st));
+        LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, P->ngroups, B.facc, st));
+        return CVL_OK;
+    }
+    const cd *grid = (const cd *)grid_in;
+    cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
+    LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, b0, st));
+    LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, b0, b1, st));
+    LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
+                                         S.beta.Qs, b1, b0, st));
+    LAUNCH(ST_CONTRACT_FWD,
+           launch_contract_fwd(g, L, ctx->delta, b0, S.psi, b1, P->ngroups, st));
+    LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, b1, P->ngroups, B.facc, st));
+    return CVL_OK;
 }
 
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *maps,
@@ -847,7 +908,7 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
     const int L = P->L, Lp = P->Lphi;
     for (int bi = 0; bi < batch; ++bi) {
         const double *map = maps + (size_t)bi * L * (2 * L - 1);
@@ -855,28 +916,10 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         if ((rc = sht_forward_run(ctx, SL, map, B.fpad, L, B.s0, B.s1, st))) return rc;
         LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
         if ((rc = sht_inverse_run(ctx, SP, B.fphi, Lp, smap, B.s0, B.s1, st))) return rc;
-        for (int s = 0; s < nJ; ++s) {
-            const ScaleRt &S = P->scales[s];
-            const ScaleGeom &g = S.g;
-            if (p->precision != CVL_FP64) {
-                cf *grid = (cf *)grids[(size_t)bi * nJ + s];
-                cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
-                LAUNCH(ST_CONTRACT_INV, launch_contract_inv_mx(p->precision, g, L, ctx->delta,
-                                                               B.fpad, S.psi, b0, st));
-                LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep,
-                                                         S.betaf.Cinv, S.betaf.Sinv, b0, b1, st));
-                LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
-                LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
-                continue;
-            }
-            cd *grid = (cd *)grids[(size_t)bi * nJ + s];
-            LAUNCH(ST_CONTRACT_INV,
-                   launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, B.b0, st));
-            LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0,
-                                                 S.beta.Cinv, S.beta.Sinv, B.b0, B.b1, st));
-            LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full, B.b1, B.b0, st));
-            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, B.b0, grid, st));
-        }
+        for (int s = 0; s < nJ; ++s)
+            if ((rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, B,
+                                         grids[(size_t)bi * nJ + s], st)))
+                return rc;
     }
     return CVL_OK;
 }
@@ -893,41 +936,90 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
         if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
     const int L = P->L, Lp = P->Lphi;
     for (int bi = 0; bi < batch; ++bi) {
         const double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
         double *map = maps + (size_t)bi * L * (2 * L - 1);
         LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
-        for (int s = 0; s < nJ; ++s) {
-            const ScaleRt &S = P->scales[s];
-            const ScaleGeom &g = S.g;
-            if (p->precision != CVL_FP64) {
-                const cf *grid = (const cf *)grids[(size_t)bi * nJ + s];
-                cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
-                LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full_f, grid, b0, st));
-                LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
-                LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep,
-                                                         S.betaf.Qp, S.betaf.Qs, b1, b0, st));
-                LAUNCH(ST_CONTRACT_FWD,
-                       launch_contract_fwd_mx(p->precision, g, L, ctx->delta, b0, S.psi, b1,
-                                              P->ngroups, st));
-                LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, P->ngroups, B.facc, st));
-                continue;
-            }
-            const cd *grid = (const cd *)grids[(size_t)bi * nJ + s];
-            LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, B.b0, st));
-            LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, B.b0, B.b1, st));
-            LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
-                                                 S.beta.Qs, B.b1, B.b0, st));
-            LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd(g, L, ctx->delta, B.b0, S.psi, B.b1,
-                                                        P->ngroups, st));
-            LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, B.b1, P->ngroups, B.facc, st));
-        }
+        for (int s = 0; s < nJ; ++s)
+            if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, B,
+                                          grids[(size_t)bi * nJ + s], st)))
+                return rc;
         if ((rc = sht_forward_run(ctx, SP, smap, B.fphi, Lp, B.s0, B.s1, st))) return rc;
         LAUNCH(ST_MISC, launch_scale_flm(Lp, Lp, L, P->phifac, B.fphi, B.facc, 1, st));
         if ((rc = sht_inverse_run(ctx, SL, B.facc, L, map, B.s0, B.s1, st))) return rc;
     }
+    return CVL_OK;
+}
+
+// ---- streaming interface: one scale at a time, harmonic-space accumulator ----
+static int check_scale_call(cvl_ctx *ctx, const cvl_params *p, int j, const void *a,
+                            const void *b, void *ws, size_t ws_bytes, Plan **P, int *s) {
+    int rc = check_curvelet_call(ctx, p, 1, a, b, a, ws, ws_bytes, P);
+    if (rc) return rc;
+    if (j < (*P)->J0 || j > (*P)->J)
+        return fail(CVL_EINVAL, "scale j=%d outside [J0=%d, J=%d]", j, (*P)->J0, (*P)->J);
+    if (s) *s = j - (*P)->J0;
+    return CVL_OK;
+}
+
+int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const cvl_c128 *flm,
+                                void *grid, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    Plan *P;
+    int s, rc = check_scale_call(ctx, p, j, flm, grid, ws, ws_bytes, &P, &s);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    LAUNCH(ST_MISC, launch_flm_pack(P->L, (const cd *)flm, B.fpad, st));
+    return analysis_scale_run(ctx, P, P->scales[s], p->precision, B, grid, st);
+}
+
+int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const void *grid,
+                                 cvl_c128 *flm_acc, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    Plan *P;
+    int s, rc = check_scale_call(ctx, p, j, grid, flm_acc, ws, ws_bytes, &P, &s);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    const int L = P->L;
+    LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
+    if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, B, grid, st))) return rc;
+    LAUNCH(ST_MISC, launch_flm_unpack(L, B.facc, (cd *)flm_acc, 1, st));
+    return CVL_OK;
+}
+
+int cvl_curvelet_scaling_analysis(cvl_ctx *ctx, const cvl_params *p, const cvl_c128 *flm,
+                                  double *scal_map, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    Plan *P;
+    int rc = check_curvelet_call(ctx, p, 1, flm, scal_map, flm, ws, ws_bytes, &P);
+    if (rc) return rc;
+    ShtRt *SP = ctx->sht[P->Lphi].get();
+    hipStream_t st = (hipStream_t)stream;
+    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    const int L = P->L, Lp = P->Lphi;
+    LAUNCH(ST_MISC, launch_flm_pack(L, (const cd *)flm, B.fpad, st));
+    LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
+    return sht_inverse_run(ctx, SP, B.fphi, Lp, scal_map, B.s0, B.s1, st);
+}
+
+int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p, const double *scal_map,
+                                   cvl_c128 *flm_acc, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    Plan *P;
+    int rc = check_curvelet_call(ctx, p, 1, scal_map, flm_acc, scal_map, ws, ws_bytes, &P);
+    if (rc) return rc;
+    ShtRt *SP = ctx->sht[P->Lphi].get();
+    hipStream_t st = (hipStream_t)stream;
+    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    const int L = P->L, Lp = P->Lphi;
+    if ((rc = sht_forward_run(ctx, SP, scal_map, B.fphi, Lp, B.s0, B.s1, st))) return rc;
+    LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
+    LAUNCH(ST_MISC, launch_scale_flm(Lp, Lp, L, P->phifac, B.fphi, B.facc, 1, st));
+    LAUNCH(ST_MISC, launch_flm_unpack(L, B.facc, (cd *)flm_acc, 1, st));
     return CVL_OK;
 }
 

@@ -159,7 +159,7 @@ hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int mode_fwd, const doub
                             const double *Aodd, const cd *in, cd *out, hipStream_t st);
 hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z, cd *fpad,
                                 hipStream_t st);
-hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, hipStream_t st);
+hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, int accumulate, hipStream_t st);
 hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st);
 hipError_t launch_scale_flm(int Lphi, int Lsrc, int Ldst, const double *fac, const cd *src,
                             cd *dst, int accumulate, hipStream_t st);

@@ -713,18 +713,18 @@ hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int, const double *Aeven
 }
 
 // f (flat l^2+l+m) <-> fpad [l][m], m >= 0.
-__global__ void k_flm_unpack(int L, const cd *__restrict__ fpad, cd *__restrict__ flm) {
+// flm[l^2 + l + m] (=|+=) fpad[l][|m|] (negative m by the reality condition).
+__global__ void k_flm_unpack(int L, const cd *__restrict__ fpad, cd *__restrict__ flm,
+                             int accumulate) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= L * L) return;
     int l = (int)sqrt((double)idx);
     while (l * l > idx) --l;
     while ((l + 1) * (l + 1) <= idx) ++l;
     const int m = idx - l * l - l;
-    const cd v = fpad[(size_t)l * L + (m < 0 ? -m : m)];
-    if (m >= 0)
-        flm[idx] = v;
-    else
-        flm[idx] = cscale(cconj(v), (m & 1) ? -1.0 : 1.0);
+    cd v = fpad[(size_t)l * L + (m < 0 ? -m : m)];
+    if (m < 0) v = cscale(cconj(v), (m & 1) ? -1.0 : 1.0);
+    flm[idx] = accumulate ? cadd(flm[idx], v) : v;
 }
 __global__ void k_flm_pack(int L, const cd *__restrict__ flm, cd *__restrict__ fpad) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -732,8 +732,9 @@ __global__ void k_flm_pack(int L, const cd *__restrict__ flm, cd *__restrict__ f
     const int l = idx / L, m = idx % L;
     fpad[idx] = (m <= l) ? flm[(size_t)l * l + l + m] : cd{0.0, 0.0};
 }
-hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, hipStream_t st) {
-    hipLaunchKernelGGL(k_flm_unpack, dim3((L * L + 255) / 256), dim3(256), 0, st, L, fpad, flm);
+hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_flm_unpack, dim3((L * L + 255) / 256), dim3(256), 0, st, L, fpad, flm,
+                       accumulate);
     return hipGetLastError();
 }
 hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st) {

@@ -55,3 +55,25 @@ def serving_trace(n_requests=1024, bandlimits=(64, 128, 256, 512), rate_hz=100.0
     t = np.cumsum(gaps) - gaps[0]
     Ls = rs.choice(np.asarray(bandlimits), size=n_requests)
     return t, Ls
+
+
+def point_sources(L, n=64, seed=7):
+    """n point sources on distinct MW sample positions of a band-limit-L map.
+
+    Returns (t, p, amp): theta index t in [0, L), phi index p in [0, 2L-1) and
+    amplitude amp ~ U[0.5, 1.5] of each source, drawn from
+    ``numpy.random.default_rng(seed)`` (positions first, then amplitudes)."""
+    rng = np.random.default_rng(seed)
+    npix = L * (2 * L - 1)
+    flat = rng.choice(npix, size=n, replace=False)
+    amp = rng.uniform(0.5, 1.5, size=n)
+    return flat // (2 * L - 1), flat % (2 * L - 1), amp
+
+
+def add_point_sources(fmap, sources):
+    """fmap (L x (2L-1) samples, modified in place) plus a spike of height
+    amp at each source's sample; returns fmap.  The result is not band-limited:
+    consumers project it onto band-limit L with their own SHT pair."""
+    t, p, amp = sources
+    np.add.at(fmap, (t, p), amp)
+    return fmap
