@@ -39,7 +39,12 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kGroups = 32;  // m' groups of the synthesis contraction
+// The synthesis contraction splits the m' sum into groups (one work-group
+// column each, partial sums reduced in a fixed order afterwards).  The number
+// of groups per scale is chosen so that the launch has about kFwdWGs
+// work-groups, with at least kMinGroups groups and at most L_j (one m' each).
+constexpr int kFwdWGs = 1024;
+constexpr int kMinGroups = 32;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Stage {
@@ -101,6 +106,7 @@ struct ScaleRt {
     BluesteinDev inv_full, fwd_full, fwd_half;
     BetaTabsF betaf;
     BluesteinF inv_full_f, fwd_full_f;
+    int ngroups;  // m' groups of the synthesis contraction
 };
 
 struct Plan {
@@ -108,7 +114,6 @@ struct Plan {
     double lambda;
     std::vector<ScaleRt> scales;
     double *phifac;  // [Lphi]: sqrt(4pi/(2l+1)) Phi_l0
-    int ngroups;
 };
 
 struct ShtRt {
@@ -352,13 +357,24 @@ ScaleGeom geom_of(int Lj) {
 }
 
 // Element counts of the two cube-sized workspace buffers of a curvelet call.
-void curvelet_buf_elems(int L, double lam, int J0, int J, int ngroups, size_t *b0, size_t *b1) {
+// m' groups of the synthesis contraction of a scale (see kFwdWGs).
+int fwd_groups(const ScaleGeom &g) {
+    const int mt = (g.L + 63) / 64;
+    const int nl = g.lhi >= g.llo ? g.lhi - (g.llo & ~1) + 1 : 1;
+    const int lt = (nl + 63) / 64;
+    int want = (kFwdWGs + mt * lt - 1) / (mt * lt);
+    if (want < kMinGroups) want = kMinGroups;
+    const int gsz = (g.L + want - 1) / want;
+    return (g.L + gsz - 1) / gsz;
+}
+
+void curvelet_buf_elems(int L, double lam, int J0, int J, size_t *b0, size_t *b1) {
     *b0 = *b1 = 0;
     for (int j = J0; j <= J; ++j) {
         ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
         size_t cube = (size_t)g.L * g.L * g.Nep;
         size_t w2 = (size_t)g.L * g.Nm * (g.h + 1);
-        size_t part = (size_t)ngroups * g.L * g.L;
+        size_t part = (size_t)g.L * g.L * g.L;  // at most L_j groups
         *b0 = std::max({*b0, cube, w2});
         *b1 = std::max({*b1, cube, part});
     }
@@ -366,9 +382,9 @@ void curvelet_buf_elems(int L, double lam, int J0, int J, int ngroups, size_t *b
 
 // Workspace bytes of a curvelet call: two cube buffers (complex128, or
 // complex64 in reduced precision) and five L x L complex128 planes.
-size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int ngroups, int precision) {
+size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision) {
     size_t b0, b1;
-    curvelet_buf_elems(L, lam, J0, J, ngroups, &b0, &b1);
+    curvelet_buf_elems(L, lam, J0, J, &b0, &b1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     const int Lphi = scaling_bandlimit(L, lam, J0);
     size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
@@ -393,7 +409,6 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
     P->J = J;
     P->lambda = p->lambda;
     P->Lphi = scaling_bandlimit(p->L, p->lambda, p->J0);
-    P->ngroups = kGroups;
     const int L = p->L;
     std::vector<double> kap = host::kappa_table(L, p->lambda, p->J0, J);
     std::vector<double> phi = host::phi_table(L, p->lambda, p->J0);
@@ -412,6 +427,7 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
             }
         S.g.llo = llo;
         S.g.lhi = lhi;
+        S.ngroups = fwd_groups(S.g);
         const int h = S.g.h;
         std::vector<double> psi((size_t)Lj * (h + 1), 0.0);
         for (int l = 0; l < Lj; ++l)
@@ -616,7 +632,7 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
     if (rc) return rc;
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, kGroups, p->precision);
+    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision);
     return CVL_OK;
 }
 
@@ -808,8 +824,7 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
     if (!a || !b || !grids || !ws) return fail(CVL_EINVAL, "NULL pointer argument");
     if ((rc = set_device(ctx))) return rc;
     if ((rc = get_plan(ctx, p, P))) return rc;
-    const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, (*P)->ngroups,
-                                          p->precision);
+    const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, p->precision);
     if (ws_bytes < need)
         return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -826,7 +841,7 @@ struct CurveletBufs {
 
 static CurveletBufs carve_curvelet(const Plan *P, int precision, void *ws, size_t ws_bytes) {
     size_t b0, b1;
-    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, P->ngroups, &b0, &b1);
+    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, &b0, &b1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     Carver cv{(char *)ws, ws_bytes};
     CurveletBufs B;
@@ -880,8 +895,8 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
         LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Qp,
                                                  S.betaf.Qs, b1, b0, st));
         LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd_mx(precision, g, L, ctx->delta, b0, S.psi,
-                                                       b1, P->ngroups, st));
-        LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, P->ngroups, B.facc, st));
+                                                       b1, S.ngroups, st));
+        LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, S.ngroups, B.facc, st));
         return CVL_OK;
     }
     const cd *grid = (const cd *)grid_in;
@@ -891,8 +906,8 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
     LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
                                          S.beta.Qs, b1, b0, st));
     LAUNCH(ST_CONTRACT_FWD,
-           launch_contract_fwd(g, L, ctx->delta, b0, S.psi, b1, P->ngroups, st));
-    LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, b1, P->ngroups, B.facc, st));
+           launch_contract_fwd(g, L, ctx->delta, b0, S.psi, b1, S.ngroups, st));
+    LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, b1, S.ngroups, B.facc, st));
     return CVL_OK;
 }
 

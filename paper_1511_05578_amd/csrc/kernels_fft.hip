@@ -23,6 +23,17 @@ namespace cvl {
 
 enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
 
+// Work-groups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// index.  Lines of neighbouring work-groups share cache lines (interleaved
+// lines, e.g. neighbouring k at the same m), so the logical group index is
+// remapped to give each XCD a contiguous range of groups: hardware index b
+// runs on XCD b % 8 and processes group start(b % 8) + b / 8.  A bijection of
+// [0, n) for any n.
+__device__ __forceinline__ int xcd_group(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // In-place Stockham FFT of one LDS line (forward, tw[x] = e^{-2 pi i x / P}).
 // Radix-4 stages first, then one radix-2 stage when log2 P is odd.  Every
 // thread of the work-group must call it (it synchronises the work-group).
@@ -102,7 +113,7 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BlueT<type
     constexpr int TPL = 256 / LINES;
     const int tid = threadIdx.x;
     const int li = tid / TPL, lane = tid % TPL;
-    const int line0 = blockIdx.x * LINES;
+    const int line0 = xcd_group(blockIdx.x, gridDim.x) * LINES;
     for (int idx = tid; idx < LINES * P; idx += 256) {
         int l, t;
         if (IN_IL) {
@@ -378,7 +389,7 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     extern __shared__ __align__(16) char smem_raw[];
     R *smem_d = reinterpret_cast<R *>(smem_raw);
     const int li = threadIdx.x / T, tid = threadIdx.x % T;
-    const int line0 = blockIdx.x * LINES;
+    const int line0 = xcd_group(blockIdx.x, gridDim.x) * LINES;
     const int line = line0 + li;
     R *lds = smem_d + li * LW;
     C v[16];

@@ -178,7 +178,8 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
 // m, so one parity per tile).  Tile 128 rows x 64 real columns x 16 k; wave w
 // owns rows [32w, 32w+32) as 2 x 4 blocks of v_mfma_f64_16x16x4f64, whose lane
 // layout is A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].  The factor i of
-// odd parity is applied while staging B: (re, im) -> (-im, re).
+// odd parity is applied while staging B: (re, im) -> (-im, re).  The next K
+// tile is loaded into registers while the current one is multiplied.
 typedef double cvl_d4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_beta_mfma(int M, int K, int ncols, int Nep,
@@ -200,39 +201,47 @@ __global__ __launch_bounds__(256) void k_beta_mfma(int M, int K, int ncols, int 
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = cvl_d4{0.0, 0.0, 0.0, 0.0};
     const int lr = lane & 15, lk = lane >> 4;
+    // Next K tile held in registers while the current one is multiplied.
+    double ra[8];
+    double2 rb[2];
+    const int kkb = tid >> 4, ccb = (tid & 15) * 4;  // 4 doubles = 2 complex
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int r = r0 + (idx >> 4), k = k0 + (idx & 15);
+            ra[q] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.0;
+        }
+        const int k = k0 + kkb;
+        const size_t col = 2 * (size_t)c0 + ccb;
+        rb[0] = make_double2(0.0, 0.0);
+        rb[1] = make_double2(0.0, 0.0);
+        if (k < K && col + 3 < ld) {
+            const double2 *src = reinterpret_cast<const double2 *>(in + (size_t)k * ld + col);
+            rb[0] = src[0];
+            rb[1] = src[1];
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int idx = tid + 256 * q;
-            const int rr = idx >> 4, kk = idx & 15;
-            const int r = r0 + rr, k = k0 + kk;
-            As[rr][kk] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.0;
+            As[idx >> 4][idx & 15] = ra[q];
         }
-        {
-            const int kk = tid >> 4, cc = (tid & 15) * 4;  // 4 doubles = 2 complex
-            const int k = k0 + kk;
-            const size_t col = 2 * (size_t)c0 + cc;
-            double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
-            if (k < K && col + 3 < ld) {
-                const double *src = in + (size_t)k * ld + col;
-                x0 = src[0];
-                x1 = src[1];
-                x2 = src[2];
-                x3 = src[3];
-            }
-            if (par) {
-                Bs[kk][cc] = -x1;
-                Bs[kk][cc + 1] = x0;
-                Bs[kk][cc + 2] = -x3;
-                Bs[kk][cc + 3] = x2;
-            } else {
-                Bs[kk][cc] = x0;
-                Bs[kk][cc + 1] = x1;
-                Bs[kk][cc + 2] = x2;
-                Bs[kk][cc + 3] = x3;
-            }
+        if (par) {
+            Bs[kkb][ccb] = -rb[0].y;
+            Bs[kkb][ccb + 1] = rb[0].x;
+            Bs[kkb][ccb + 2] = -rb[1].y;
+            Bs[kkb][ccb + 3] = rb[1].x;
+        } else {
+            Bs[kkb][ccb] = rb[0].x;
+            Bs[kkb][ccb + 1] = rb[0].y;
+            Bs[kkb][ccb + 2] = rb[1].x;
+            Bs[kkb][ccb + 3] = rb[1].y;
         }
         __syncthreads();
+        if (k0 + 16 < K) fetch(k0 + 16);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int k = 4 * ks + lk;

@@ -66,7 +66,8 @@ __device__ __forceinline__ f4v mma32(const Op<PREC_BF16X3> &a, const Op<PREC_BF1
 // Parity-folded beta stage in FP32 (curvelet layout, Nep % 32 == 0):
 //   out[r][c] = (i^par(c)) sum_k A^{par(c)}[r][k] in[k][c].
 // Tile 128 rows x 64 real columns x 32 k; wave w owns rows [32w, 32w+32) as
-// 2 x 4 blocks of v_mfma_f32_16x16x4_f32.
+// 2 x 4 blocks of v_mfma_f32_16x16x4_f32.  The next K tile is loaded into
+// registers while the current one is multiplied.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, int Nep,
                                                        const float *__restrict__ Ae,
@@ -87,22 +88,37 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     const int li = lane & 15, lq = lane >> 4;
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    // Next K tile held in registers while the current one is multiplied.
+    float ra[16];
+    float4 rb[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int idx = tid + 256 * q;
-            const int rr = idx >> 5, kk = idx & 31;
-            const int r = r0 + rr, k = k0 + kk;
-            As[rr][kk] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.f;
+            const int r = r0 + (idx >> 5), k = k0 + (idx & 31);
+            ra[q] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.f;
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int idx = tid + 256 * q;
-            const int kk = idx >> 4, cc = (idx & 15) * 4;  // 4 floats = 2 complex
-            const int k = k0 + kk;
-            const size_t col = 2 * (size_t)c0 + cc;
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < K && col + 3 < ld) x = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
+            const int k = k0 + (idx >> 4);
+            const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
+            rb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < K && col + 3 < ld) rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = tid + 256 * q;
+            As[idx >> 5][idx & 31] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx >> 4, cc = (idx & 15) * 4;
+            const float4 x = rb[q];
             if (par) {
                 Bs[kk][cc] = -x.y;
                 Bs[kk][cc + 1] = x.x;
@@ -116,6 +132,7 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
             }
         }
         __syncthreads();
+        if (k0 + 32 < K) fetch(k0 + 32);
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
             const int k = 4 * ks + lq;
