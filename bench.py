@@ -57,20 +57,21 @@ def scale_geoms(L, lam=2.0, J0=2):
 
 
 def stage_models(L, lam=2.0, J0=2, B=16.0):
-    """Algorithmic bytes / flops per round trip of each kernel stage.
+    """Algorithmic bytes / flops of each kernel stage per round trip of one
+    map, keyed (stage, L_j): one launch per scale, scales of equal L_j summed.
 
     bytes: each stage's input read once and output written once (B = 16 bytes
     per complex128, 8 per complex64).  flops: contractions 4 per
-    (l, m, m', n>=0) term of the
-    parity-folded sums (complex x real multiply-add); beta GEMMs 2 per
-    multiply-add of the L_j x L_j real matrix on the 2*L_j*Ne real columns;
-    DFT stages 5 n log2 n per complex line of length n = 2L_j - 1.
+    (l, m, m', n>=0) term of the parity-folded sums (complex x real
+    multiply-add); beta GEMMs 2 per multiply-add of the L_j x L_j real matrix
+    on the 2*L_j*Ne real columns; DFT stages 5 n log2 n per complex line of
+    length n = 2L_j - 1.
     """
     m = {}
 
-    def add(name, nbytes, flops):
-        b, f = m.get(name, (0.0, 0.0))
-        m[name] = (b + nbytes, f + flops)
+    def add(name, Lj, nbytes, flops):
+        b, f, n = m.get((name, Lj), (0.0, 0.0, 0))
+        m[(name, Lj)] = (b + nbytes, f + flops, n + 1)
 
     for g in scale_geoms(L, lam, J0):
         Lj, Nm, h, Ne = g["L"], g["Nm"], g["h"], g["Ne"]
@@ -80,15 +81,82 @@ def stage_models(L, lam=2.0, J0=2, B=16.0):
         grid = Nm * Lj * Nm * B
         v1 = Lj * Nm * Ne * B
         fft = 5.0 * Nm * math.log2(Nm)
-        add("contract_inv", cube, 4.0 * terms)
-        add("beta_gemm_inv", 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
-        add("alpha_dft_inv", cube + w2, Lj * (h + 1) * fft)
-        add("gamma_dft_inv", w2 + grid, Nm * Lj * fft)
-        add("gamma_dft_fwd", grid + v1, Nm * Lj * fft)
-        add("alpha_dft_fwd", v1 + cube, Lj * Ne * fft)
-        add("beta_gemm_fwd", 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
-        add("contract_fwd", cube, 4.0 * terms)
+        add("contract_inv", Lj, cube, 4.0 * terms)
+        add("beta_gemm_inv", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
+        add("alpha_dft_inv", Lj, cube + w2, Lj * (h + 1) * fft)
+        add("gamma_dft_inv", Lj, w2 + grid, Nm * Lj * fft)
+        add("gamma_dft_fwd", Lj, grid + v1, Nm * Lj * fft)
+        add("alpha_dft_fwd", Lj, v1 + cube, Lj * Ne * fft)
+        add("beta_gemm_fwd", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
+        add("contract_fwd", Lj, cube, 4.0 * terms)
     return m
+
+
+def bluestein_size(Lj):
+    n = 2 * (2 * Lj - 1) - 1
+    P = 8
+    while P < n:
+        P *= 2
+    return P
+
+
+def kernel_symbol(stage, Lj, prec):
+    """HIP kernel (template instance) that runs a stage at band-limit L_j."""
+    c = "cd" if prec == "fp64" else "cf"
+    P = bluestein_size(Lj)
+    io = {"alpha_dft_inv": "InvAlphaIO", "alpha_dft_fwd": "FwdAlphaIO",
+          "gamma_dft_inv": "InvGammaPackIO" if P >= 256 else "InvGammaIO",
+          "gamma_dft_fwd": "FwdGammaPackIO" if P >= 256 else "FwdGammaIO"}
+    if stage in io:
+        eng = "k_blue_r16<%d, %s<%s> >" % (P, io[stage], c) if P >= 256 else \
+              "k_bluestein<%d, ..., %s<%s> >" % (P, io[stage], c)
+        return eng
+    mode = {"fp64": "", "fp32": "<1>", "bf16x3": "<2>"}[prec]
+    if stage.startswith("beta"):
+        return "k_beta_mfma" if prec == "fp64" else "k_beta_mfma_f32"
+    if stage == "contract_inv":
+        return "k_contract_inv" if prec == "fp64" else "k_contract_inv_mx" + mode
+    if stage == "contract_fwd":
+        return "k_contract_fwd_mfma" if prec == "fp64" else "k_contract_fwd_mx" + mode
+    return stage
+
+
+def source_fingerprint():
+    """sha1 of the library sources: counter figures taken from another build
+    do not describe this one."""
+    import hashlib
+    hsh = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_1511_05578_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            hsh.update(name.encode() + f.read())
+    return hsh.hexdigest()[:16]
+
+
+def recorded_traffic(workload_key, kernel):
+    """HBM bytes per launch of `kernel` from a committed counter summary of
+    this workload and this source fingerprint, else None."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    fp = source_fingerprint()
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if not line.startswith("TRAFFIC_JSON "):
+                    continue
+                try:
+                    rec = json.loads(line[len("TRAFFIC_JSON "):])
+                except ValueError:
+                    continue
+                if rec.get("workload") != workload_key or rec.get("source") != fp:
+                    continue
+                k = rec.get("kernels", {}).get(kernel)
+                if k:
+                    return k["fetch_bytes"] + k["write_bytes"]
+    return None
 
 
 def grid_bytes(L, lam=2.0, J0=2, B=16.0):
@@ -152,6 +220,9 @@ def main():
     ap.add_argument("--stream", action="store_true",
                     help="one scale at a time through the streaming interface (batch 1)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="after timing, copy BYTES of device memory once (a plain copy kernel "
+                         "of known size, for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -206,6 +277,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = ctx.profile_read()
+    detail = ctx.profile_read_detail()
     ctx.profile_enable(False)
     print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
 
@@ -229,27 +301,38 @@ def main():
     ms = dt * 1e3 / args.steps
     models = stage_models(L, lam, J0, EB)
     stages = {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in prof.items() if v[0]}
-    top = max((k for k in stages if k in models), key=lambda k: stages[k]["ms_per_step"])
-    launches_per_step = stages[top]["launches"] / args.steps
-    t_top = stages[top]["ms_per_step"] * 1e-3 / launches_per_step  # s per launch
-    nb, nf = models[top]
-    nb *= NB
-    nf *= NB
-    bytes_per_launch = nb / launches_per_step
-    flops_per_launch = nf / launches_per_step
-    peak_tf = stage_peak(top, prec)
+    # dominant kernel: the (stage, L_j) pair with the most device time
+    top = max((k for k in detail if k in models), key=lambda k: detail[k][1])
+    n_launch, t_ms = detail[top]
+    t_top = t_ms * 1e-3 / n_launch  # s per launch
+    nb, nf, nscales = models[top]
+    bytes_per_launch = nb / nscales  # one launch per scale per map
+    flops_per_launch = nf / nscales
+    peak_tf = stage_peak(top[0], prec)
     ai = nf / max(nb, 1.0)
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai < ridge:
         roof = {"bound": "hbm", "achieved": bytes_per_launch / t_top / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     else:
-        roof = {"bound": "mfma" if top.startswith(("contract", "beta")) else "alu",
+        roof = {"bound": "mfma" if top[0].startswith(("contract", "beta")) else "alu",
                 "achieved": flops_per_launch / t_top / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = top
+    wkey = "L%d_b%d_%s%s%s" % (L, NB, prec, "_stream" if args.stream else "",
+                               "_ps%d" % args.point_sources if args.point_sources else "")
+    sym = kernel_symbol(top[0], top[1], prec)
+    roof["traffic"] = recorded_traffic(wkey, sym)
+    roof["kernel"] = sym
+    roof["stage"] = top[0]
+    roof["L_j"] = top[1]
+    roof["launch_ms"] = t_top * 1e3
     roof["algorithmic_per_launch"] = {"bytes": bytes_per_launch, "flops": flops_per_launch}
+    if args.copy_calibration:
+        x = torch.ones(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     gname = "complex128" if prec == "fp64" else "complex64"
     work = ("%d real spin-0 map%s%s, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, %s grids%s, %s, "
@@ -277,9 +360,11 @@ def main():
                    "precision": prec, "stream": bool(args.stream),
                    "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, EB)},
         "round_trip_rel_l2": err,
+        "source": source_fingerprint(),
         "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, EB) / (HBM_PEAK_GBS * 1e9) * 1e3,
         "roofline": roof,
         "stages": stages,
+        "stages_by_bandlimit": {"%s@%d" % k: round(v[1] / args.steps, 4) for k, v in sorted(detail.items())},
     }
     if vs64 is not None:
         out["vs_fp64_path"] = vs64

@@ -212,6 +212,12 @@ int cvl_profile_enable(cvl_ctx *ctx, int on);
 int cvl_profile_read(cvl_ctx *ctx, int max, int *n, const char **names,
                      int *launches, double *ms);
 
+/* The same times split by (stage, band-limit): row i < min(*n, max) is stage
+ * index stage[i] (names as in cvl_profile_read) at band-limit bandlimit[i]
+ * (the scale's L_j, or the SHT's L), with its launch count and milliseconds. */
+int cvl_profile_read_detail(cvl_ctx *ctx, int max, int *n, int *stage,
+                            int *bandlimit, int *launches, double *ms);
+
 /* Copy block l of the resident Delta table to host memory (synchronous):
  * out[m' * (l+1) + m] = Delta^l_{m'm} = d^l_{m'm}(pi/2), 0 <= m', m <= l < L_max. */
 int cvl_delta_block(cvl_ctx *ctx, int l, double *out);

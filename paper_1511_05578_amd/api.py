@@ -70,6 +70,8 @@ SIGNATURES = {
     "cvl_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "cvl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p,
                                         ctypes.POINTER(ctypes.c_char_p), _c_int_p, _c_double_p]),
+    "cvl_profile_read_detail": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p, _c_int_p,
+                                                _c_int_p, _c_int_p, _c_double_p]),
     "cvl_delta_block": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p]),
     "cvl_last_error": (ctypes.c_char_p, []),
 }
@@ -387,3 +389,15 @@ class Context:
         ms = (ctypes.c_double * mx)()
         _check(lib.cvl_profile_read(self.h, mx, ctypes.byref(n), names, launches, ms))
         return {names[i].decode(): (launches[i], ms[i]) for i in range(min(n.value, mx))}
+
+    def profile_read_detail(self):
+        """{(stage name, band-limit): (launches, ms)} of the timed launches."""
+        stage_names = list(self.profile_read().keys())
+        n = ctypes.c_int()
+        mx = 512
+        st = (ctypes.c_int * mx)()
+        bl = (ctypes.c_int * mx)()
+        launches = (ctypes.c_int * mx)()
+        ms = (ctypes.c_double * mx)()
+        _check(lib.cvl_profile_read_detail(self.h, mx, ctypes.byref(n), st, bl, launches, ms))
+        return {(stage_names[st[i]], bl[i]): (launches[i], ms[i]) for i in range(min(n.value, mx))}

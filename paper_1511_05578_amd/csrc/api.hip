@@ -148,9 +148,10 @@ struct cvl_ctx {
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> pool;
-    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
+    std::vector<std::tuple<int, int, hipEvent_t, hipEvent_t>> rec;  // stage, tag, events
     double stage_ms[ST_COUNT] = {0};
     int stage_n[ST_COUNT] = {0};
+    std::map<std::pair<int, int>, std::pair<int, double>> detail;  // (stage, tag) -> (n, ms)
 };
 
 namespace {
@@ -473,12 +474,21 @@ int get_sht(cvl_ctx *c, int L, ShtRt **out) {
 }
 
 // ---- profiling ----
+// Band-limit of the scale (or SHT) whose kernels are being enqueued on this
+// thread; recorded with each timed launch.
+thread_local int g_tag = 0;
+struct TagScope {
+    int prev;
+    explicit TagScope(int t) : prev(g_tag) { g_tag = t; }
+    ~TagScope() { g_tag = prev; }
+};
+
 struct Prof {
     cvl_ctx *c;
     hipStream_t st;
-    int stage;
+    int stage, tag;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    Prof(cvl_ctx *c_, hipStream_t s, int stg) : c(c_), st(s), stage(stg) {
+    Prof(cvl_ctx *c_, hipStream_t s, int stg) : c(c_), st(s), stage(stg), tag(g_tag) {
         if (!c->prof) return;
         e0 = take();
         e1 = take();
@@ -499,7 +509,7 @@ struct Prof {
         if (!c->prof || !e0 || !e1) return;
         (void)hipEventRecord(e1, st);
         std::lock_guard<std::mutex> lk(c->mu);
-        c->rec.emplace_back(stage, e0, e1);
+        c->rec.emplace_back(stage, tag, e0, e1);
     }
 };
 
@@ -530,6 +540,7 @@ struct Carver {
 int sht_forward_run(cvl_ctx *ctx, ShtRt *S, const double *map, cd *fpad, int Lf, cd *F1,
                     cd *Zs, hipStream_t st) {
     const int L = S->L;
+    TagScope tag(L);
     LAUNCH(ST_SHT_PHI, launch_sht_fwd_phi(L, S->fwd, map, F1, st));
     LAUNCH(ST_SHT_THETA, launch_sht_theta(L, L, L, 1, S->beta.Qp, S->beta.Qs, F1, Zs, st));
     LAUNCH(ST_SHT_DELTA, launch_sht_fwd_delta(L, Lf, ctx->delta, Zs, fpad, st));
@@ -539,6 +550,7 @@ int sht_forward_run(cvl_ctx *ctx, ShtRt *S, const double *map, cd *fpad, int Lf,
 int sht_inverse_run(cvl_ctx *ctx, ShtRt *S, const cd *fpad, int Lf, double *map, cd *F,
                     cd *G, hipStream_t st) {
     const int L = S->L;
+    TagScope tag(L);
     LAUNCH(ST_SHT_DELTA, launch_sht_inv_delta(L, Lf, ctx->delta, fpad, F, st));
     LAUNCH(ST_SHT_THETA, launch_sht_theta(L, L, L, 0, S->beta.Cinv, S->beta.Sinv, F, G, st));
     LAUNCH(ST_SHT_PHI, launch_sht_inv_phi(L, S->inv, G, map, st));
@@ -593,8 +605,8 @@ void cvl_context_destroy(cvl_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &r : ctx->rec) {
-        (void)hipEventDestroy(std::get<1>(r));
         (void)hipEventDestroy(std::get<2>(r));
+        (void)hipEventDestroy(std::get<3>(r));
     }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -861,6 +873,7 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
                               const CurveletBufs &B, void *grid_out, hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
+    TagScope tag(g.L);
     if (precision != CVL_FP64) {
         cf *grid = (cf *)grid_out;
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
@@ -887,6 +900,7 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
                                const CurveletBufs &B, const void *grid_in, hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
+    TagScope tag(g.L);
     if (precision != CVL_FP64) {
         const cf *grid = (const cf *)grid_in;
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
@@ -1059,6 +1073,34 @@ int cvl_profile_enable(cvl_ctx *ctx, int on) {
         ctx->stage_ms[i] = 0;
         ctx->stage_n[i] = 0;
     }
+    ctx->detail.clear();
+    return CVL_OK;
+}
+
+// Waits for the recorded launches and adds their times to the totals.
+static int profile_drain(cvl_ctx *ctx) {
+    std::vector<std::tuple<int, int, hipEvent_t, hipEvent_t>> rec;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        rec.swap(ctx->rec);
+    }
+    for (auto &r : rec) {
+        hipEvent_t e0 = std::get<2>(r), e1 = std::get<3>(r);
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        const int stg = std::get<0>(r);
+        ctx->stage_ms[stg] += t;
+        ctx->stage_n[stg] += 1;
+        auto &d = ctx->detail[std::make_pair(stg, std::get<1>(r))];
+        d.first += 1;
+        d.second += t;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &r : rec) {
+        ctx->pool.push_back(std::get<2>(r));
+        ctx->pool.push_back(std::get<3>(r));
+    }
     return CVL_OK;
 }
 
@@ -1066,31 +1108,32 @@ int cvl_profile_read(cvl_ctx *ctx, int max, int *n, const char **names, int *lau
                      double *ms) {
     g_err.clear();
     if (!ctx || !n) return fail(CVL_EINVAL, "NULL argument");
-    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        rec.swap(ctx->rec);
-    }
-    for (auto &r : rec) {
-        hipEvent_t e0 = std::get<1>(r), e1 = std::get<2>(r);
-        HIP_TRY(hipEventSynchronize(e1));
-        float t = 0.f;
-        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-        ctx->stage_ms[std::get<0>(r)] += t;
-        ctx->stage_n[std::get<0>(r)] += 1;
-    }
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        for (auto &r : rec) {
-            ctx->pool.push_back(std::get<1>(r));
-            ctx->pool.push_back(std::get<2>(r));
-        }
-    }
+    int rc = profile_drain(ctx);
+    if (rc) return rc;
     *n = ST_COUNT;
     for (int i = 0; i < ST_COUNT && i < max; ++i) {
         if (names) names[i] = kStageNames[i];
         if (launches) launches[i] = ctx->stage_n[i];
         if (ms) ms[i] = ctx->stage_ms[i];
+    }
+    return CVL_OK;
+}
+
+int cvl_profile_read_detail(cvl_ctx *ctx, int max, int *n, int *stage, int *bandlimit,
+                            int *launches, double *ms) {
+    g_err.clear();
+    if (!ctx || !n) return fail(CVL_EINVAL, "NULL argument");
+    int rc = profile_drain(ctx);
+    if (rc) return rc;
+    *n = (int)ctx->detail.size();
+    int i = 0;
+    for (auto &kv : ctx->detail) {
+        if (i >= max) break;
+        if (stage) stage[i] = kv.first.first;
+        if (bandlimit) bandlimit[i] = kv.first.second;
+        if (launches) launches[i] = kv.second.first;
+        if (ms) ms[i] = kv.second.second;
+        ++i;
     }
     return CVL_OK;
 }
