@@ -57,23 +57,29 @@ def serving_trace(n_requests=1024, bandlimits=(64, 128, 256, 512), rate_hz=100.0
     return t, Ls
 
 
-def point_sources(L, n=64, seed=7):
-    """n point sources on distinct MW sample positions of a band-limit-L map.
+def point_sources(L, n=64, seed=1):
+    """n point sources uniform on the sphere, snapped to MW samples of band-limit L.
 
-    Returns (t, p, amp): theta index t in [0, L), phi index p in [0, 2L-1) and
-    amplitude amp ~ U[0.5, 1.5] of each source, drawn from
-    ``numpy.random.default_rng(seed)`` (positions first, then amplitudes)."""
+    Draws cos(theta) ~ U[-1, 1], phi ~ U[0, 2 pi) and a relative amplitude
+    a ~ U[1, 10] per source from ``numpy.random.default_rng(seed)`` (all
+    cos(theta), then all phi, then all a).  Returns (t, p, a): the nearest MW
+    sample indices (theta_t = pi(2t+1)/(2L-1), phi_p = 2 pi p/(2L-1)) and a."""
     rng = np.random.default_rng(seed)
-    npix = L * (2 * L - 1)
-    flat = rng.choice(npix, size=n, replace=False)
-    amp = rng.uniform(0.5, 1.5, size=n)
-    return flat // (2 * L - 1), flat % (2 * L - 1), amp
+    ct = rng.uniform(-1.0, 1.0, size=n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    amp = rng.uniform(1.0, 10.0, size=n)
+    theta = np.arccos(ct)
+    t = np.clip(np.rint((theta * (2 * L - 1) / np.pi - 1.0) / 2.0), 0, L - 1).astype(np.int64)
+    p = np.rint(ph * (2 * L - 1) / (2.0 * np.pi)).astype(np.int64) % (2 * L - 1)
+    return t, p, amp
 
 
 def add_point_sources(fmap, sources):
-    """fmap (L x (2L-1) samples, modified in place) plus a spike of height
-    amp at each source's sample; returns fmap.  The result is not band-limited:
-    consumers project it onto band-limit L with their own SHT pair."""
+    """fmap (L x (2L-1) samples, modified in place) plus, at each source's
+    sample, a spike of height a * rms(fmap) (rms of the samples before any
+    source is added); returns fmap.  The result is not band-limited: consumers
+    project it onto band-limit L with their own SHT pair."""
     t, p, amp = sources
-    np.add.at(fmap, (t, p), amp)
+    rms = float(np.sqrt(np.mean(fmap * fmap)))
+    np.add.at(fmap, (t, p), amp * rms)
     return fmap
