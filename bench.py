@@ -113,7 +113,7 @@ def kernel_symbol(stage, Lj, prec):
         return eng
     mode = {"fp64": "", "fp32": "<1>", "bf16x3": "<2>"}[prec]
     if stage.startswith("beta"):
-        return "k_beta_mfma" if prec == "fp64" else "k_beta_mfma_f32"
+        return {"fp64": "k_beta_mfma", "fp32": "k_beta_mfma_f32", "bf16x3": "k_beta_mfma_bf16x3"}[prec]
     if stage == "contract_inv":
         return "k_contract_inv" if prec == "fp64" else "k_contract_inv_mx" + mode
     if stage == "contract_fwd":

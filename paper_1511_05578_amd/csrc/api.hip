@@ -879,7 +879,7 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_CONTRACT_INV,
                launch_contract_inv_mx(precision, g, L, ctx->delta, B.fpad, S.psi, b0, st));
-        LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Cinv,
+        LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Cinv,
                                                  S.betaf.Sinv, b0, b1, st));
         LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
         LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
@@ -906,7 +906,7 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full_f, grid, b0, st));
         LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
-        LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Qp,
+        LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Qp,
                                                  S.betaf.Qs, b1, b0, st));
         LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd_mx(precision, g, L, ctx->delta, b0, S.psi,
                                                        b1, S.ngroups, st));

@@ -127,7 +127,7 @@ hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0
                             cd *out, hipStream_t st);
 
 // Reduced-precision dense stages (FP32 data; see kernels_mixed.hip).
-hipError_t launch_beta_gemm_f32(int M, int K, int ncols, int Nep, const float *Aeven,
+hipError_t launch_beta_gemm_f32(int mode, int M, int K, int ncols, int Nep, const float *Aeven,
                                 const float *Aodd, const cf *in, cf *out, hipStream_t st);
 hipError_t launch_contract_inv_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
                                   const cd *fpad, const double *psi, cf *X, hipStream_t st);

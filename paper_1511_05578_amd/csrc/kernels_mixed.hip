@@ -9,7 +9,8 @@
 //     relative size 2^-16, is dropped).
 // Delta stays FP64 in HBM; each element is multiplied by its FP64 partner
 // (f_lm, or Psi) before rounding to FP32, so the operands carry one rounding.
-// The beta stage is an FP32 MFMA GEMM; the FFT stages run in FP32 elsewhere.
+// The beta stage is a GEMM on the matrix cores in the same operand precision
+// (FP32, or split BF16); the FFT stages run in FP32 elsewhere.
 //
 // Lane layouts (16 x 16 output block, 64 lanes, lane = 16 q + i, i < 16):
 //   f32 16x16x4:   A[i][q], B[q][i];           D[4q + r][i] in result reg r
@@ -159,12 +160,114 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
             }
 }
 
-hipError_t launch_beta_gemm_f32(int M, int K, int ncols, int Nep, const float *Aeven,
+// The same beta stage with split-BF16 products (BF16x3 mode): K tiles of 32,
+// one v_mfma_f32_16x16x32_bf16 triple per 16 x 16 block and tile.  Operands
+// are staged in FP32 and split in registers.
+__global__ __launch_bounds__(256) void k_beta_mfma_bf16x3(int M, int K, int ncols, int Nep,
+                                                          const float *__restrict__ Ae,
+                                                          const float *__restrict__ Ao,
+                                                          const float *__restrict__ in,
+                                                          float *__restrict__ out) {
+    __shared__ __align__(16) float As[128][36];
+    __shared__ float Bs[32][68];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.y * 128;
+    const int c0 = blockIdx.x * 32;  // complex column base
+    const size_t ld = 2 * (size_t)ncols;
+    const int par = (c0 / Nep) & 1;
+    const float *A = par ? Ao : Ae;
+    f4v acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int li = lane & 15, lq = lane >> 4;
+    float ra[16];
+    float4 rb[2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = tid + 256 * q;
+            const int r = r0 + (idx >> 5), k = k0 + (idx & 31);
+            ra[q] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + 256 * q;
+            const int k = k0 + (idx >> 4);
+            const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
+            rb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < K && col + 3 < ld) rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = tid + 256 * q;
+            As[idx >> 5][idx & 31] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx >> 4, cc = (idx & 15) * 4;
+            const float4 x = rb[q];
+            if (par) {
+                Bs[kk][cc] = -x.y;
+                Bs[kk][cc + 1] = x.x;
+                Bs[kk][cc + 2] = -x.w;
+                Bs[kk][cc + 3] = x.z;
+            } else {
+                Bs[kk][cc] = x.x;
+                Bs[kk][cc + 1] = x.y;
+                Bs[kk][cc + 2] = x.z;
+                Bs[kk][cc + 3] = x.w;
+            }
+        }
+        __syncthreads();
+        if (k0 + 32 < K) fetch(k0 + 32);
+        Op<PREC_BF16X3> aop[2];
+#pragma unroll
+        for (int rb2 = 0; rb2 < 2; ++rb2) {
+            const float4 *src = reinterpret_cast<const float4 *>(&As[32 * w + 16 * rb2 + li][8 * lq]);
+            const float4 x0 = src[0], x1 = src[1];
+            const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            aop[rb2].set(x);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = Bs[8 * lq + e][16 * j + li];
+            Op<PREC_BF16X3> bop;
+            bop.set(x);
+            acc[0][j] = mma32(aop[0], bop, acc[0][j]);
+            acc[1][j] = mma32(aop[1], bop, acc[1][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 32 * w + 16 * i + 4 * lq + r;
+                const size_t col = 2 * (size_t)c0 + 16 * j + li;
+                if (row < M && col < ld) out[(size_t)row * ld + col] = acc[i][j][r];
+            }
+}
+
+hipError_t launch_beta_gemm_f32(int mode, int M, int K, int ncols, int Nep, const float *Aeven,
                                 const float *Aodd, const cf *in, cf *out, hipStream_t st) {
     if (Nep % 32 != 0) return hipErrorInvalidValue;
     dim3 g((ncols + 31) / 32, (M + 127) / 128);
-    hipLaunchKernelGGL(k_beta_mfma_f32, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
-                       (const float *)in, (float *)out);
+    if (mode == PREC_BF16X3)
+        hipLaunchKernelGGL(k_beta_mfma_bf16x3, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
+                           (const float *)in, (float *)out);
+    else
+        hipLaunchKernelGGL(k_beta_mfma_f32, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
+                           (const float *)in, (float *)out);
     return hipGetLastError();
 }
 
