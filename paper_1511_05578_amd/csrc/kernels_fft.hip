@@ -277,7 +277,7 @@ __device__ __forceinline__ void line_sync() {
 template <int P>
 struct R16 {
     static constexpr int T = P / 16;                 // threads per line
-    static constexpr int WG = T < 128 ? 128 : T;     // threads per work-group
+    static constexpr int WG = T < 256 ? 256 : T;     // threads per work-group (>= 4 waves)
     static constexpr int LINES = WG / T;             // lines per work-group
     static constexpr int RC = P / 256;               // radix of the last pass (1: none)
     static constexpr int LW = P + P / 16 + 4;        // reals per LDS line (padded)
@@ -392,6 +392,11 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     const int line0 = xcd_group(blockIdx.x, gridDim.x) * LINES;
     const int line = line0 + li;
     R *lds = smem_d + li * LW;
+    // The chirp spectrum is read by every line between the two FFTs: one copy
+    // in LDS per work-group instead of a cache-missing global read per line.
+    C *vh = reinterpret_cast<C *>(smem_d + LINES * LW);
+    for (int i = threadIdx.x; i < P; i += WG) vh[i] = B.vhat[i];
+    __syncthreads();
     C v[16];
     if constexpr (IO::kLoad == IO_DIRECT) {
         if (line < nlines) {
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     }
     fft_r16<P>(v, lds, B.tw, tid);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) v[s] = cconj(cmul(v[s], B.vhat[tid + T * s]));
+    for (int s = 0; s < 16; ++s) v[s] = cconj(cmul(v[s], vh[tid + T * s]));
     fft_r16<P>(v, lds, B.tw, tid);
     // v[s] = conj(c[q]), q = tid + T*s; output k = k0 + q - (Kin - 1)
     const int qlo = B.Kin - 1;
@@ -471,7 +476,8 @@ template <int P, class IO>
 static hipError_t launch_r16(const IO &io, int nlines, const BlueT<typename IO::C> &B,
                              hipStream_t st) {
     using G = R16<P>;
-    const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>);
+    const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>) +
+                       (size_t)P * sizeof(typename IO::C);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {
