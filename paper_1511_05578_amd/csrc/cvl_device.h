@@ -56,6 +56,29 @@ __host__ __device__ __forceinline__ C cmk(double x, double y) {
 // Precision of a curvelet call (values of cvl_params.precision).
 enum Precision { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
+// Work-groups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// index.  Kernels whose neighbouring logical work-groups share data (cache
+// lines of interleaved lines, Delta rows, cube rows, GEMM operand tiles)
+// remap the hardware index so that each XCD gets a contiguous range of
+// logical groups: hardware index b runs on XCD b % 8 and processes group
+// start(b % 8) + b / 8.  A bijection of [0, n) for any n.
+__device__ __forceinline__ int xcd_group(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// The same in chunks: logical groups come in runs of G that share data (all
+// tiles of one m', say) while runs differ in cost; each XCD gets whole runs,
+// dealt round-robin (run r to XCD r % 8), which keeps the sharing inside one
+// L2 and the load balanced across XCDs.  Groups past the last full round of
+// 8 runs keep their index.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_group_runs(int b, int n, int G) {
+    const int full = (n / (8 * G)) * 8 * G;
+    if (b >= full) return b;
+    const int x = b & 7, i = b >> 3;
+    return ((i / G) * 8 + x) * G + (i % G);
+}
+
 // Offset of block l in the quarter Delta table: sum_{k<l} (k+1)^2.
 __host__ __device__ __forceinline__ int64_t delta_off(int l) {
     return (int64_t)l * (l + 1) * (2 * l + 1) / 6;

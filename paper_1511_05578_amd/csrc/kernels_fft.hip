@@ -23,16 +23,7 @@ namespace cvl {
 
 enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
 
-// Work-groups are dealt to the 8 XCDs (each with its own L2) round-robin by
-// index.  Lines of neighbouring work-groups share cache lines (interleaved
-// lines, e.g. neighbouring k at the same m), so the logical group index is
-// remapped to give each XCD a contiguous range of groups: hardware index b
-// runs on XCD b % 8 and processes group start(b % 8) + b / 8.  A bijection of
-// [0, n) for any n.
-__device__ __forceinline__ int xcd_group(int b, int n) {
-    const int q = n >> 3, r = n & 7, x = b & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
+
 
 // In-place Stockham FFT of one LDS line (forward, tw[x] = e^{-2 pi i x / P}).
 // Radix-4 stages first, then one radix-2 stage when log2 P is odd.  Every
@@ -394,9 +385,15 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     R *lds = smem_d + li * LW;
     // The chirp spectrum is read by every line between the two FFTs: one copy
     // in LDS per work-group instead of a cache-missing global read per line.
-    C *vh = reinterpret_cast<C *>(smem_d + LINES * LW);
-    for (int i = threadIdx.x; i < P; i += WG) vh[i] = B.vhat[i];
-    __syncthreads();
+    // (Up to P = 2048; at P = 4096 the copy would cost occupancy.)
+    constexpr bool kVhLds = P <= 2048;
+    const C *vh = B.vhat;
+    if constexpr (kVhLds) {
+        C *v2 = reinterpret_cast<C *>(smem_d + LINES * LW);
+        for (int i = threadIdx.x; i < P; i += WG) v2[i] = B.vhat[i];
+        __syncthreads();
+        vh = v2;
+    }
     C v[16];
     if constexpr (IO::kLoad == IO_DIRECT) {
         if (line < nlines) {
@@ -477,7 +474,7 @@ static hipError_t launch_r16(const IO &io, int nlines, const BlueT<typename IO::
                              hipStream_t st) {
     using G = R16<P>;
     const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>) +
-                       (size_t)P * sizeof(typename IO::C);
+                       (P <= 2048 ? (size_t)P * sizeof(typename IO::C) : 0);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {

@@ -190,8 +190,12 @@ __global__ __launch_bounds__(256) void k_beta_mfma(int M, int K, int ncols, int 
     __shared__ double As[128][17];
     __shared__ double Bs[16][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int r0 = blockIdx.y * 128;
-    const int c0 = blockIdx.x * 32;  // complex column base
+    // logical tile (row tile fastest: the row tiles of one column tile share
+    // its B operand, so they run together on one XCD)
+    const int nrt = (M + 127) / 128;
+    const int lg = xcd_group(blockIdx.x, gridDim.x);
+    const int r0 = (lg % nrt) * 128;
+    const int c0 = (lg / nrt) * 32;  // complex column base
     const size_t ld = 2 * (size_t)ncols;
     const int par = (c0 / Nep) & 1;
     const double *A = par ? Ao : Ae;
@@ -272,7 +276,7 @@ hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0
                             const double *Aeven, const double *Aodd, const cd *in, cd *out,
                             hipStream_t st) {
     if (mode == 0 && Nep % 32 == 0) {
-        dim3 g((ncols + 31) / 32, (M + 127) / 128);
+        dim3 g(((ncols + 31) / 32) * ((M + 127) / 128));
         hipLaunchKernelGGL(k_beta_mfma, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
                            (const double *)in, (double *)out);
         return hipGetLastError();
@@ -303,9 +307,12 @@ __global__ __launch_bounds__(256) void k_contract_inv(ScaleGeom g, int Lf,
     __shared__ cd Ash[8][64];
     __shared__ double Bsh[8][32];
     const int L = g.L, h = g.h;
-    const int mp = blockIdx.y;
-    const int nkt = (h + 1 + 31) / 32;
-    const int m0 = (blockIdx.x / nkt) * 64, k0 = (blockIdx.x % nkt) * 32;
+    // logical tile: k tile fastest, then m tile, then m' (tiles of one m'
+    // share its Delta rows; the tiles of one m' run on one XCD)
+    const int nkt = (h + 1 + 31) / 32, nmt = (L + 63) / 64;
+    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nkt * nmt);
+    const int mp = lg / (nkt * nmt);
+    const int m0 = ((lg / nkt) % nmt) * 64, k0 = (lg % nkt) * 32;
     const int tid = threadIdx.x;
     const int tm = tid % 16, tk = tid / 16;
     cd pe[4][2], po[4][2];
@@ -385,7 +392,7 @@ __global__ __launch_bounds__(256) void k_contract_inv(ScaleGeom g, int Lf,
 hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta, const cd *fpad,
                                const double *psi, cd *X, hipStream_t st) {
     const int nkt = (g.h + 1 + 31) / 32;
-    dim3 grid(((g.L + 63) / 64) * nkt, g.L);
+    dim3 grid(((g.L + 63) / 64) * nkt * g.L);
     hipLaunchKernelGGL(k_contract_inv, grid, dim3(256), 0, st, g, Lf, delta, fpad, psi, X);
     return hipGetLastError();
 }
@@ -431,10 +438,13 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mfma(ScaleGeom g, int L
     // (rows below llo carry a zero kernel and are never read back).
     const int lbase = g.llo & ~1;
     const int nl = g.lhi - lbase + 1;
-    const int nlt = (nl + 63) / 64;
-    const int m0 = (blockIdx.x / nlt) * 64;
-    const int l0 = lbase + (blockIdx.x % nlt) * 64;
-    const int grp = blockIdx.y;
+    const int nlt = (nl + 63) / 64, nmt = (L + 63) / 64;
+    // logical tile: l tile fastest, then m tile, then m' group (tiles of one
+    // (group, m tile) read the same cube rows and run on one XCD)
+    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt);
+    const int m0 = ((lg / nlt) % nmt) * 64;
+    const int l0 = lbase + (lg % nlt) * 64;
+    const int grp = lg / (nlt * nmt);
     const int gsz = (L + ngroups - 1) / ngroups;
     const int mpa = grp * gsz;
     int mpb = mpa + gsz;
@@ -561,7 +571,7 @@ hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta, 
                                const double *psi, cd *part, int ngroups, hipStream_t st) {
     if (g.lhi < g.llo) return hipSuccess;
     const int nl = g.lhi - (g.llo & ~1) + 1;
-    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64), ngroups);
+    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * ngroups);
     hipLaunchKernelGGL(k_contract_fwd_mfma, grid, dim3(256), 0, st, g, Lf, delta, Z, psi, part,
                        ngroups);
     return hipGetLastError();

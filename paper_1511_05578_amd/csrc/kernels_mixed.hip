@@ -78,8 +78,12 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
     __shared__ float As[128][33];
     __shared__ float Bs[32][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int r0 = blockIdx.y * 128;
-    const int c0 = blockIdx.x * 32;  // complex column base
+    // logical tile (row tile fastest: the row tiles of one column tile share
+    // its B operand, so they run together on one XCD)
+    const int nrt = (M + 127) / 128;
+    const int lg = xcd_group(blockIdx.x, gridDim.x);
+    const int r0 = (lg % nrt) * 128;
+    const int c0 = (lg / nrt) * 32;  // complex column base
     const size_t ld = 2 * (size_t)ncols;
     const int par = (c0 / Nep) & 1;
     const float *A = par ? Ao : Ae;
@@ -171,8 +175,12 @@ __global__ __launch_bounds__(256) void k_beta_mfma_bf16x3(int M, int K, int ncol
     __shared__ __align__(16) float As[128][36];
     __shared__ float Bs[32][68];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int r0 = blockIdx.y * 128;
-    const int c0 = blockIdx.x * 32;  // complex column base
+    // logical tile (row tile fastest: the row tiles of one column tile share
+    // its B operand, so they run together on one XCD)
+    const int nrt = (M + 127) / 128;
+    const int lg = xcd_group(blockIdx.x, gridDim.x);
+    const int r0 = (lg % nrt) * 128;
+    const int c0 = (lg / nrt) * 32;  // complex column base
     const size_t ld = 2 * (size_t)ncols;
     const int par = (c0 / Nep) & 1;
     const float *A = par ? Ao : Ae;
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(256) void k_beta_mfma_bf16x3(int M, int K, int ncol
 hipError_t launch_beta_gemm_f32(int mode, int M, int K, int ncols, int Nep, const float *Aeven,
                                 const float *Aodd, const cf *in, cf *out, hipStream_t st) {
     if (Nep % 32 != 0) return hipErrorInvalidValue;
-    dim3 g((ncols + 31) / 32, (M + 127) / 128);
+    dim3 g(((ncols + 31) / 32) * ((M + 127) / 128));
     if (mode == PREC_BF16X3)
         hipLaunchKernelGGL(k_beta_mfma_bf16x3, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
                            (const float *)in, (float *)out);
@@ -296,9 +304,11 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
     float(*As)[2][32][66] = reinterpret_cast<float(*)[2][32][66]>(smem);
     float(*Bs)[32][34] = reinterpret_cast<float(*)[32][34]>(smem + 2 * 2 * 32 * 66);
     const int L = g.L, h = g.h;
-    const int mp = blockIdx.y;
-    const int nkt = (h + 1 + 31) / 32;
-    const int m0 = (blockIdx.x / nkt) * 64, k0 = (blockIdx.x % nkt) * 32;
+    // logical tile: k tile fastest, then m tile, then m' (see k_contract_inv)
+    const int nkt = (h + 1 + 31) / 32, nmt = (L + 63) / 64;
+    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nkt * nmt);
+    const int mp = lg / (nkt * nmt);
+    const int m0 = ((lg / nkt) % nmt) * 64, k0 = (lg % nkt) * 32;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int p = w & 1, c = w >> 1;
     const int li = lane & 15, lq = lane >> 4;
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
 hipError_t launch_contract_inv_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
                                   const cd *fpad, const double *psi, cf *X, hipStream_t st) {
     const int nkt = (g.h + 1 + 31) / 32;
-    dim3 grid(((g.L + 63) / 64) * nkt, g.L);
+    dim3 grid(((g.L + 63) / 64) * nkt * g.L);
     if (mode == PREC_FP32)
         hipLaunchKernelGGL(k_contract_inv_mx<PREC_FP32>, grid, dim3(256), 0, st, g, Lf, delta,
                            fpad, psi, X);
@@ -427,10 +437,13 @@ __global__ __launch_bounds__(256) void k_contract_fwd_mx(ScaleGeom g, int Lf,
     const int L = g.L, h = g.h, Nep = g.Nep;
     const int lbase = g.llo & ~1;
     const int nl = g.lhi - lbase + 1;
-    const int nlt = (nl + 63) / 64;
-    const int m0 = (blockIdx.x / nlt) * 64;
-    const int l0 = lbase + (blockIdx.x % nlt) * 64;
-    const int grp = blockIdx.y;
+    const int nlt = (nl + 63) / 64, nmt = (L + 63) / 64;
+    // logical tile: l tile fastest, then m tile, then m' group (see
+    // k_contract_fwd_mfma)
+    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt);
+    const int m0 = ((lg / nlt) % nmt) * 64;
+    const int l0 = lbase + (lg % nlt) * 64;
+    const int grp = lg / (nlt * nmt);
     const int gsz = (L + ngroups - 1) / ngroups;
     const int mpa = grp * gsz;
     int mpb = mpa + gsz;
@@ -557,7 +570,7 @@ hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, int Lf, const do
                                   hipStream_t st) {
     if (g.lhi < g.llo) return hipSuccess;
     const int nl = g.lhi - (g.llo & ~1) + 1;
-    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64), ngroups);
+    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * ngroups);
     if (mode == PREC_FP32)
         hipLaunchKernelGGL(k_contract_fwd_mx<PREC_FP32>, grid, dim3(256), 0, st, g, Lf, delta, Z,
                            psi, part, ngroups);
