@@ -724,11 +724,51 @@ hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z,
                        Z, fpad);
     return hipGetLastError();
 }
+// theta stage of the SHT: out[r][m] = (i^(m&1)) sum_k A^{m&1}[r][k] in[k][m],
+// r < Mrows, k < Kdim, m < L.  One output per thread, 16 x 16 tiles (enough
+// work-groups to fill the device at small L), K in chunks of 32 through LDS.
+__global__ __launch_bounds__(256) void k_sht_theta(int L, int Mrows, int Kdim,
+                                                   const double *__restrict__ Ae,
+                                                   const double *__restrict__ Ao,
+                                                   const cd *__restrict__ in,
+                                                   cd *__restrict__ out) {
+    __shared__ double As[2][16][33];
+    __shared__ cd Bs[32][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int m = blockIdx.x * 16 + tx, r = blockIdx.y * 16 + ty;
+    const int par = m & 1;
+    double re = 0.0, im = 0.0;
+    for (int k0 = 0; k0 < Kdim; k0 += 32) {
+        for (int i = threadIdx.x; i < 512; i += 256) {
+            const int rr = i >> 5, kk = i & 31;
+            const int rg = blockIdx.y * 16 + rr, k = k0 + kk;
+            const bool ok = rg < Mrows && k < Kdim;
+            As[0][rr][kk] = ok ? Ae[(size_t)rg * Kdim + k] : 0.0;
+            As[1][rr][kk] = ok ? Ao[(size_t)rg * Kdim + k] : 0.0;
+        }
+        for (int i = threadIdx.x; i < 512; i += 256) {
+            const int kk = i >> 4, mm = i & 15;
+            const int k = k0 + kk, mg = blockIdx.x * 16 + mm;
+            Bs[kk][mm] = (k < Kdim && mg < L) ? in[(size_t)k * L + mg] : cd{0.0, 0.0};
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+            const double a = As[par][ty][kk];
+            const cd b = Bs[kk][tx];
+            re += a * b.x;
+            im += a * b.y;
+        }
+        __syncthreads();
+    }
+    if (r < Mrows && m < L) out[(size_t)r * L + m] = par ? cd{-im, re} : cd{re, im};
+}
+
 hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int, const double *Aeven,
                             const double *Aodd, const cd *in, cd *out, hipStream_t st) {
-    (void)L;
-    // columns are m = 0..L-1 with parity m & 1: general-mode GEMM with Nep = 1.
-    return launch_beta_gemm(Mrows, Kdim, L, 1, 1, 0, Aeven, Aodd, in, out, st);
+    dim3 grid((L + 15) / 16, (Mrows + 15) / 16);
+    hipLaunchKernelGGL(k_sht_theta, grid, dim3(256), 0, st, L, Mrows, Kdim, Aeven, Aodd, in, out);
+    return hipGetLastError();
 }
 
 // f (flat l^2+l+m) <-> fpad [l][m], m >= 0.
