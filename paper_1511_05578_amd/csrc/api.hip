@@ -45,6 +45,9 @@ constexpr size_t kAlign = 256;
 // work-groups, with at least kMinGroups groups and at most L_j (one m' each).
 constexpr int kFwdWGs = 1024;
 constexpr int kMinGroups = 32;
+// Scales with L_j at least this run the analysis beta stage as an FFT
+// (O(L^3 log L)) instead of the dense parity-folded GEMM (O(L^4)).
+constexpr int kBetaFftMinL = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Stage {
@@ -107,6 +110,9 @@ struct ScaleRt {
     BetaTabsF betaf;
     BluesteinF inv_full_f, fwd_full_f;
     int ngroups;  // m' groups of the synthesis contraction
+    bool beta_fft;  // analysis beta stage as an FFT (large L_j) instead of a GEMM
+    BluesteinDev beta_inv;
+    BluesteinF beta_inv_f;
 };
 
 struct Plan {
@@ -444,6 +450,12 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
         if ((rc = get_beta_f(c, Lj, 0, &S.betaf))) return rc;
         if ((rc = get_bluestein_f(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full_f))) return rc;
         if ((rc = get_bluestein_f(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full_f))) return rc;
+        S.beta_fft = Lj >= kBetaFftMinL;
+        if (S.beta_fft) {
+            if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, -(Lj - 1), +1, &S.beta_inv))) return rc;
+            if ((rc = get_bluestein_f(c, Nm, Nm, -(Lj - 1), Nm, -(Lj - 1), +1, &S.beta_inv_f)))
+                return rc;
+        }
         P->scales.push_back(S);
     }
     std::vector<double> pf(P->Lphi);
@@ -879,8 +891,11 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_CONTRACT_INV,
                launch_contract_inv_mx(precision, g, L, ctx->delta, B.fpad, S.psi, b0, st));
-        LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Cinv,
-                                                 S.betaf.Sinv, b0, b1, st));
+        if (S.beta_fft)
+            LAUNCH(ST_BETA_INV, launch_inv_beta_dft(g, S.beta_inv_f, b0, b1, st));
+        else
+            LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep,
+                                                     S.betaf.Cinv, S.betaf.Sinv, b0, b1, st));
         LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
         LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
         return CVL_OK;
@@ -888,8 +903,11 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
     cd *grid = (cd *)grid_out;
     cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
     LAUNCH(ST_CONTRACT_INV, launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, b0, st));
-    LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Cinv,
-                                         S.beta.Sinv, b0, b1, st));
+    if (S.beta_fft)
+        LAUNCH(ST_BETA_INV, launch_inv_beta_dft(g, S.beta_inv, b0, b1, st));
+    else
+        LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Cinv,
+                                             S.beta.Sinv, b0, b1, st));
     LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full, b1, b0, st));
     LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, b0, grid, st));
     return CVL_OK;

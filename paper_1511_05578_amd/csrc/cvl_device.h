@@ -117,6 +117,14 @@ hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd 
                             cd *V1, hipStream_t st);
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
                             cd *V2, hipStream_t st);
+// beta DFT of the analysis as an FFT (line pairs of opposite m-parity):
+// X [m'][m][nn] (m' >= 0) -> W1 [b][m][nn], b < L; B: length 2L-1, inputs
+// j in (-L, L), outputs k' in (-L, L).
+hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const cd *X, cd *W1,
+                               hipStream_t st);
+hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X, cf *W1,
+                               hipStream_t st);
+
 // The same four stages in single precision (complex64 cubes and grids).
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1, cf *W2,
                             hipStream_t st);

@@ -21,7 +21,10 @@
 
 namespace cvl {
 
-enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2 };
+// Output modes: IO_PAIR hands the policy output pairs (k, -k) of a symmetric
+// window, line by line; IO_STAGED_PAIR does the same with the work-group's
+// lines interleaved (neighbouring lines neighbouring in memory).
+enum { IO_DIRECT = 0, IO_STAGED = 1, IO_PAIR = 2, IO_STAGED_PAIR = 3 };
 
 
 
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BlueT<type
         buf[t + B.Kin - 1] = cmul(c, B.post[t]);
     }
     __syncthreads();
-    if constexpr (IO::kStore == IO_PAIR) {
+    if constexpr (IO::kStore == IO_PAIR || IO::kStore == IO_STAGED_PAIR) {
         const int line = line0 + li;
         if (line < nlines) {
             const auto c = io.at(line);
@@ -459,6 +462,15 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
                 for (int t = threadIdx.x / LINES; t < B.Kout; t += WG / LINES)
                     io.store(c, B.k0 + t, src[t]);
             }
+        } else if constexpr (IO::kStore == IO_STAGED_PAIR) {
+            const int ls = threadIdx.x % LINES, lns = line0 + ls;
+            if (lns < nlines) {
+                const auto c = io.at(lns);
+                const C *src = reinterpret_cast<const C *>(smem_d + ls * LW);
+                const int K = -B.k0;
+                for (int k = threadIdx.x / LINES; k <= K; k += WG / LINES)
+                    io.store_pair(c, k, src[k + K], src[K - k]);
+            }
         } else {  // IO_PAIR: outputs k in [-K, K], K = -k0; pairs (k, -k)
             if (line < nlines) {
                 const auto c = io.at(line);
@@ -708,6 +720,50 @@ struct FwdAlphaIO {
     }
 };
 
+// beta DFT of the analysis (replaces the parity-folded GEMM at large L_j).
+// With beta_b = pi + 2 pi k'/(2L-1), k' = b - (L-1), the sum over m' in
+// (-L, L) of X[m'] e^{i m' beta_b} is a plain DFT of (-1)^{m'} X[m'] at k'.
+// The cube holds m' >= 0 with X[-m'] = (-1)^{m+n} X[m'] (n even), so a line of
+// even m is even in m' and one of odd m odd: line (p, nn) transforms
+// z = X_{2p} + X_{2p+1} and splits the result by parity of beta ->
+// -beta (k' -> -k'):  W1_e(beta) = (Z(beta) + Z(-beta))/2,
+// W1_o(beta) = (Z(beta) - Z(-beta))/2, stored for b = L-1-k, k = 0..L-1.
+// X, W1: [row][m][nn] with row m' (input) or b (output), row length L*Nep.
+template <class C_>
+struct BetaInvPairIO {
+    using C = C_;
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED_PAIR;
+    const C *X;
+    C *W1;
+    int L, Ne, Nep;
+    struct Ctx {
+        const C *xe, *xo;  // X[0][2p][nn], X[0][2p+1][nn] (xo null past the last m)
+        C *we, *wo;        // W1[0][2p][nn], W1[0][2p+1][nn]
+    };
+    __device__ Ctx at(int line) const {
+        const int p = line / Ne, nn = line % Ne;
+        const int me = 2 * p, mo = 2 * p + 1;
+        const size_t oe = (size_t)me * Nep + nn, oo = (size_t)mo * Nep + nn;
+        return Ctx{X + oe, mo < L ? X + oo : nullptr, W1 + oe, mo < L ? W1 + oo : nullptr};
+    }
+    __device__ C load(const Ctx &c, int j) const {
+        const int mp = j < 0 ? -j : j;
+        const size_t row = (size_t)mp * L * Nep;
+        C v = c.xe[row];
+        if (c.xo) {
+            const C o = c.xo[row];
+            v = j < 0 ? csub(v, o) : cadd(v, o);
+        }
+        return (mp & 1) ? C{-v.x, -v.y} : v;
+    }
+    __device__ void store_pair(const Ctx &c, int k, C zk, C zmk) const {
+        const size_t row = (size_t)(L - 1 - k) * L * Nep;  // b = L-1-k: Z(beta_b) = zmk
+        const real_t<C> h = (real_t<C>)0.5;
+        c.we[row] = C{(zmk.x + zk.x) * h, (zmk.y + zk.y) * h};
+        if (c.wo) c.wo[row] = C{(zmk.x - zk.x) * h, (zmk.y - zk.y) * h};
+    }
+};
+
 struct ShtInvPhiIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
@@ -773,6 +829,21 @@ static hipError_t fwd_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *V1
                               hipStream_t st) {
     FwdAlphaIO<C> io{V1, V2, g.L, g.h, g.Nm, g.Nep};
     return run_bluestein(io, g.L * (g.h + 1), B, st);
+}
+
+template <class C>
+static hipError_t inv_beta_t(const ScaleGeom &g, const BlueT<C> &B, const C *X, C *W1,
+                             hipStream_t st) {
+    BetaInvPairIO<C> io{X, W1, g.L, g.Ne, g.Nep};
+    return run_bluestein(io, ((g.L + 1) / 2) * g.Ne, B, st);
+}
+hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const cd *X, cd *W1,
+                               hipStream_t st) {
+    return inv_beta_t(g, B, X, W1, st);
+}
+hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X, cf *W1,
+                               hipStream_t st) {
+    return inv_beta_t(g, B, X, W1, st);
 }
 
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1, cd *W2,
