@@ -271,3 +271,34 @@ def test_l1024_round_trip():
         torch.cuda.synchronize()
         c.close()
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_odd_bandlimit_above_fft_beta_threshold(prec):
+    # L = 257: odd, not a power of two, finest scales L_j = 257 take the FFT
+    # beta path with an unpaired last m.  Oracle rows of the finest scale,
+    # full round trip.
+    L, lam, J0 = 257, 2.0, 2
+    bound = TOL if prec == "fp64" else 1e-5
+    c = api.Context(L, 0)
+    try:
+        plan = ocurv.Plan(L, lam, J0)
+        f = inputs.gaussian_real_flm(L, seed=8)
+        fmap = osht.inverse(f, L).real
+        scal, grids = c.curvelet_analysis(dev(fmap), lam, J0, precision=prec)
+        # the first full-size scale (the last one's kernel support lies above L)
+        s, j = [(s, j) for s, j in enumerate(plan.scales) if plan.Lj[j] == L][0]
+        rows = [0, 100, 256]
+        say("L=257 %s: oracle rows %s of scale %d" % (prec, rows, j))
+        ref = ocurv.analysis_scale(plan, f, j, rows=rows)
+        assert np.abs(ref).max() > 1e-6
+        e = rel_l2(host(grids[s])[:, rows, :], ref)
+        say("  rows rel L2 %.2e" % e)
+        assert e < bound
+        rec = host(c.curvelet_synthesis(scal, grids, L, lam, J0, precision=prec))
+        e = rel_l2(rec, fmap)
+        say("  round trip rel L2 %.2e" % e)
+        assert e < bound
+    finally:
+        torch.cuda.synchronize()
+        c.close()
