@@ -106,7 +106,7 @@ struct ScaleRt {
     ScaleGeom g;
     double *psi;  // [l][k]: Psi^(j)_{l,2k}
     BetaTabs beta;
-    BluesteinDev inv_full, fwd_full, fwd_half;
+    BluesteinDev inv_full, fwd_full;
     BetaTabsF betaf;
     BluesteinF inv_full_f, fwd_full_f;
     int ngroups;  // m' groups of the synthesis contraction
@@ -446,7 +446,6 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
         const int Nm = 2 * Lj - 1;
         if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full))) return rc;
         if ((rc = get_bluestein(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full))) return rc;
-        if ((rc = get_bluestein(c, Nm, Nm, 0, Lj, 0, -1, &S.fwd_half))) return rc;
         if ((rc = get_beta_f(c, Lj, 0, &S.betaf))) return rc;
         if ((rc = get_bluestein_f(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full_f))) return rc;
         if ((rc = get_bluestein_f(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full_f))) return rc;

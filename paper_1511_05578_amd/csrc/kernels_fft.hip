@@ -398,13 +398,26 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
         vh = v2;
     }
     C v[16];
+    // Every load of a line is issued before any is used: indices are clamped
+    // into the window and out-of-window elements zeroed afterwards, so no
+    // load waits behind a branch (the IO policies' loads are branch-free too).
     if constexpr (IO::kLoad == IO_DIRECT) {
         if (line < nlines) {
             const auto c = io.at(line);
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int t = tid + T * s;
-                v[s] = t < B.Kin ? cmul(io.load(c, B.j0 + t), B.pre[t]) : C{0, 0};
+            for (int h8 = 0; h8 < 16; h8 += IO::kBatch) {
+                C raw[IO::kBatch];
+#pragma unroll
+                for (int e = 0; e < IO::kBatch; ++e) {
+                    const int t = tid + T * (h8 + e);
+                    raw[e] = io.load(c, B.j0 + (t < B.Kin ? t : B.Kin - 1));
+                }
+#pragma unroll
+                for (int e = 0; e < IO::kBatch; ++e) {
+                    const int t = tid + T * (h8 + e);
+                    const C pw = B.pre[t < B.Kin ? t : B.Kin - 1];
+                    v[h8 + e] = t < B.Kin ? cmul(raw[e], pw) : C{0, 0};
+                }
             }
         } else {
 #pragma unroll
@@ -413,12 +426,26 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     } else {
         // Staged through the LDS lines viewed as complex (Kin <= P/2 fits).
         // WG is a multiple of LINES, so each thread always stages the same line.
-        const int ls = threadIdx.x % LINES, lns = line0 + ls;
+        // Each line has WG / LINES = T staging threads, 16 elements each.
+        const int ls = threadIdx.x % LINES, lns = line0 + ls, tl = threadIdx.x / LINES;
         C *dst = reinterpret_cast<C *>(smem_d + ls * LW);
         if (lns < nlines) {
             const auto c = io.at(lns);
-            for (int t = threadIdx.x / LINES; t < B.Kin; t += WG / LINES)
-                dst[t] = cmul(io.load(c, B.j0 + t), B.pre[t]);
+#pragma unroll
+            for (int h8 = 0; h8 < 16; h8 += IO::kBatch) {
+                C raw[IO::kBatch];
+#pragma unroll
+                for (int e = 0; e < IO::kBatch; ++e) {
+                    const int t = tl + T * (h8 + e);
+                    raw[e] = io.load(c, B.j0 + (t < B.Kin ? t : B.Kin - 1));
+                }
+#pragma unroll
+                for (int e = 0; e < IO::kBatch; ++e) {
+                    const int t = tl + T * (h8 + e);
+                    const C pw = B.pre[t < B.Kin ? t : B.Kin - 1];
+                    if (t < B.Kin) dst[t] = cmul(raw[e], pw);
+                }
+            }
         }
         __syncthreads();
         const C *src = reinterpret_cast<const C *>(lds);
@@ -435,13 +462,25 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     fft_r16<P>(v, lds, B.tw, tid);
     // v[s] = conj(c[q]), q = tid + T*s; output k = k0 + q - (Kin - 1)
     const int qlo = B.Kin - 1;
+    // post-chirp factors: loaded 8 at a time (clamped indices), so that a
+    // half line's loads are in flight together without doubling the registers
     if constexpr (IO::kStore == IO_DIRECT) {
         if (line < nlines) {
             const auto c = io.at(line);
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int q = tid + T * s - qlo;
-                if (q >= 0 && q < B.Kout) io.store(c, B.k0 + q, cmul(cconj(v[s]), B.post[q]));
+            for (int h8 = 0; h8 < 16; h8 += 8) {
+                C pq[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int q = tid + T * (h8 + e) - qlo;
+                    pq[e] = B.post[q < 0 ? 0 : (q < B.Kout ? q : B.Kout - 1)];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int q = tid + T * (h8 + e) - qlo;
+                    if (q >= 0 && q < B.Kout)
+                        io.store(c, B.k0 + q, cmul(cconj(v[h8 + e]), pq[e]));
+                }
             }
         }
     } else {
@@ -449,9 +488,18 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
         C *buf = reinterpret_cast<C *>(lds);
         line_sync<P>();
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int q = tid + T * s - qlo;
-            if (q >= 0 && q < B.Kout) buf[q] = cmul(cconj(v[s]), B.post[q]);
+        for (int h8 = 0; h8 < 16; h8 += 8) {
+            C pq[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int q = tid + T * (h8 + e) - qlo;
+                pq[e] = B.post[q < 0 ? 0 : (q < B.Kout ? q : B.Kout - 1)];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int q = tid + T * (h8 + e) - qlo;
+                if (q >= 0 && q < B.Kout) buf[q] = cmul(cconj(v[h8 + e]), pq[e]);
+            }
         }
         __syncthreads();
         if constexpr (IO::kStore == IO_STAGED) {
@@ -551,6 +599,7 @@ template <class C_>
 struct InvAlphaIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const C *W1;
     C *W2;
     int L, h, Nep, Nm;
@@ -564,7 +613,9 @@ struct InvAlphaIO {
         return Ctx{base + k, base - k, W2 + (size_t)b * Nm * (h + 1) + k};
     }
     __device__ C load(const Ctx &c, int m) const {
-        return m >= 0 ? c.pos[(size_t)m * Nep] : cconj(c.neg[(size_t)(-m) * Nep]);
+        const bool pos = m >= 0;
+        const C v = pos ? c.pos[(size_t)m * Nep] : c.neg[(size_t)(-m) * Nep];
+        return C{v.x, pos ? v.y : -v.y};
     }
     __device__ void store(const Ctx &c, int a, C v) const { c.out[(size_t)a * (h + 1)] = v; }
 };
@@ -575,6 +626,7 @@ template <class C_>
 struct InvGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const C *W2;
     C *grid;
     int L, h, Nm;
@@ -587,8 +639,9 @@ struct InvGammaIO {
         return Ctx{W2 + ((size_t)b * Nm + a) * (h + 1), grid + (size_t)line * Nm};
     }
     __device__ C load(const Ctx &c, int n) const {
-        if (n & 1) return C{0, 0};
-        return n >= 0 ? c.src[n / 2] : cconj(c.src[-n / 2]);
+        const C v = c.src[(n < 0 ? -n : n) >> 1];
+        const real_t<C> z = 0;
+        return (n & 1) ? C{z, z} : C{v.x, n < 0 ? -v.y : v.y};
     }
     __device__ void store(const Ctx &c, int g, C v) const { c.dst[g] = C{v.x, 0}; }
 };
@@ -599,6 +652,7 @@ template <class C_>
 struct InvGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 8;  // two loads per element
     const C *W2;
     C *grid;
     int L, h, Nm, nreal;
@@ -616,15 +670,14 @@ struct InvGammaPackIO {
                    grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm, two};
     }
     __device__ C load(const Ctx &c, int n) const {
-        if (n & 1) return C{0, 0};
-        const int k = n >= 0 ? n / 2 : -n / 2;
-        C c1 = c.s1[k];
-        C c2 = c.two ? c.s2[k] : C{0, 0};
-        if (n < 0) {
-            c1 = cconj(c1);
-            c2 = cconj(c2);
-        }
-        return C{c1.x - c2.y, c1.y + c2.x};
+        // s2 is a valid pointer even for a lone last line (it then repeats s1)
+        const int k = (n < 0 ? -n : n) >> 1;
+        const C c1 = c.s1[k], c2r = c.s2[k];
+        const real_t<C> z = 0;
+        const C c2 = c.two ? c2r : C{z, z};
+        const real_t<C> sg = n < 0 ? -1 : 1;  // conjugate both for n < 0
+        const C r{c1.x - sg * c2.y, sg * c1.y + c2.x};
+        return (n & 1) ? C{z, z} : r;
     }
     __device__ void store(const Ctx &c, int g, C v) const {
         c.d1[g] = C{v.x, 0};
@@ -638,6 +691,7 @@ template <class C_>
 struct FwdGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const C *grid;
     C *V1;
     int L, h, Nm;
@@ -663,6 +717,7 @@ template <class C_>
 struct FwdGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const C *grid;
     C *V1;
     int L, h, Nm, nreal;
@@ -681,7 +736,9 @@ struct FwdGammaPackIO {
                    two};
     }
     __device__ C load(const Ctx &c, int g) const {
-        return C{c.s1[g].x, c.two ? c.s2[g].x : (real_t<C>)0};
+        // s2 is a valid pointer even for a lone last line (it then repeats s1)
+        const real_t<C> a = c.s1[g].x, b = c.s2[g].x;
+        return C{a, c.two ? b : (real_t<C>)0};
     }
     __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
         if (n & 1) return;
@@ -700,6 +757,7 @@ template <class C_>
 struct FwdAlphaIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const C *V1;
     C *V2;
     int L, h, Nm, Nep;
@@ -733,28 +791,30 @@ template <class C_>
 struct BetaInvPairIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED_PAIR;
+    static constexpr int kBatch = 8;  // two loads per element
     const C *X;
     C *W1;
     int L, Ne, Nep;
     struct Ctx {
-        const C *xe, *xo;  // X[0][2p][nn], X[0][2p+1][nn] (xo null past the last m)
-        C *we, *wo;        // W1[0][2p][nn], W1[0][2p+1][nn]
+        const C *xe, *xo;  // X[0][2p][nn], X[0][2p+1][nn]
+        C *we, *wo;        // W1[0][2p][nn], W1[0][2p+1][nn] (wo null past the last m)
+        real_t<C> wo_on;   // 1, or 0 when there is no odd partner
     };
     __device__ Ctx at(int line) const {
         const int p = line / Ne, nn = line % Ne;
         const int me = 2 * p, mo = 2 * p + 1;
         const size_t oe = (size_t)me * Nep + nn, oo = (size_t)mo * Nep + nn;
-        return Ctx{X + oe, mo < L ? X + oo : nullptr, W1 + oe, mo < L ? W1 + oo : nullptr};
+        // a lone last (even) m reads its own row as the odd partner, weighted 0
+        return Ctx{X + oe, X + (mo < L ? oo : oe), W1 + oe, mo < L ? W1 + oo : nullptr,
+                   (real_t<C>)(mo < L ? 1 : 0)};
     }
     __device__ C load(const Ctx &c, int j) const {
         const int mp = j < 0 ? -j : j;
         const size_t row = (size_t)mp * L * Nep;
-        C v = c.xe[row];
-        if (c.xo) {
-            const C o = c.xo[row];
-            v = j < 0 ? csub(v, o) : cadd(v, o);
-        }
-        return (mp & 1) ? C{-v.x, -v.y} : v;
+        const C e = c.xe[row], o = c.xo[row];
+        const real_t<C> se = (mp & 1) ? -1 : 1;
+        const real_t<C> so = (j < 0 ? -c.wo_on : c.wo_on) * se;
+        return C{se * e.x + so * o.x, se * e.y + so * o.y};
     }
     __device__ void store_pair(const Ctx &c, int k, C zk, C zmk) const {
         const size_t row = (size_t)(L - 1 - k) * L * Nep;  // b = L-1-k: Z(beta_b) = zmk
@@ -767,6 +827,7 @@ struct BetaInvPairIO {
 struct ShtInvPhiIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const cd *G;
     double *map;
     int L, Nm;
@@ -776,7 +837,8 @@ struct ShtInvPhiIO {
     };
     __device__ Ctx at(int t) const { return Ctx{G + (size_t)t * L, map + (size_t)t * Nm}; }
     __device__ cd load(const Ctx &c, int m) const {
-        return m >= 0 ? c.src[m] : cconj(c.src[-m]);
+        const cd v = c.src[m < 0 ? -m : m];
+        return cd{v.x, m < 0 ? -v.y : v.y};
     }
     __device__ void store(const Ctx &c, int p, cd v) const { c.dst[p] = v.x; }
 };
@@ -784,6 +846,7 @@ struct ShtInvPhiIO {
 struct ShtFwdPhiIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const double *map;
     cd *F1;
     int L, Nm;
@@ -898,6 +961,7 @@ static inline int nnp_of(int N) { return ((2 * N - 1) + 31) / 32 * 32; }
 struct GenInvAlphaIO {  // line (b, n); in m; out a
     using C = cd;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const cd *W1;
     cd *W2;
     int L, Nn, Nnp, Nm;
@@ -915,6 +979,7 @@ struct GenInvAlphaIO {  // line (b, n); in m; out a
 struct GenInvGammaIO {  // line (a, b); in n; out g
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const cd *W2;
     cd *grid;
     int L, N, Nnp, Nm, Ng;
@@ -932,6 +997,7 @@ struct GenInvGammaIO {  // line (a, b); in n; out g
 struct GenFwdGammaIO {  // line (a, b); in g; out n
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const cd *grid;
     cd *V1;
     int L, N, Nnp, Nm, Ng;
@@ -949,6 +1015,7 @@ struct GenFwdGammaIO {  // line (a, b); in g; out n
 struct GenFwdAlphaIO {  // line (b, n); in a; out m
     using C = cd;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
+    static constexpr int kBatch = 16;  // loads in flight per thread
     const cd *V1;
     cd *V2;
     int L, Nn, Nnp, Nm;

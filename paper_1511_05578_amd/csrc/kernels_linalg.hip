@@ -70,17 +70,17 @@ hipError_t launch_delta_fill(double *tab, int Lmax, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Parity-folded beta stage: out[r][c] = (i^par) * sum_k A^{par(c)}[r][k] in[k][c].
-// Real GEMM over interleaved (re, im) columns; tile 64 rows x 32 complex
+// Real GEMM over interleaved (re, im) columns for layouts whose column parity
+// varies inside a tile (general Wigner transforms): both matrices are applied
+// and each column keeps its parity's result.  Tile 64 rows x 32 complex
 // columns x 16 k; each thread owns 4 rows x 2 complex columns.
-// UNIFORM: all columns of a tile share one parity (curvelet layout, Nep % 32 == 0).
 // ---------------------------------------------------------------------------
-template <bool UNIFORM>
 __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int Nep, int mode,
                                                    int par0, const double *__restrict__ Ae,
                                                    const double *__restrict__ Ao,
                                                    const double *__restrict__ in,
                                                    double *__restrict__ out) {
-    __shared__ double As[UNIFORM ? 1 : 2][16][64];
+    __shared__ double As[2][16][64];
     __shared__ double Bs[16][64];
     const int tid = threadIdx.x;
     const int tr = tid / 16, tc = tid % 16;
@@ -91,31 +91,18 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
         if (mode == 0) return (c / Nep) & 1;
         return ((c / Nep) + (c % Nep) + par0) & 1;
     };
-    const int tpar = parity(c0 < ncols ? c0 : 0);
-    const double *Au = tpar ? Ao : Ae;
-    double acc[4][4];
+    double acc[4][4], acc2[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[i][e] = 0.0;
-    double acc2[UNIFORM ? 1 : 4][UNIFORM ? 1 : 4];
-    if constexpr (!UNIFORM) {
-#pragma unroll
-        for (int i = 0; i < (UNIFORM ? 1 : 4); ++i)
-#pragma unroll
-            for (int e = 0; e < (UNIFORM ? 1 : 4); ++e) acc2[i][e] = 0.0;
-    }
+        for (int e = 0; e < 4; ++e) acc[i][e] = acc2[i][e] = 0.0;
     for (int k0 = 0; k0 < K; k0 += 16) {
         for (int i = tid; i < 1024; i += 256) {
             const int rr = i / 16, kk = i % 16;
             const int r = r0 + rr, k = k0 + kk;
             const bool ok = (r < M && k < K);
-            if constexpr (UNIFORM) {
-                As[0][kk][rr] = ok ? Au[(size_t)r * K + k] : 0.0;
-            } else {
-                As[0][kk][rr] = ok ? Ae[(size_t)r * K + k] : 0.0;
-                As[UNIFORM ? 0 : 1][kk][rr] = ok ? Ao[(size_t)r * K + k] : 0.0;
-            }
+            As[0][kk][rr] = ok ? Ae[(size_t)r * K + k] : 0.0;
+            As[1][kk][rr] = ok ? Ao[(size_t)r * K + k] : 0.0;
         }
         for (int i = tid; i < 1024; i += 256) {
             const int kk = i / 64, cc = i % 64;
@@ -132,12 +119,11 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const double a = As[0][kk][tr + 16 * i];
+                const double ao = As[1][kk][tr + 16 * i];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[i][e] += a * b[e];
-                if constexpr (!UNIFORM) {
-                    const double ao = As[UNIFORM ? 0 : 1][kk][tr + 16 * i];
-#pragma unroll
-                    for (int e = 0; e < (UNIFORM ? 1 : 4); ++e) acc2[i][e] += ao * b[e];
+                for (int e = 0; e < 4; ++e) {
+                    acc[i][e] += a * b[e];
+                    acc2[i][e] += ao * b[e];
                 }
             }
         }
@@ -151,17 +137,9 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
         for (int q = 0; q < 2; ++q) {
             const int c = c0 + tc * 2 + q;
             if (c >= ncols) continue;
-            int par;
-            double re, im;
-            if constexpr (UNIFORM) {
-                par = tpar;
-                re = acc[i][2 * q];
-                im = acc[i][2 * q + 1];
-            } else {
-                par = parity(c);
-                re = par ? acc2[i][2 * q] : acc[i][2 * q];
-                im = par ? acc2[i][2 * q + 1] : acc[i][2 * q + 1];
-            }
+            const int par = parity(c);
+            const double re = par ? acc2[i][2 * q] : acc[i][2 * q];
+            const double im = par ? acc2[i][2 * q + 1] : acc[i][2 * q + 1];
             double *o = out + (size_t)r * ld + 2 * (size_t)c;
             if (par) {
                 o[0] = -im;
@@ -282,12 +260,8 @@ hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0
         return hipGetLastError();
     }
     dim3 grid((ncols + 31) / 32, (M + 63) / 64);
-    if (mode == 0 && Nep % 32 == 0)
-        hipLaunchKernelGGL(k_beta_gemm<true>, grid, dim3(256), 0, st, M, K, ncols, Nep, mode,
-                           par0, Aeven, Aodd, (const double *)in, (double *)out);
-    else
-        hipLaunchKernelGGL(k_beta_gemm<false>, grid, dim3(256), 0, st, M, K, ncols, Nep, mode,
-                           par0, Aeven, Aodd, (const double *)in, (double *)out);
+    hipLaunchKernelGGL(k_beta_gemm, grid, dim3(256), 0, st, M, K, ncols, Nep, mode, par0, Aeven,
+                       Aodd, (const double *)in, (double *)out);
     return hipGetLastError();
 }
 
