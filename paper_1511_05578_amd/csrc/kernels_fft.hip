@@ -252,6 +252,15 @@ __device__ __forceinline__ void dft_small(C *v) {
 
 __device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
 
+// Keeps loaded values in registers at this point: an empty asm statement that
+// takes them as inputs, so that the compiler issues (and waits for) a whole
+// batch of loads here instead of sinking each load into the conditional block
+// that uses it, one wait per element.
+template <class C>
+__device__ __forceinline__ void materialize(const C &v) {
+    asm volatile("" ::"v"(v.x), "v"(v.y));
+}
+
 // Orders one line's LDS exchange.  When a line lives in a single wavefront
 // (P <= 1024) the exchange is wave-local: a wavefront-scope fence keeps the
 // compiler from moving LDS accesses across it, and a wave's LDS instructions
@@ -406,17 +415,18 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
             const auto c = io.at(line);
 #pragma unroll
             for (int h8 = 0; h8 < 16; h8 += IO::kBatch) {
-                C raw[IO::kBatch];
+                C raw[IO::kBatch], pw[IO::kBatch];
 #pragma unroll
                 for (int e = 0; e < IO::kBatch; ++e) {
                     const int t = tid + T * (h8 + e);
-                    raw[e] = io.load(c, B.j0 + (t < B.Kin ? t : B.Kin - 1));
+                    const int tc = t < B.Kin ? t : B.Kin - 1;
+                    raw[e] = io.load(c, B.j0 + tc);
+                    pw[e] = B.pre[tc];
                 }
 #pragma unroll
                 for (int e = 0; e < IO::kBatch; ++e) {
                     const int t = tid + T * (h8 + e);
-                    const C pw = B.pre[t < B.Kin ? t : B.Kin - 1];
-                    v[h8 + e] = t < B.Kin ? cmul(raw[e], pw) : C{0, 0};
+                    v[h8 + e] = cscale(cmul(raw[e], pw[e]), (real_t<C>)(t < B.Kin ? 1 : 0));
                 }
             }
         } else {
@@ -433,17 +443,23 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
             const auto c = io.at(lns);
 #pragma unroll
             for (int h8 = 0; h8 < 16; h8 += IO::kBatch) {
-                C raw[IO::kBatch];
+                C raw[IO::kBatch], pw[IO::kBatch];
 #pragma unroll
                 for (int e = 0; e < IO::kBatch; ++e) {
                     const int t = tl + T * (h8 + e);
-                    raw[e] = io.load(c, B.j0 + (t < B.Kin ? t : B.Kin - 1));
+                    const int tc = t < B.Kin ? t : B.Kin - 1;
+                    raw[e] = io.load(c, B.j0 + tc);
+                    pw[e] = B.pre[tc];
+                }
+#pragma unroll
+                for (int e = 0; e < IO::kBatch; ++e) {
+                    materialize(raw[e]);
+                    materialize(pw[e]);
                 }
 #pragma unroll
                 for (int e = 0; e < IO::kBatch; ++e) {
                     const int t = tl + T * (h8 + e);
-                    const C pw = B.pre[t < B.Kin ? t : B.Kin - 1];
-                    if (t < B.Kin) dst[t] = cmul(raw[e], pw);
+                    if (t < B.Kin) dst[t] = cmul(raw[e], pw[e]);
                 }
             }
         }
@@ -476,6 +492,8 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
                     pq[e] = B.post[q < 0 ? 0 : (q < B.Kout ? q : B.Kout - 1)];
                 }
 #pragma unroll
+                for (int e = 0; e < 8; ++e) materialize(pq[e]);
+#pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int q = tid + T * (h8 + e) - qlo;
                     if (q >= 0 && q < B.Kout)
@@ -495,6 +513,8 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
                 const int q = tid + T * (h8 + e) - qlo;
                 pq[e] = B.post[q < 0 ? 0 : (q < B.Kout ? q : B.Kout - 1)];
             }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) materialize(pq[e]);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int q = tid + T * (h8 + e) - qlo;
@@ -640,8 +660,8 @@ struct InvGammaIO {
     }
     __device__ C load(const Ctx &c, int n) const {
         const C v = c.src[(n < 0 ? -n : n) >> 1];
-        const real_t<C> z = 0;
-        return (n & 1) ? C{z, z} : C{v.x, n < 0 ? -v.y : v.y};
+        const real_t<C> keep = (n & 1) ? 0 : 1, sg = n < 0 ? -keep : keep;
+        return C{keep * v.x, sg * v.y};
     }
     __device__ void store(const Ctx &c, int g, C v) const { c.dst[g] = C{v.x, 0}; }
 };
@@ -672,12 +692,11 @@ struct InvGammaPackIO {
     __device__ C load(const Ctx &c, int n) const {
         // s2 is a valid pointer even for a lone last line (it then repeats s1)
         const int k = (n < 0 ? -n : n) >> 1;
-        const C c1 = c.s1[k], c2r = c.s2[k];
-        const real_t<C> z = 0;
-        const C c2 = c.two ? c2r : C{z, z};
-        const real_t<C> sg = n < 0 ? -1 : 1;  // conjugate both for n < 0
-        const C r{c1.x - sg * c2.y, sg * c1.y + c2.x};
-        return (n & 1) ? C{z, z} : r;
+        const C c1 = c.s1[k], c2 = c.s2[k];
+        const real_t<C> keep = (n & 1) ? 0 : 1;        // odd n: zero
+        const real_t<C> w2 = c.two ? keep : 0;         // no second line: zero
+        const real_t<C> sg = n < 0 ? -1 : 1;           // conjugate both for n < 0
+        return C{keep * c1.x - sg * w2 * c2.y, sg * keep * c1.y + w2 * c2.x};
     }
     __device__ void store(const Ctx &c, int g, C v) const {
         c.d1[g] = C{v.x, 0};
@@ -738,7 +757,7 @@ struct FwdGammaPackIO {
     __device__ C load(const Ctx &c, int g) const {
         // s2 is a valid pointer even for a lone last line (it then repeats s1)
         const real_t<C> a = c.s1[g].x, b = c.s2[g].x;
-        return C{a, c.two ? b : (real_t<C>)0};
+        return C{a, (real_t<C>)(c.two ? 1 : 0) * b};
     }
     __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
         if (n & 1) return;
