@@ -93,9 +93,12 @@ __device__ __forceinline__ void fft_lds(C *buf, const C *__restrict__ tw, int la
     }
 }
 
+// Lines per 256-thread work-group of the small engine: P/4 threads per line
+// (one radix-4 butterfly each per stage), at most 64 lines.  Few lines per
+// group keep enough work-groups to spread small stages over the device.
 template <int P>
 struct LinesFor {
-    static constexpr int v = (4096 / P) > 64 ? 64 : (4096 / P) < 1 ? 1 : (4096 / P);
+    static constexpr int v = (1024 / P) > 64 ? 64 : (1024 / P) < 1 ? 1 : (1024 / P);
 };
 
 template <int P, int LINES, class IO>
