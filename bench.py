@@ -1,11 +1,11 @@
 """Benchmark: spin-0 curvelet analysis + synthesis round trips on one MI355X.
 
 Default workload (one step): one real map at L = 256, lambda = 2, J0 = 2 (J = 8,
-scales j = 2..8 with L_j = 8, 16, 32, 64, 128, 256, 256), complex128 SO(3)
+scales j = 2..8 with L_j = 8, 16, 32, 64, 128, 256, 256), real float64 SO(3)
 grids, FP64 throughout: curvelet analysis (map -> scaling map + 7 grids)
 followed by curvelet synthesis (-> map).  Inputs are resident in HBM before
 timing.  Other workloads: --L, --batch (maps per call) and --precision
-(fp64 | fp32 | bf16x3: complex64 grids, reduced-precision contractions).
+(fp64 | fp32 | bf16x3: float32 grids, reduced-precision contractions).
 
 Prints ONE JSON line.  `value` is round trips (maps) per second.  `roofline` is
 for the kernel stage with the largest device time, timed live with HIP events
@@ -26,6 +26,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+# Band-limit from which the analysis beta stage runs as an odd-length DFT
+# (even/odd m' line pairs through the Bluestein engine) instead of a GEMM.
+BETA_FFT_MIN_L = 256
 
 METRIC = "curvelet fwd+inv transforms/s at L=256,1024; rel-L2 err vs FP64; p99 latency"
 HBM_PEAK_GBS = 8000.0
@@ -61,11 +65,13 @@ def stage_models(L, lam=2.0, J0=2, B=16.0):
     map, keyed (stage, L_j): one launch per scale, scales of equal L_j summed.
 
     bytes: each stage's input read once and output written once (B = 16 bytes
-    per complex128, 8 per complex64).  flops: contractions 4 per
-    (l, m, m', n>=0) term of the parity-folded sums (complex x real
-    multiply-add); beta GEMMs 2 per multiply-add of the L_j x L_j real matrix
-    on the 2*L_j*Ne real columns; DFT stages 5 n log2 n per complex line of
-    length n = 2L_j - 1.
+    per complex128, 8 per complex64; the grids are real, B / 2 per element).
+    flops: contractions 4 per (l, m, m', n>=0) term of the parity-folded sums
+    (complex x real multiply-add); beta GEMMs 2 per multiply-add of the
+    L_j x L_j real matrix on the 2*L_j*Ne real columns; DFT stages
+    5 n log2 n per complex line of length n = 2L_j - 1 (from L_j =
+    BETA_FFT_MIN_L on, the analysis beta stage is such a DFT stage over
+    (L_j + 1) / 2 * Ne line pairs).
     """
     m = {}
 
@@ -78,11 +84,14 @@ def stage_models(L, lam=2.0, J0=2, B=16.0):
         terms = sum((l + 1) * (l + 1) * (l // 2 + 1) for l in range(g["llo"], g["lhi"] + 1))
         cube = Lj * Lj * Ne * B
         w2 = Lj * Nm * (h + 1) * B
-        grid = Nm * Lj * Nm * B
+        grid = Nm * Lj * Nm * B / 2  # real grid
         v1 = Lj * Nm * Ne * B
         fft = 5.0 * Nm * math.log2(Nm)
         add("contract_inv", Lj, cube, 4.0 * terms)
-        add("beta_gemm_inv", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
+        if Lj >= BETA_FFT_MIN_L:  # one DFT line per even/odd m' line pair
+            add("beta_gemm_inv", Lj, 2 * cube, ((Lj + 1) // 2) * Ne * fft)
+        else:
+            add("beta_gemm_inv", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
         add("alpha_dft_inv", Lj, cube + w2, Lj * (h + 1) * fft)
         add("gamma_dft_inv", Lj, w2 + grid, Nm * Lj * fft)
         add("gamma_dft_fwd", Lj, grid + v1, Nm * Lj * fft)
@@ -112,6 +121,8 @@ def kernel_symbol(stage, Lj, prec):
               "k_bluestein<%d, ..., %s<%s> >" % (P, io[stage], c)
         return eng
     mode = {"fp64": "", "fp32": "<1>", "bf16x3": "<2>"}[prec]
+    if stage == "beta_gemm_inv" and Lj >= BETA_FFT_MIN_L:
+        return "k_blue_r16<%d, BetaInvPairIO<%s> >" % (P, c)
     if stage.startswith("beta"):
         return {"fp64": "k_beta_mfma", "fp32": "k_beta_mfma_f32", "bf16x3": "k_beta_mfma_bf16x3"}[prec]
     if stage == "contract_inv":
@@ -159,7 +170,8 @@ def recorded_traffic(workload_key, kernel):
     return None
 
 
-def grid_bytes(L, lam=2.0, J0=2, B=16.0):
+def grid_bytes(L, lam=2.0, J0=2, B=8.0):
+    """Bytes of one map's real grids, B bytes per element."""
     return sum(g["Nm"] * g["L"] * g["Nm"] * B for g in scale_geoms(L, lam, J0))
 
 
@@ -233,7 +245,7 @@ def main():
     from paper_1511_05578_amd import api, inputs
 
     L, lam, J0, NB, prec = args.L, 2.0, 2, args.batch, args.precision
-    EB = 16.0 if prec == "fp64" else 8.0
+    EB = 16.0 if prec == "fp64" else 8.0  # complex element of the intermediates
     ctx = api.Context(L, 0)
     ctx.prepare(L, lam, J0)
     if args.stream and NB != 1:
@@ -283,13 +295,13 @@ def main():
 
     vs64 = None
     if prec != "fp64" and grids is not None:
-        # the first map's grids against the FP64 path's (complex128)
+        # the first map's grids against the FP64 path's (float64)
         s64, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64")
         num = den = 0.0
         mx = mref = 0.0
         for a, b in zip(grids[0], g64[0]):
             for i0 in range(0, a.shape[0], 64):  # in slabs: bounded temporaries
-                d = a[i0:i0 + 64].to(torch.complex128) - b[i0:i0 + 64]
+                d = a[i0:i0 + 64].to(torch.float64) - b[i0:i0 + 64]
                 num += torch.linalg.norm(d).item() ** 2
                 den += torch.linalg.norm(b[i0:i0 + 64]).item() ** 2
                 mx = max(mx, d.abs().max().item())
@@ -334,7 +346,7 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    gname = "complex128" if prec == "fp64" else "complex64"
+    gname = "real float64" if prec == "fp64" else "real float32"
     work = ("%d real spin-0 map%s%s, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, %s grids%s, %s, "
             "analysis+synthesis round trip" % (
                 NB, "" if NB == 1 else "s",
@@ -358,10 +370,10 @@ def main():
         "data": "synthetic: f_lm ~ N(0,(l+1)^-2) real-map coefficients, seeds 0..%d" % (NB - 1),
         "config": {"workload": work, "L": L, "lambda": lam, "J0": J0, "batch": NB,
                    "precision": prec, "stream": bool(args.stream),
-                   "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, EB)},
+                   "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, EB / 2)},
         "round_trip_rel_l2": err,
         "source": source_fingerprint(),
-        "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, EB) / (HBM_PEAK_GBS * 1e9) * 1e3,
+        "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, EB / 2) / (HBM_PEAK_GBS * 1e9) * 1e3,
         "roofline": roof,
         "stages": stages,
         "stages_by_bandlimit": {"%s@%d" % k: round(v[1] / args.steps, 4) for k, v in sorted(detail.items())},

@@ -244,8 +244,10 @@ class Context:
         return out
 
     def grid_dtype(self, precision=CVL_FP64):
+        """Element type of the curvelet grids: the coefficients of a real map
+        are real, float64 (precision "fp64") or float32 ("fp32", "bf16x3")."""
         t = self.torch
-        return t.complex128 if _prec(precision) == CVL_FP64 else t.complex64
+        return t.float64 if _prec(precision) == CVL_FP64 else t.float32
 
     def alloc_outputs(self, L, lam=2.0, J0=2, batch=1, precision=CVL_FP64):
         t = self.torch
@@ -258,7 +260,7 @@ class Context:
 
     def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None, precision=CVL_FP64):
         """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids);
-        grids are complex128 (precision "fp64") or complex64 ("fp32", "bf16x3")."""
+        grids are float64 (precision "fp64") or float32 ("fp32", "bf16x3")."""
         t = self.torch
         single = maps.dim() == 2
         if single:
@@ -331,22 +333,26 @@ class Context:
                                                 _stream(t)))
         return flm_acc
 
-    def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None):
+    # The scaling part is FP64 at every precision; `precision` only names the
+    # streaming workspace (cvl_workspace_bytes of the same parameters) to use.
+    def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None, precision=CVL_FP64):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
         if out is None:
             out = t.empty((Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1))
-        _check(lib.cvl_curvelet_scaling_analysis(self.h, ctypes.byref(params(L, lam, J0)),
-                                                 flm.data_ptr(), out.data_ptr(), ws.data_ptr(),
-                                                 ws.numel(), _stream(t)))
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
+        p = params(L, lam, J0, precision=precision)
+        _check(lib.cvl_curvelet_scaling_analysis(self.h, ctypes.byref(p), flm.data_ptr(),
+                                                 out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                 _stream(t)))
         return out
 
-    def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2):
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1))
-        _check(lib.cvl_curvelet_scaling_synthesis(self.h, ctypes.byref(params(L, lam, J0)),
-                                                  scal.data_ptr(), flm_acc.data_ptr(), ws.data_ptr(),
-                                                  ws.numel(), _stream(self.torch)))
+    def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2, precision=CVL_FP64):
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
+        p = params(L, lam, J0, precision=precision)
+        _check(lib.cvl_curvelet_scaling_synthesis(self.h, ctypes.byref(p), scal.data_ptr(),
+                                                  flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                  _stream(self.torch)))
         return flm_acc
 
     def round_trip_streamed(self, fmap, lam=2.0, J0=2, precision=CVL_FP64, on_grid=None):
@@ -357,7 +363,7 @@ class Context:
         L = fmap.shape[-2]
         flm = self.sht_forward(fmap)
         acc = t.zeros(L * L, dtype=t.complex128, device=self.device)
-        scal = self.scaling_analysis(flm, L, lam, J0)
+        scal = self.scaling_analysis(flm, L, lam, J0, precision=precision)
         J = num_scales(L, lam, J0)
         Lt, _ = scale_shape(L, J, lam, J0)
         buf = t.empty((2 * Lt - 1) * Lt * (2 * Lt - 1), dtype=self.grid_dtype(precision),
@@ -369,7 +375,7 @@ class Context:
             if on_grid is not None:
                 on_grid(j, g)
             self.synthesis_scale(g, L, j, acc, lam, J0, precision=precision)
-        self.scaling_synthesis(scal, L, acc, lam, J0)
+        self.scaling_synthesis(scal, L, acc, lam, J0, precision=precision)
         return self.sht_inverse(acc, L), scal
 
     def delta_block(self, l):

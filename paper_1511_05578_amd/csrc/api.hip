@@ -886,7 +886,7 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
     const int L = P->L;
     TagScope tag(g.L);
     if (precision != CVL_FP64) {
-        cf *grid = (cf *)grid_out;
+        float *grid = (float *)grid_out;
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_CONTRACT_INV,
                launch_contract_inv_mx(precision, g, L, ctx->delta, B.fpad, S.psi, b0, st));
@@ -899,7 +899,7 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
         LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
         return CVL_OK;
     }
-    cd *grid = (cd *)grid_out;
+    double *grid = (double *)grid_out;
     cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
     LAUNCH(ST_CONTRACT_INV, launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, b0, st));
     if (S.beta_fft)
@@ -919,7 +919,7 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
     const int L = P->L;
     TagScope tag(g.L);
     if (precision != CVL_FP64) {
-        const cf *grid = (const cf *)grid_in;
+        const float *grid = (const float *)grid_in;
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full_f, grid, b0, st));
         LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
@@ -930,7 +930,7 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
         LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, S.ngroups, B.facc, st));
         return CVL_OK;
     }
-    const cd *grid = (const cd *)grid_in;
+    const double *grid = (const double *)grid_in;
     cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
     LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, b0, st));
     LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, b0, b1, st));

@@ -112,8 +112,8 @@ hipError_t launch_delta_fill(double *tab, int Lmax, hipStream_t st);
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
                             cd *W2, hipStream_t st);
 hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
-                            cd *grid, hipStream_t st);
-hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                            double *grid, hipStream_t st);
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const double *grid,
                             cd *V1, hipStream_t st);
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
                             cd *V2, hipStream_t st);
@@ -128,10 +128,10 @@ hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf
 // The same four stages in single precision (complex64 cubes and grids).
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1, cf *W2,
                             hipStream_t st);
-hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2, cf *grid,
-                            hipStream_t st);
-hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid, cf *V1,
-                            hipStream_t st);
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
+                            float *grid, hipStream_t st);
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const float *grid,
+                            cf *V1, hipStream_t st);
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1, cf *V2,
                             hipStream_t st);
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,

@@ -613,7 +613,8 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BlueT<typename I
 // ---------------------------------------------------------------------------
 // Curvelet (real map, even n) stage IO.
 // Cube / plane layouts: X, W1, V2, Z: [r][m][nn] with m in [0, L), nn = n/2 + h,
-// row length Nep.  W2: [b][a][k], k = n/2 in [0, h].  V1: [b][a][nn].
+// row length Nep.  W2: [b][a][k], k = n/2 in [0, h].  V1: [b][a][nn].  The
+// grid is real (double or float), [a][b][g].
 // ---------------------------------------------------------------------------
 
 // alpha DFT of the analysis: line (b, k >= 0); input over m in (-L, L) with the
@@ -643,7 +644,7 @@ struct InvAlphaIO {
     __device__ void store(const Ctx &c, int a, C v) const { c.out[(size_t)a * (h + 1)] = v; }
 };
 
-// gamma DFT of the analysis, one real line (a, b) per transform; written as (re, 0).
+// gamma DFT of the analysis, one real line (a, b) per transform into the real grid.
 // Coefficients: even n from W2 (n < 0 by conjugation), odd n zero.
 template <class C_>
 struct InvGammaIO {
@@ -651,11 +652,11 @@ struct InvGammaIO {
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 16;  // loads in flight per thread
     const C *W2;
-    C *grid;
+    real_t<C> *grid;
     int L, h, Nm;
     struct Ctx {
         const C *src;
-        C *dst;
+        real_t<C> *dst;
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
@@ -666,7 +667,7 @@ struct InvGammaIO {
         const real_t<C> keep = (n & 1) ? 0 : 1, sg = n < 0 ? -keep : keep;
         return C{keep * v.x, sg * v.y};
     }
-    __device__ void store(const Ctx &c, int g, C v) const { c.dst[g] = C{v.x, 0}; }
+    __device__ void store(const Ctx &c, int g, C v) const { c.dst[g] = v.x; }
 };
 
 // gamma DFT of the analysis, two real lines (2p, 2p+1) per complex transform:
@@ -677,11 +678,11 @@ struct InvGammaPackIO {
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 8;  // two loads per element
     const C *W2;
-    C *grid;
+    real_t<C> *grid;
     int L, h, Nm, nreal;
     struct Ctx {
         const C *s1, *s2;
-        C *d1, *d2;
+        real_t<C> *d1, *d2;
         bool two;
     };
     __device__ Ctx at(int p) const {
@@ -702,37 +703,37 @@ struct InvGammaPackIO {
         return C{keep * c1.x - sg * w2 * c2.y, sg * keep * c1.y + w2 * c2.x};
     }
     __device__ void store(const Ctx &c, int g, C v) const {
-        c.d1[g] = C{v.x, 0};
-        if (c.two) c.d2[g] = C{v.y, 0};
+        c.d1[g] = v.x;
+        if (c.two) c.d2[g] = v.y;
     }
 };
 
-// gamma DFT of the synthesis on the real part of line (a, b).  The line is
-// real, so c_-n = conj c_n: only even n >= 0 are kept, V1[b][a][n/2].
+// gamma DFT of the synthesis on line (a, b) of the real grid, so
+// c_-n = conj c_n: only even n >= 0 are kept, V1[b][a][n/2].
 template <class C_>
 struct FwdGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 16;  // loads in flight per thread
-    const C *grid;
+    const real_t<C> *grid;
     C *V1;
     int L, h, Nm;
     struct Ctx {
-        const C *src;
+        const real_t<C> *src;
         C *dst;  // V1[b][a][0]
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
         return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * (h + 1)};
     }
-    __device__ C load(const Ctx &c, int g) const { return C{c.src[g].x, 0}; }
+    __device__ C load(const Ctx &c, int g) const { return C{c.src[g], 0}; }
     __device__ void store(const Ctx &c, int n, C v) const {
         if ((n & 1) || n < 0) return;
         c.dst[n / 2] = v;
     }
 };
 
-// gamma DFT of the synthesis, real parts of lines (2p, 2p+1) packed as
+// gamma DFT of the synthesis, real lines (2p, 2p+1) of the grid packed as
 // z = w1 + i w2; with Z_n its DFT, c1_n = (Z_n + conj Z_-n)/2 and
 // c2_n = (Z_n - conj Z_-n)/(2i); even n >= 0 kept.
 template <class C_>
@@ -740,11 +741,11 @@ struct FwdGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
     static constexpr int kBatch = 16;  // loads in flight per thread
-    const C *grid;
+    const real_t<C> *grid;
     C *V1;
     int L, h, Nm, nreal;
     struct Ctx {
-        const C *s1, *s2;
+        const real_t<C> *s1, *s2;
         C *d1, *d2;  // V1[b][a][0] of both lines
         bool two;
     };
@@ -759,7 +760,7 @@ struct FwdGammaPackIO {
     }
     __device__ C load(const Ctx &c, int g) const {
         // s2 is a valid pointer even for a lone last line (it then repeats s1)
-        const real_t<C> a = c.s1[g].x, b = c.s2[g].x;
+        const real_t<C> a = c.s1[g], b = c.s2[g];
         return C{a, (real_t<C>)(c.two ? 1 : 0) * b};
     }
     __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
@@ -888,8 +889,8 @@ static hipError_t inv_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *W1
     return run_bluestein(io, g.L * (g.h + 1), B, st);
 }
 template <class C>
-static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2, C *grid,
-                              hipStream_t st) {
+static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2,
+                              real_t<C> *grid, hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
         InvGammaPackIO<C> io{W2, grid, g.L, g.h, g.Nm, nreal};
@@ -899,8 +900,8 @@ static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2
     return run_bluestein(io, nreal, B, st);
 }
 template <class C>
-static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *grid, C *V1,
-                              hipStream_t st) {
+static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const real_t<C> *grid,
+                              C *V1, hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
         FwdGammaPackIO<C> io{grid, V1, g.L, g.h, g.Nm, nreal};
@@ -935,12 +936,12 @@ hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd 
                             hipStream_t st) {
     return inv_alpha_t(g, B, W1, W2, st);
 }
-hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2, cd *grid,
-                            hipStream_t st) {
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                            double *grid, hipStream_t st) {
     return inv_gamma_t(g, B, W2, grid, st);
 }
-hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid, cd *V1,
-                            hipStream_t st) {
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const double *grid,
+                            cd *V1, hipStream_t st) {
     return fwd_gamma_t(g, B, grid, V1, st);
 }
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1, cd *V2,
@@ -951,12 +952,12 @@ hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W
                             hipStream_t st) {
     return inv_alpha_t(g, B, W1, W2, st);
 }
-hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2, cf *grid,
-                            hipStream_t st) {
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
+                            float *grid, hipStream_t st) {
     return inv_gamma_t(g, B, W2, grid, st);
 }
-hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid, cf *V1,
-                            hipStream_t st) {
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const float *grid,
+                            cf *V1, hipStream_t st) {
     return fwd_gamma_t(g, B, grid, V1, st);
 }
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1, cf *V2,
