@@ -1,11 +1,13 @@
 """Benchmark: spin-0 curvelet analysis + synthesis round trips on one MI355X.
 
 Default workload (one step): one real map at L = 256, lambda = 2, J0 = 2 (J = 8,
-scales j = 2..8 with L_j = 8, 16, 32, 64, 128, 256, 256), real float64 SO(3)
+scales j = 2..8 with L_j = 8, 16, 32, 64, 128, 256, 256), complex128 SO(3)
 grids, FP64 throughout: curvelet analysis (map -> scaling map + 7 grids)
 followed by curvelet synthesis (-> map).  Inputs are resident in HBM before
 timing.  Other workloads: --L, --batch (maps per call) and --precision
-(fp64 | fp32 | bf16x3: float32 grids, reduced-precision contractions).
+(fp64 | fp32 | bf16x3: complex64 grids, reduced-precision contractions) and
+--real-grids (float64 / float32 grids: the real coefficients without the zero
+imaginary parts).
 
 Prints ONE JSON line.  `value` is round trips (maps) per second.  `roofline` is
 for the kernel stage with the largest device time, timed live with HIP events
@@ -60,12 +62,13 @@ def scale_geoms(L, lam=2.0, J0=2):
     return out
 
 
-def stage_models(L, lam=2.0, J0=2, B=16.0):
+def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None):
     """Algorithmic bytes / flops of each kernel stage per round trip of one
     map, keyed (stage, L_j): one launch per scale, scales of equal L_j summed.
 
     bytes: each stage's input read once and output written once (B = 16 bytes
-    per complex128, 8 per complex64; the grids are real, B / 2 per element).
+    per complex128, 8 per complex64; GB per grid element, B by default, B / 2
+    for real grids).
     flops: contractions 4 per (l, m, m', n>=0) term of the parity-folded sums
     (complex x real multiply-add); beta GEMMs 2 per multiply-add of the
     L_j x L_j real matrix on the 2*L_j*Ne real columns; DFT stages
@@ -74,6 +77,7 @@ def stage_models(L, lam=2.0, J0=2, B=16.0):
     (L_j + 1) / 2 * Ne line pairs).
     """
     m = {}
+    GB = B if GB is None else GB
 
     def add(name, Lj, nbytes, flops):
         b, f, n = m.get((name, Lj), (0.0, 0.0, 0))
@@ -84,7 +88,7 @@ def stage_models(L, lam=2.0, J0=2, B=16.0):
         terms = sum((l + 1) * (l + 1) * (l // 2 + 1) for l in range(g["llo"], g["lhi"] + 1))
         cube = Lj * Lj * Ne * B
         w2 = Lj * Nm * (h + 1) * B
-        grid = Nm * Lj * Nm * B / 2  # real grid
+        grid = Nm * Lj * Nm * GB
         v1 = Lj * Nm * Ne * B
         fft = 5.0 * Nm * math.log2(Nm)
         add("contract_inv", Lj, cube, 4.0 * terms)
@@ -109,7 +113,7 @@ def bluestein_size(Lj):
     return P
 
 
-def kernel_symbol(stage, Lj, prec):
+def kernel_symbol(stage, Lj, prec, real_grids=False):
     """HIP kernel (template instance) that runs a stage at band-limit L_j."""
     c = "cd" if prec == "fp64" else "cf"
     P = bluestein_size(Lj)
@@ -117,8 +121,11 @@ def kernel_symbol(stage, Lj, prec):
           "gamma_dft_inv": "InvGammaPackIO" if P >= 256 else "InvGammaIO",
           "gamma_dft_fwd": "FwdGammaPackIO" if P >= 256 else "FwdGammaIO"}
     if stage in io:
-        eng = "k_blue_r16<%d, %s<%s> >" % (P, io[stage], c) if P >= 256 else \
-              "k_bluestein<%d, ..., %s<%s> >" % (P, io[stage], c)
+        targs = c
+        if stage.startswith("gamma"):  # grid element type
+            targs += ", " + (("double" if prec == "fp64" else "float") if real_grids else c)
+        eng = "k_blue_r16<%d, %s<%s> >" % (P, io[stage], targs) if P >= 256 else \
+              "k_bluestein<%d, ..., %s<%s> >" % (P, io[stage], targs)
         return eng
     mode = {"fp64": "", "fp32": "<1>", "bf16x3": "<2>"}[prec]
     if stage == "beta_gemm_inv" and Lj >= BETA_FFT_MIN_L:
@@ -170,8 +177,8 @@ def recorded_traffic(workload_key, kernel):
     return None
 
 
-def grid_bytes(L, lam=2.0, J0=2, B=8.0):
-    """Bytes of one map's real grids, B bytes per element."""
+def grid_bytes(L, lam=2.0, J0=2, B=16.0):
+    """Bytes of one map's grids, B bytes per element."""
     return sum(g["Nm"] * g["L"] * g["Nm"] * B for g in scale_geoms(L, lam, J0))
 
 
@@ -231,6 +238,8 @@ def main():
                     help="add this many point sources to each map (projected onto band-limit L)")
     ap.add_argument("--stream", action="store_true",
                     help="one scale at a time through the streaming interface (batch 1)")
+    ap.add_argument("--real-grids", action="store_true",
+                    help="real (float64 / float32) grids instead of complex ones")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after timing, copy BYTES of device memory once (a plain copy kernel "
@@ -246,6 +255,8 @@ def main():
 
     L, lam, J0, NB, prec = args.L, 2.0, 2, args.batch, args.precision
     EB = 16.0 if prec == "fp64" else 8.0  # complex element of the intermediates
+    RG = args.real_grids
+    GB = EB / 2 if RG else EB  # grid element
     ctx = api.Context(L, 0)
     ctx.prepare(L, lam, J0)
     if args.stream and NB != 1:
@@ -266,14 +277,15 @@ def main():
         grids = None
 
         def step():
-            r, _ = ctx.round_trip_streamed(maps[0], lam, J0, precision=prec)
+            r, _ = ctx.round_trip_streamed(maps[0], lam, J0, precision=prec, real_grids=RG)
             rec[0].copy_(r)
     else:
-        scal, grids = ctx.alloc_outputs(L, lam, J0, NB, precision=prec)
+        scal, grids = ctx.alloc_outputs(L, lam, J0, NB, precision=prec, real_grids=RG)
 
         def step():
-            ctx.curvelet_analysis(maps, lam, J0, out=(scal, grids), precision=prec)
-            ctx.curvelet_synthesis(scal, grids, L, lam, J0, out=rec, precision=prec)
+            ctx.curvelet_analysis(maps, lam, J0, out=(scal, grids), precision=prec, real_grids=RG)
+            ctx.curvelet_synthesis(scal, grids, L, lam, J0, out=rec, precision=prec,
+                                   real_grids=RG)
 
     for _ in range(args.warmup):
         step()
@@ -295,13 +307,13 @@ def main():
 
     vs64 = None
     if prec != "fp64" and grids is not None:
-        # the first map's grids against the FP64 path's (float64)
-        s64, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64")
+        # the first map's grids against the FP64 path's
+        s64, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64", real_grids=RG)
         num = den = 0.0
         mx = mref = 0.0
         for a, b in zip(grids[0], g64[0]):
             for i0 in range(0, a.shape[0], 64):  # in slabs: bounded temporaries
-                d = a[i0:i0 + 64].to(torch.float64) - b[i0:i0 + 64]
+                d = a[i0:i0 + 64].to(b.dtype) - b[i0:i0 + 64]
                 num += torch.linalg.norm(d).item() ** 2
                 den += torch.linalg.norm(b[i0:i0 + 64]).item() ** 2
                 mx = max(mx, d.abs().max().item())
@@ -311,7 +323,7 @@ def main():
         del s64, g64
 
     ms = dt * 1e3 / args.steps
-    models = stage_models(L, lam, J0, EB)
+    models = stage_models(L, lam, J0, EB, GB)
     stages = {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in prof.items() if v[0]}
     # dominant kernel: the (stage, L_j) pair with the most device time
     top = max((k for k in detail if k in models), key=lambda k: detail[k][1])
@@ -330,9 +342,10 @@ def main():
         roof = {"bound": "mfma" if top[0].startswith(("contract", "beta")) else "alu",
                 "achieved": flops_per_launch / t_top / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    wkey = "L%d_b%d_%s%s%s" % (L, NB, prec, "_stream" if args.stream else "",
-                               "_ps%d" % args.point_sources if args.point_sources else "")
-    sym = kernel_symbol(top[0], top[1], prec)
+    wkey = "L%d_b%d_%s%s%s%s" % (L, NB, prec, "_stream" if args.stream else "",
+                                 "_ps%d" % args.point_sources if args.point_sources else "",
+                                 "_rg" if RG else "")
+    sym = kernel_symbol(top[0], top[1], prec, RG)
     roof["traffic"] = recorded_traffic(wkey, sym)
     roof["kernel"] = sym
     roof["stage"] = top[0]
@@ -346,7 +359,8 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    gname = "real float64" if prec == "fp64" else "real float32"
+    gname = ("float64" if prec == "fp64" else "float32") if RG else \
+        ("complex128" if prec == "fp64" else "complex64")
     work = ("%d real spin-0 map%s%s, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, %s grids%s, %s, "
             "analysis+synthesis round trip" % (
                 NB, "" if NB == 1 else "s",
@@ -370,10 +384,10 @@ def main():
         "data": "synthetic: f_lm ~ N(0,(l+1)^-2) real-map coefficients, seeds 0..%d" % (NB - 1),
         "config": {"workload": work, "L": L, "lambda": lam, "J0": J0, "batch": NB,
                    "precision": prec, "stream": bool(args.stream),
-                   "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, EB / 2)},
+                   "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, GB)},
         "round_trip_rel_l2": err,
         "source": source_fingerprint(),
-        "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, EB / 2) / (HBM_PEAK_GBS * 1e9) * 1e3,
+        "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, GB) / (HBM_PEAK_GBS * 1e9) * 1e3,
         "roofline": roof,
         "stages": stages,
         "stages_by_bandlimit": {"%s@%d" % k: round(v[1] / args.steps, 4) for k, v in sorted(detail.items())},

@@ -34,7 +34,7 @@
  *   not checked: they propagate to the outputs.
  * - Precision: by default every step is IEEE FP64 (round to nearest, FMA
  *   contraction).  The curvelet calls also offer a reduced-precision path
- *   (cvl_params.precision): float32 coefficient grids, the two
+ *   (cvl_params.precision): complex64 (or float32) coefficient grids, the two
  *   l-contractions on the matrix cores in FP32 or in split bfloat16 ("BF16x3",
  *   a*b = hi*hi + hi*lo + lo*hi) with FP32 accumulation, the beta stage and the
  *   FFTs in FP32, while the Delta table, the SHTs, the scaling part and the
@@ -60,10 +60,11 @@ enum {
 
 /* Flags of cvl_params. */
 #define CVL_REAL 1u        /* real map (f_{l,-m} = (-1)^m conj f_lm); required */
+#define CVL_REAL_GRIDS 2u  /* curvelet grids of real elements (see cvl_curvelet_analysis) */
 
 /* Precision of the curvelet calls (cvl_params.precision). */
-#define CVL_FP64 0         /* everything FP64, float64 grids */
-#define CVL_FP32 1         /* FP32 MFMA contractions, FP32 FFT/beta, float32 grids */
+#define CVL_FP64 0         /* everything FP64, complex128 (or double) grids */
+#define CVL_FP32 1         /* FP32 MFMA contractions, FP32 FFT/beta, complex64 (or float) grids */
 #define CVL_BF16X3 2       /* split-bfloat16 MFMA contractions, otherwise as CVL_FP32 */
 
 typedef struct { double re, im; } cvl_c128;   /* layout of torch.complex128 */
@@ -76,7 +77,8 @@ typedef struct cvl_ctx cvl_ctx;
  * 0 or L (each scale then uses N_j = L_j).  lambda > 1: dilation.  J0 >= 1:
  * lowest curvelet scale, J0 <= J where J = ceil(log_lambda L).  spin: must
  * be 0.  precision: CVL_FP64, CVL_FP32 or CVL_BF16X3 (curvelet calls only;
- * it selects the grid element type).  flags: CVL_REAL. */
+ * it selects the grid element type).  flags: CVL_REAL (required), optionally
+ * CVL_REAL_GRIDS; other bits are rejected. */
 typedef struct {
     int L;
     int N;
@@ -147,10 +149,12 @@ int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid,
  *   scal_maps + i * L_Phi * (2L_Phi-1): the scaling coefficients as a real MW
  *     map of band-limit L_Phi;
  *   grids[i * nJ + (j - J0)], nJ = J - J0 + 1: SO(3) grid W^(j)[a][b][g] of
- *     scale j, (2L_j-1) x L_j x (2L_j-1), of double (CVL_FP64) or float
- *     (CVL_FP32, CVL_BF16X3) elements.  The curvelet coefficients of a real
- *     map are real, so the grids store them as reals: the conjugate symmetry
- *     of real signals halves their memory (Sec. III-A-3).
+ *     scale j, (2L_j-1) x L_j x (2L_j-1), of cvl_c128 (CVL_FP64) or cvl_c64
+ *     (CVL_FP32, CVL_BF16X3) elements.  For a real map the curvelet
+ *     coefficients are real: the imaginary parts are written as 0.  With
+ *     CVL_REAL_GRIDS the elements are double (CVL_FP64) or float instead,
+ *     holding the same real parts: the conjugate symmetry of real signals
+ *     halves the grids' memory and traffic (Sec. III-A-3).
  * `grids` is a HOST array of batch * nJ device pointers. */
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
                           const double *maps, double *scal_maps,
@@ -158,7 +162,11 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
                           void *stream);
 
 /* Curvelet synthesis (Sec. II-D-2, exact reconstruction): the inverse of
- * cvl_curvelet_analysis on its range.  Writes `batch` real maps.  Same layouts as cvl_curvelet_analysis. */
+ * cvl_curvelet_analysis on its range.  Synthesis is linear, and a grid's
+ * imaginary part only feeds the imaginary part of the synthesised map, so the
+ * real map returned is the synthesis of the grids' real parts (the imaginary
+ * parts are not used).  Writes `batch` real maps.  Same layouts (and
+ * CVL_REAL_GRIDS element types) as cvl_curvelet_analysis. */
 int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
                            const double *scal_maps, const void *const *grids,
                            double *maps, void *ws, size_t ws_bytes, void *stream);
@@ -181,7 +189,7 @@ int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j,
                                 const cvl_c128 *flm, void *grid, void *ws,
                                 size_t ws_bytes, void *stream);
 
-/* flm_acc += f^(j)_lm, the synthesis of scale j's (real) grid. */
+/* flm_acc += f^(j)_lm, the synthesis of the real part of scale j's grid. */
 int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j,
                                  const void *grid, cvl_c128 *flm_acc, void *ws,
                                  size_t ws_bytes, void *stream);

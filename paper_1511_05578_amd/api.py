@@ -13,7 +13,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcurvelet.so")
 
 CVL_OK, CVL_EINVAL, CVL_ENOMEM, CVL_EDEVICE, CVL_EUNSUPPORTED = 0, -1, -2, -3, -4
-CVL_REAL = 1
+CVL_REAL, CVL_REAL_GRIDS = 1, 2
 CVL_FP64, CVL_FP32, CVL_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": CVL_FP64, "fp32": CVL_FP32, "bf16x3": CVL_BF16X3}
 
@@ -107,7 +107,9 @@ def _prec(precision):
     return int(precision)
 
 
-def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL, precision=CVL_FP64):
+def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL, precision=CVL_FP64, real_grids=False):
+    if real_grids:
+        flags |= CVL_REAL_GRIDS
     return CvlParams(L, N, float(lam), J0, spin, _prec(precision), flags)
 
 
@@ -243,24 +245,28 @@ class Context:
             out.append((2 * Lj - 1, Lj, 2 * Nj - 1))
         return out
 
-    def grid_dtype(self, precision=CVL_FP64):
-        """Element type of the curvelet grids: the coefficients of a real map
-        are real, float64 (precision "fp64") or float32 ("fp32", "bf16x3")."""
+    def grid_dtype(self, precision=CVL_FP64, real_grids=False):
+        """Element type of the curvelet grids: complex128 (precision "fp64") or
+        complex64 ("fp32", "bf16x3") with zero imaginary parts, or with
+        real_grids float64 / float32 holding the same (real) coefficients."""
         t = self.torch
-        return t.float64 if _prec(precision) == CVL_FP64 else t.float32
+        if real_grids:
+            return t.float64 if _prec(precision) == CVL_FP64 else t.float32
+        return t.complex128 if _prec(precision) == CVL_FP64 else t.complex64
 
-    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1, precision=CVL_FP64):
+    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, real_grids=False):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
         scal = t.empty((batch, Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
-        dt = self.grid_dtype(precision)
+        dt = self.grid_dtype(precision, real_grids)
         grids = [[t.empty(s, dtype=dt, device=self.device)
                   for s in self.grid_shapes(L, lam, J0)] for _ in range(batch)]
         return scal, grids
 
-    def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None, precision=CVL_FP64):
+    def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None, precision=CVL_FP64,
+                          real_grids=False):
         """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids);
-        grids are float64 (precision "fp64") or float32 ("fp32", "bf16x3")."""
+        grids of grid_dtype(precision, real_grids)."""
         t = self.torch
         single = maps.dim() == 2
         if single:
@@ -268,15 +274,15 @@ class Context:
         assert maps.dtype == t.float64 and maps.is_contiguous()
         batch, L = maps.shape[0], maps.shape[1]
         if out is None:
-            out = self.alloc_outputs(L, lam, J0, batch, precision)
+            out = self.alloc_outputs(L, lam, J0, batch, precision, real_grids)
         scal, grids = out
         flat = [g for per in grids for g in per]
-        dt = self.grid_dtype(precision)
+        dt = self.grid_dtype(precision, real_grids)
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
         ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision))
-        p = params(L, lam, J0, precision=precision)
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
         _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(p), batch,
                                          maps.data_ptr(), scal.data_ptr(), arr, ws.data_ptr(),
                                          ws.numel(), _stream(t)))
@@ -284,7 +290,8 @@ class Context:
             return scal[0], grids[0]
         return scal, grids
 
-    def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None, precision=CVL_FP64):
+    def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None, precision=CVL_FP64,
+                           real_grids=False):
         t = self.torch
         single = scal.dim() == 2
         if single:
@@ -294,40 +301,42 @@ class Context:
         if out is None:
             out = t.empty((batch, L, 2 * L - 1), dtype=t.float64, device=self.device)
         flat = [g for per in grids for g in per]
-        dt = self.grid_dtype(precision)
+        dt = self.grid_dtype(precision, real_grids)
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
         ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision))
-        p = params(L, lam, J0, precision=precision)
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
         _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(p), batch,
                                           scal.data_ptr(), arr, out.data_ptr(), ws.data_ptr(),
                                           ws.numel(), _stream(t)))
         return out[0] if single else out
 
     # ---- streaming (one scale at a time) ----
-    def analysis_scale(self, flm, L, j, lam=2.0, J0=2, out=None, precision=CVL_FP64):
+    def analysis_scale(self, flm, L, j, lam=2.0, J0=2, out=None, precision=CVL_FP64,
+                       real_grids=False):
         """Grid of scale j from harmonic coefficients flm (L^2 complex128)."""
         t = self.torch
         assert flm.dtype == t.complex128 and flm.is_contiguous() and flm.numel() == L * L
+        dt = self.grid_dtype(precision, real_grids)
         if out is None:
             Lj, _ = scale_shape(L, j, lam, J0)
-            out = t.empty((2 * Lj - 1, Lj, 2 * Lj - 1), dtype=self.grid_dtype(precision),
-                          device=self.device)
-        assert out.dtype == self.grid_dtype(precision) and out.is_contiguous()
+            out = t.empty((2 * Lj - 1, Lj, 2 * Lj - 1), dtype=dt, device=self.device)
+        assert out.dtype == dt and out.is_contiguous()
         ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
-        p = params(L, lam, J0, precision=precision)
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
         _check(lib.cvl_curvelet_analysis_scale(self.h, ctypes.byref(p), j, flm.data_ptr(),
                                                out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(t)))
         return out
 
-    def synthesis_scale(self, grid, L, j, flm_acc, lam=2.0, J0=2, precision=CVL_FP64):
+    def synthesis_scale(self, grid, L, j, flm_acc, lam=2.0, J0=2, precision=CVL_FP64,
+                        real_grids=False):
         """flm_acc += f^(j)_lm from scale j's grid."""
         t = self.torch
-        assert grid.dtype == self.grid_dtype(precision) and grid.is_contiguous()
+        assert grid.dtype == self.grid_dtype(precision, real_grids) and grid.is_contiguous()
         assert flm_acc.dtype == t.complex128 and flm_acc.numel() == L * L
         ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
-        p = params(L, lam, J0, precision=precision)
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
         _check(lib.cvl_curvelet_synthesis_scale(self.h, ctypes.byref(p), j, grid.data_ptr(),
                                                 flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
                                                 _stream(t)))
@@ -355,7 +364,8 @@ class Context:
                                                   _stream(self.torch)))
         return flm_acc
 
-    def round_trip_streamed(self, fmap, lam=2.0, J0=2, precision=CVL_FP64, on_grid=None):
+    def round_trip_streamed(self, fmap, lam=2.0, J0=2, precision=CVL_FP64, on_grid=None,
+                            real_grids=False):
         """Analysis + synthesis of one real map, one scale at a time (a single
         grid buffer of the largest scale is reused).  on_grid(j, grid), if
         given, sees each scale's grid between its analysis and synthesis."""
@@ -366,15 +376,17 @@ class Context:
         scal = self.scaling_analysis(flm, L, lam, J0, precision=precision)
         J = num_scales(L, lam, J0)
         Lt, _ = scale_shape(L, J, lam, J0)
-        buf = t.empty((2 * Lt - 1) * Lt * (2 * Lt - 1), dtype=self.grid_dtype(precision),
-                      device=self.device)
+        buf = t.empty((2 * Lt - 1) * Lt * (2 * Lt - 1),
+                      dtype=self.grid_dtype(precision, real_grids), device=self.device)
         for j in range(J0, J + 1):
             Lj, _ = scale_shape(L, j, lam, J0)
             g = buf[:(2 * Lj - 1) * Lj * (2 * Lj - 1)].view(2 * Lj - 1, Lj, 2 * Lj - 1)
-            self.analysis_scale(flm, L, j, lam, J0, out=g, precision=precision)
+            self.analysis_scale(flm, L, j, lam, J0, out=g, precision=precision,
+                                real_grids=real_grids)
             if on_grid is not None:
                 on_grid(j, g)
-            self.synthesis_scale(g, L, j, acc, lam, J0, precision=precision)
+            self.synthesis_scale(g, L, j, acc, lam, J0, precision=precision,
+                                 real_grids=real_grids)
         self.scaling_synthesis(scal, L, acc, lam, J0, precision=precision)
         return self.sht_inverse(acc, L), scal
 

@@ -347,6 +347,8 @@ int check_params(const cvl_params *p, int *J) {
     if (p->precision != CVL_FP64 && p->precision != CVL_FP32 && p->precision != CVL_BF16X3)
         return fail(CVL_EINVAL, "precision=%d is not CVL_FP64, CVL_FP32 or CVL_BF16X3",
                     p->precision);
+    if (p->flags & ~(CVL_REAL | CVL_REAL_GRIDS))
+        return fail(CVL_EINVAL, "flags=0x%x: unknown bits", p->flags);
     if (J) *J = JJ;
     return CVL_OK;
 }
@@ -879,14 +881,17 @@ static CurveletBufs carve_curvelet(const Plan *P, int precision, void *ws, size_
     return B;
 }
 
-// Analysis of one scale from the padded harmonic coefficients B.fpad.
+static bool real_grids(const cvl_params *p) { return (p->flags & CVL_REAL_GRIDS) != 0; }
+
+// Analysis of one scale from the padded harmonic coefficients B.fpad into a
+// complex (zero imaginary parts) or, with real_grid, a real grid.
 static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
-                              const CurveletBufs &B, void *grid_out, hipStream_t st) {
+                              bool real_grid, const CurveletBufs &B, void *grid_out,
+                              hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
     TagScope tag(g.L);
     if (precision != CVL_FP64) {
-        float *grid = (float *)grid_out;
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_CONTRACT_INV,
                launch_contract_inv_mx(precision, g, L, ctx->delta, B.fpad, S.psi, b0, st));
@@ -896,10 +901,12 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
             LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep,
                                                      S.betaf.Cinv, S.betaf.Sinv, b0, b1, st));
         LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
-        LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, grid, st));
+        if (real_grid)
+            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, (float *)grid_out, st));
+        else
+            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, (cf *)grid_out, st));
         return CVL_OK;
     }
-    double *grid = (double *)grid_out;
     cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
     LAUNCH(ST_CONTRACT_INV, launch_contract_inv(g, L, ctx->delta, B.fpad, S.psi, b0, st));
     if (S.beta_fft)
@@ -908,20 +915,28 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
         LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Cinv,
                                              S.beta.Sinv, b0, b1, st));
     LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full, b1, b0, st));
-    LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, b0, grid, st));
+    if (real_grid)
+        LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, b0, (double *)grid_out, st));
+    else
+        LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full, b0, (cd *)grid_out, st));
     return CVL_OK;
 }
 
-// Synthesis of one scale: adds f^(j)_lm into the padded accumulator B.facc.
+// Synthesis of one scale (real parts of a complex grid, or a real grid): adds
+// f^(j)_lm into the padded accumulator B.facc.
 static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
-                               const CurveletBufs &B, const void *grid_in, hipStream_t st) {
+                               bool real_grid, const CurveletBufs &B, const void *grid_in,
+                               hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
     TagScope tag(g.L);
     if (precision != CVL_FP64) {
-        const float *grid = (const float *)grid_in;
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
-        LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full_f, grid, b0, st));
+        const BluesteinF &F = S.fwd_full_f;
+        if (real_grid)
+            LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, F, (const float *)grid_in, b0, st));
+        else
+            LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, F, (const cf *)grid_in, b0, st));
         LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
         LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Qp,
                                                  S.betaf.Qs, b1, b0, st));
@@ -930,9 +945,11 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
         LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, S.ngroups, B.facc, st));
         return CVL_OK;
     }
-    const double *grid = (const double *)grid_in;
     cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
-    LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, grid, b0, st));
+    if (real_grid)
+        LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, (const double *)grid_in, b0, st));
+    else
+        LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma(g, S.fwd_full, (const cd *)grid_in, b0, st));
     LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, b0, b1, st));
     LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
                                          S.beta.Qs, b1, b0, st));
@@ -963,7 +980,7 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
         if ((rc = sht_inverse_run(ctx, SP, B.fphi, Lp, smap, B.s0, B.s1, st))) return rc;
         for (int s = 0; s < nJ; ++s)
-            if ((rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, B,
+            if ((rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
                                          grids[(size_t)bi * nJ + s], st)))
                 return rc;
     }
@@ -989,7 +1006,7 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
         double *map = maps + (size_t)bi * L * (2 * L - 1);
         LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
         for (int s = 0; s < nJ; ++s)
-            if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, B,
+            if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
                                           grids[(size_t)bi * nJ + s], st)))
                 return rc;
         if ((rc = sht_forward_run(ctx, SP, smap, B.fphi, Lp, B.s0, B.s1, st))) return rc;
@@ -1019,7 +1036,7 @@ int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const 
     hipStream_t st = (hipStream_t)stream;
     CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
     LAUNCH(ST_MISC, launch_flm_pack(P->L, (const cd *)flm, B.fpad, st));
-    return analysis_scale_run(ctx, P, P->scales[s], p->precision, B, grid, st);
+    return analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B, grid, st);
 }
 
 int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const void *grid,
@@ -1032,7 +1049,7 @@ int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const
     CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
     const int L = P->L;
     LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
-    if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, B, grid, st))) return rc;
+    if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B, grid, st))) return rc;
     LAUNCH(ST_MISC, launch_flm_unpack(L, B.facc, (cd *)flm_acc, 1, st));
     return CVL_OK;
 }

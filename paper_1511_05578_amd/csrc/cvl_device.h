@@ -111,8 +111,13 @@ hipError_t launch_delta_fill(double *tab, int Lmax, hipStream_t st);
 // Bluestein stages.  Each returns hipSuccess or the launch error.
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
                             cd *W2, hipStream_t st);
+// gamma stages: complex grids (zero imaginary parts) or real grids
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                            cd *grid, hipStream_t st);
 hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
                             double *grid, hipStream_t st);
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                            cd *V1, hipStream_t st);
 hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const double *grid,
                             cd *V1, hipStream_t st);
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
@@ -128,8 +133,12 @@ hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf
 // The same four stages in single precision (complex64 cubes and grids).
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1, cf *W2,
                             hipStream_t st);
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2, cf *grid,
+                            hipStream_t st);
 hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
                             float *grid, hipStream_t st);
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid, cf *V1,
+                            hipStream_t st);
 hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const float *grid,
                             cf *V1, hipStream_t st);
 hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1, cf *V2,

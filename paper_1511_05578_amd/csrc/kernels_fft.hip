@@ -614,8 +614,18 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BlueT<typename I
 // Curvelet (real map, even n) stage IO.
 // Cube / plane layouts: X, W1, V2, Z: [r][m][nn] with m in [0, L), nn = n/2 + h,
 // row length Nep.  W2: [b][a][k], k = n/2 in [0, h].  V1: [b][a][nn].  The
-// grid is real (double or float), [a][b][g].
+// grid, [a][b][g], holds the real coefficients either as reals (G = real_t<C>)
+// or as complex numbers with a zero imaginary part (G = C).
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void grid_put(double *p, double x) { *p = x; }
+__device__ __forceinline__ void grid_put(float *p, float x) { *p = x; }
+__device__ __forceinline__ void grid_put(cd *p, double x) { *p = cd{x, 0.0}; }
+__device__ __forceinline__ void grid_put(cf *p, float x) { *p = cf{x, 0.0f}; }
+__device__ __forceinline__ double grid_get(const double *p) { return *p; }
+__device__ __forceinline__ float grid_get(const float *p) { return *p; }
+__device__ __forceinline__ double grid_get(const cd *p) { return p->x; }
+__device__ __forceinline__ float grid_get(const cf *p) { return p->x; }
 
 // alpha DFT of the analysis: line (b, k >= 0); input over m in (-L, L) with the
 // reality condition W1(b, -m, -n) = conj W1(b, m, n); output a in [0, 2L-1).
@@ -644,19 +654,19 @@ struct InvAlphaIO {
     __device__ void store(const Ctx &c, int a, C v) const { c.out[(size_t)a * (h + 1)] = v; }
 };
 
-// gamma DFT of the analysis, one real line (a, b) per transform into the real grid.
+// gamma DFT of the analysis, one real line (a, b) of the grid per transform.
 // Coefficients: even n from W2 (n < 0 by conjugation), odd n zero.
-template <class C_>
+template <class C_, class G>
 struct InvGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 16;  // loads in flight per thread
     const C *W2;
-    real_t<C> *grid;
+    G *grid;
     int L, h, Nm;
     struct Ctx {
         const C *src;
-        real_t<C> *dst;
+        G *dst;
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
@@ -667,22 +677,22 @@ struct InvGammaIO {
         const real_t<C> keep = (n & 1) ? 0 : 1, sg = n < 0 ? -keep : keep;
         return C{keep * v.x, sg * v.y};
     }
-    __device__ void store(const Ctx &c, int g, C v) const { c.dst[g] = v.x; }
+    __device__ void store(const Ctx &c, int g, C v) const { grid_put(c.dst + g, v.x); }
 };
 
 // gamma DFT of the analysis, two real lines (2p, 2p+1) per complex transform:
 // z_n = c1_n + i c2_n; line 2p is the real, line 2p+1 the imaginary part.
-template <class C_>
+template <class C_, class G>
 struct InvGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 8;  // two loads per element
     const C *W2;
-    real_t<C> *grid;
+    G *grid;
     int L, h, Nm, nreal;
     struct Ctx {
         const C *s1, *s2;
-        real_t<C> *d1, *d2;
+        G *d1, *d2;
         bool two;
     };
     __device__ Ctx at(int p) const {
@@ -703,30 +713,30 @@ struct InvGammaPackIO {
         return C{keep * c1.x - sg * w2 * c2.y, sg * keep * c1.y + w2 * c2.x};
     }
     __device__ void store(const Ctx &c, int g, C v) const {
-        c.d1[g] = v.x;
-        if (c.two) c.d2[g] = v.y;
+        grid_put(c.d1 + g, v.x);
+        if (c.two) grid_put(c.d2 + g, v.y);
     }
 };
 
 // gamma DFT of the synthesis on line (a, b) of the real grid, so
 // c_-n = conj c_n: only even n >= 0 are kept, V1[b][a][n/2].
-template <class C_>
+template <class C_, class G>
 struct FwdGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 16;  // loads in flight per thread
-    const real_t<C> *grid;
+    const G *grid;
     C *V1;
     int L, h, Nm;
     struct Ctx {
-        const real_t<C> *src;
+        const G *src;
         C *dst;  // V1[b][a][0]
     };
     __device__ Ctx at(int line) const {
         const int a = line / L, b = line % L;
         return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * (h + 1)};
     }
-    __device__ C load(const Ctx &c, int g) const { return C{c.src[g], 0}; }
+    __device__ C load(const Ctx &c, int g) const { return C{grid_get(c.src + g), 0}; }
     __device__ void store(const Ctx &c, int n, C v) const {
         if ((n & 1) || n < 0) return;
         c.dst[n / 2] = v;
@@ -736,16 +746,16 @@ struct FwdGammaIO {
 // gamma DFT of the synthesis, real lines (2p, 2p+1) of the grid packed as
 // z = w1 + i w2; with Z_n its DFT, c1_n = (Z_n + conj Z_-n)/2 and
 // c2_n = (Z_n - conj Z_-n)/(2i); even n >= 0 kept.
-template <class C_>
+template <class C_, class G>
 struct FwdGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
     static constexpr int kBatch = 16;  // loads in flight per thread
-    const real_t<C> *grid;
+    const G *grid;
     C *V1;
     int L, h, Nm, nreal;
     struct Ctx {
-        const real_t<C> *s1, *s2;
+        const G *s1, *s2;
         C *d1, *d2;  // V1[b][a][0] of both lines
         bool two;
     };
@@ -760,7 +770,7 @@ struct FwdGammaPackIO {
     }
     __device__ C load(const Ctx &c, int g) const {
         // s2 is a valid pointer even for a lone last line (it then repeats s1)
-        const real_t<C> a = c.s1[g], b = c.s2[g];
+        const real_t<C> a = grid_get(c.s1 + g), b = grid_get(c.s2 + g);
         return C{a, (real_t<C>)(c.two ? 1 : 0) * b};
     }
     __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
@@ -888,26 +898,26 @@ static hipError_t inv_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *W1
     InvAlphaIO<C> io{W1, W2, g.L, g.h, g.Nep, g.Nm};
     return run_bluestein(io, g.L * (g.h + 1), B, st);
 }
-template <class C>
-static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2,
-                              real_t<C> *grid, hipStream_t st) {
+template <class C, class G>
+static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2, G *grid,
+                              hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
-        InvGammaPackIO<C> io{W2, grid, g.L, g.h, g.Nm, nreal};
+        InvGammaPackIO<C, G> io{W2, grid, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
     }
-    InvGammaIO<C> io{W2, grid, g.L, g.h, g.Nm};
+    InvGammaIO<C, G> io{W2, grid, g.L, g.h, g.Nm};
     return run_bluestein(io, nreal, B, st);
 }
-template <class C>
-static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const real_t<C> *grid,
-                              C *V1, hipStream_t st) {
+template <class C, class G>
+static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const G *grid, C *V1,
+                              hipStream_t st) {
     const int nreal = g.Nm * g.L;
     if (B.P >= 256) {
-        FwdGammaPackIO<C> io{grid, V1, g.L, g.h, g.Nm, nreal};
+        FwdGammaPackIO<C, G> io{grid, V1, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
     }
-    FwdGammaIO<C> io{grid, V1, g.L, g.h, g.Nm};
+    FwdGammaIO<C, G> io{grid, V1, g.L, g.h, g.Nm};
     return run_bluestein(io, nreal, B, st);
 }
 template <class C>
@@ -936,9 +946,17 @@ hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd 
                             hipStream_t st) {
     return inv_alpha_t(g, B, W1, W2, st);
 }
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2, cd *grid,
+                            hipStream_t st) {
+    return inv_gamma_t(g, B, W2, grid, st);
+}
 hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
                             double *grid, hipStream_t st) {
     return inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid, cd *V1,
+                            hipStream_t st) {
+    return fwd_gamma_t(g, B, grid, V1, st);
 }
 hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const double *grid,
                             cd *V1, hipStream_t st) {
@@ -952,9 +970,17 @@ hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W
                             hipStream_t st) {
     return inv_alpha_t(g, B, W1, W2, st);
 }
+hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2, cf *grid,
+                            hipStream_t st) {
+    return inv_gamma_t(g, B, W2, grid, st);
+}
 hipError_t launch_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
                             float *grid, hipStream_t st) {
     return inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid, cf *V1,
+                            hipStream_t st) {
+    return fwd_gamma_t(g, B, grid, V1, st);
 }
 hipError_t launch_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const float *grid,
                             cf *V1, hipStream_t st) {

@@ -34,7 +34,7 @@ def footprint_bytes(L, lam=2.0, J0=2, batch=1):
     J = api.num_scales(L, lam, J0)
     for j in range(J0, J + 1):
         Lj, Nj = api.scale_shape(L, j, lam, J0)
-        grids += (2 * Lj - 1) * Lj * (2 * Nj - 1) * 8  # real float64
+        grids += (2 * Lj - 1) * Lj * (2 * Nj - 1) * 16  # complex128
     Lp = api.scaling_bandlimit(L, lam, J0)
     maps = 2 * L * (2 * L - 1) * 8 + Lp * (2 * Lp - 1) * 8
     return batch * (grids + maps)

@@ -62,6 +62,7 @@ def test_workspace_grows_with_L():
     (dict(L=32, J0=6), api.CVL_EINVAL),
     (dict(L=32, spin=2), api.CVL_EUNSUPPORTED),
     (dict(L=32, flags=0), api.CVL_EUNSUPPORTED),
+    (dict(L=32, flags=api.CVL_REAL | 4), api.CVL_EINVAL),
 ])
 def test_parameter_validation(kw, code):
     L = kw.pop("L")
@@ -71,6 +72,14 @@ def test_parameter_validation(kw, code):
     assert rc == code
     assert J.value == -7                       # nothing written on failure
     assert len(api.lib.cvl_last_error()) > 0
+
+
+def test_real_grids_flag_accepted():
+    p = api.params(32, real_grids=True)
+    assert p.flags == api.CVL_REAL | api.CVL_REAL_GRIDS
+    J = ctypes.c_int(-7)
+    assert api.lib.cvl_num_scales(ctypes.byref(p), ctypes.byref(J)) == api.CVL_OK
+    assert J.value == 5
 
 
 def test_null_arguments_rejected():
