@@ -252,13 +252,15 @@ Bluestein make_bluestein(int Nd, int Kin, int j0, int Kout, int k0, int sigma,
     B.post.resize(Kout);
     for (int t = 0; t < Kin; ++t) B.pre[t] = chirp(j0 + t, Nd, sigma);
     for (int t = 0; t < Kout; ++t) B.post[t] = chirp(k0 + t, Nd, sigma);
+    // Chirp kernel at lags s - (Kin - 1) = k - j - (k0 - j0), s < Kin + Kout - 1,
+    // stored circularly at its lag: output k0 + q then lands at position q.
     const long dmin = (long)k0 - j0 - (Kin - 1);
     std::vector<std::complex<ld>> v(B.P, 0);
     for (int s = 0; s < Kin + Kout - 1; ++s) {
         long x = s + dmin;
         long q = (x * x) % (2L * Nd);
         ld a = -sigma * kPiL * (ld)q / (ld)Nd;
-        v[s] = std::complex<ld>(std::cos(a), std::sin(a));
+        v[(s - (Kin - 1) + B.P) % B.P] = std::complex<ld>(std::cos(a), std::sin(a));
     }
     fft_ld(v);
     B.vhat.resize(B.P);

@@ -40,7 +40,8 @@ void beta_forward_mats(int L, double factor, std::vector<double> &Qp,
 // Bluestein (chirp-z) tables for
 //   out[k] = scale * sum_{j=j0}^{j0+Kin-1} in[j] exp(sigma 2 pi i j k / Nd),
 //   k in [k0, k0 + Kout),
-// evaluated as a circular convolution of length P (power of two >= Kin+Kout-1).
+// evaluated as a circular convolution of length P (power of two >= Kin+Kout-1)
+// whose position q holds output k0 + q.
 struct Bluestein {
     int Nd = 0, P = 0, Kin = 0, j0 = 0, Kout = 0, k0 = 0, sigma = 0;
     std::vector<std::complex<double>> pre;   // Kin:  exp(sigma i pi (j0+t)^2 / Nd)

@@ -131,10 +131,7 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BlueT<type
     for (int t = lane; t < P; t += TPL) buf[t] = cconj(cmul(buf[t], B.vhat[t]));
     __syncthreads();
     fft_lds<P, TPL>(buf, B.tw, lane);
-    for (int t = lane; t < B.Kout; t += TPL) {
-        const C c = cconj(buf[t + B.Kin - 1]);
-        buf[t + B.Kin - 1] = cmul(c, B.post[t]);
-    }
+    for (int t = lane; t < B.Kout; t += TPL) buf[t] = cmul(cconj(buf[t]), B.post[t]);
     __syncthreads();
     if constexpr (IO::kStore == IO_PAIR || IO::kStore == IO_STAGED_PAIR) {
         const int line = line0 + li;
@@ -142,7 +139,7 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BlueT<type
             const auto c = io.at(line);
             const int K = -B.k0;
             for (int k = lane; k <= K; k += TPL)
-                io.store_pair(c, k, buf[k + K + B.Kin - 1], buf[K - k + B.Kin - 1]);
+                io.store_pair(c, k, buf[k + K], buf[K - k]);
         }
     } else {
         for (int idx = tid; idx < LINES * B.Kout; idx += 256) {
@@ -155,7 +152,7 @@ __global__ __launch_bounds__(256) void k_bluestein(IO io, int nlines, BlueT<type
                 t = idx % B.Kout;
             }
             const int line = line0 + l;
-            if (line < nlines) io.store(io.at(line), B.k0 + t, smem[l * P + t + B.Kin - 1]);
+            if (line < nlines) io.store(io.at(line), B.k0 + t, smem[l * P + t]);
         }
     }
 }
@@ -418,6 +415,11 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
             const auto c = io.at(line);
 #pragma unroll
             for (int h8 = 0; h8 < 16; h8 += IO::kBatch) {
+                if (T * h8 >= B.Kin) {  // the whole batch lies past the input (uniform)
+#pragma unroll
+                    for (int e = 0; e < IO::kBatch; ++e) v[h8 + e] = C{0, 0};
+                    continue;
+                }
                 C raw[IO::kBatch], pw[IO::kBatch];
 #pragma unroll
                 for (int e = 0; e < IO::kBatch; ++e) {
@@ -446,6 +448,7 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
             const auto c = io.at(lns);
 #pragma unroll
             for (int h8 = 0; h8 < 16; h8 += IO::kBatch) {
+                if (T * h8 >= B.Kin) break;  // past the input (uniform)
                 C raw[IO::kBatch], pw[IO::kBatch];
 #pragma unroll
                 for (int e = 0; e < IO::kBatch; ++e) {
@@ -479,28 +482,29 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
 #pragma unroll
     for (int s = 0; s < 16; ++s) v[s] = cconj(cmul(v[s], vh[tid + T * s]));
     fft_r16<P>(v, lds, B.tw, tid);
-    // v[s] = conj(c[q]), q = tid + T*s; output k = k0 + q - (Kin - 1)
-    const int qlo = B.Kin - 1;
-    // post-chirp factors: loaded 8 at a time (clamped indices), so that a
-    // half line's loads are in flight together without doubling the registers
+    // v[s] = conj(c[q]), q = tid + T*s: output k = k0 + q for q < Kout.
+    // Post-chirp factors: loaded 8 at a time (clamped indices), so that a
+    // half line's loads are in flight together without doubling the
+    // registers; a half past the outputs is skipped (with Kout <= P/2, the
+    // usual case, one half and one round trip).
     if constexpr (IO::kStore == IO_DIRECT) {
         if (line < nlines) {
             const auto c = io.at(line);
 #pragma unroll
             for (int h8 = 0; h8 < 16; h8 += 8) {
+                if (T * h8 >= B.Kout) break;  // uniform
                 C pq[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int q = tid + T * (h8 + e) - qlo;
-                    pq[e] = B.post[q < 0 ? 0 : (q < B.Kout ? q : B.Kout - 1)];
+                    const int q = tid + T * (h8 + e);
+                    pq[e] = B.post[q < B.Kout ? q : B.Kout - 1];
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e) materialize(pq[e]);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int q = tid + T * (h8 + e) - qlo;
-                    if (q >= 0 && q < B.Kout)
-                        io.store(c, B.k0 + q, cmul(cconj(v[h8 + e]), pq[e]));
+                    const int q = tid + T * (h8 + e);
+                    if (q < B.Kout) io.store(c, B.k0 + q, cmul(cconj(v[h8 + e]), pq[e]));
                 }
             }
         }
@@ -510,18 +514,19 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
         line_sync<P>();
 #pragma unroll
         for (int h8 = 0; h8 < 16; h8 += 8) {
+            if (T * h8 >= B.Kout) break;  // uniform
             C pq[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int q = tid + T * (h8 + e) - qlo;
-                pq[e] = B.post[q < 0 ? 0 : (q < B.Kout ? q : B.Kout - 1)];
+                const int q = tid + T * (h8 + e);
+                pq[e] = B.post[q < B.Kout ? q : B.Kout - 1];
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) materialize(pq[e]);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int q = tid + T * (h8 + e) - qlo;
-                if (q >= 0 && q < B.Kout) buf[q] = cmul(cconj(v[h8 + e]), pq[e]);
+                const int q = tid + T * (h8 + e);
+                if (q < B.Kout) buf[q] = cmul(cconj(v[h8 + e]), pq[e]);
             }
         }
         __syncthreads();
