@@ -251,6 +251,9 @@ __device__ __forceinline__ void dft_small(C *v) {
 }
 
 __device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
+// Padded offset of an offset o that is a multiple of 16:
+// lpad(e + o) = lpad(e) + lpo(o) for every e.
+__host__ __device__ constexpr int lpo(int o) { return o + (o >> 4); }
 
 // Keeps loaded values in registers at this point: an empty asm statement that
 // takes them as inputs, so that the compiler issues (and waits for) a whole
@@ -287,22 +290,26 @@ struct R16 {
 };
 
 // Moves one line between passes through LDS, one real component at a time
-// (the LDS line holds P reals): element wpos(k) leaves v[k], element rpos(r)
-// arrives in v[r].
-template <int P, class C, class WP, class RP>
-__device__ __forceinline__ void exchange(C v[16], real_t<C> *lds, WP wpos, RP rpos) {
+// (the LDS line holds P reals): v[k] leaves to padded index wb + wo(k), v[r]
+// arrives from padded index rb + ro(r).  The bases are per thread, the
+// offsets compile-time constants, so every access is one base register plus
+// an immediate offset.
+template <int P, class C, class WO, class RO>
+__device__ __forceinline__ void exchange(C v[16], real_t<C> *lds, int wb, WO wo, int rb, RO ro) {
     real_t<C> nx[16];
+    real_t<C> *w = lds + wb;
+    const real_t<C> *r = lds + rb;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) lds[lpad(wpos(k))] = v[k].x;
+    for (int k = 0; k < 16; ++k) w[wo(k)] = v[k].x;
     line_sync<P>();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) nx[r] = lds[lpad(rpos(r))];
+    for (int i = 0; i < 16; ++i) nx[i] = r[ro(i)];
     line_sync<P>();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) lds[lpad(wpos(k))] = v[k].y;
+    for (int k = 0; k < 16; ++k) w[wo(k)] = v[k].y;
     line_sync<P>();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = C{nx[r], lds[lpad(rpos(r))]};
+    for (int i = 0; i < 16; ++i) v[i] = C{nx[i], r[ro(i)]};
     line_sync<P>();
 }
 
@@ -335,14 +342,20 @@ __device__ __forceinline__ void fft_r16(C v[16], real_t<C> *lds, const C *__rest
                                         int tid) {
     constexpr int T = R16<P>::T, RC = R16<P>::RC;
     dft16(v);  // pass Ns = 1: butterfly tid, no twiddles
-    exchange<P>(v, lds, [&](int k) { return 16 * tid + k; }, [&](int r) { return tid + T * r; });
+    // element 16 tid + k leaves v[k] (lpad = 17 tid + k), element tid + T r
+    // arrives in v[r] (T is a multiple of 16)
+    const int rb = lpad(tid);
+    exchange<P>(
+        v, lds, 17 * tid, [](int k) { return k; }, rb, [](int r) { return lpo(T * r); });
     twiddle16(v, tw[(tid & 15) * (P / 256)]);
     dft16(v);  // pass Ns = 16
     if constexpr (RC > 1) {
         constexpr int NB = 16 / RC;  // butterflies per thread
+        // element (tid >> 4) 256 + (tid & 15) + 16 k leaves v[k], element
+        // tid + T (idx / RC) + 256 (idx % RC) arrives in v[idx]
         exchange<P>(
-            v, lds, [&](int k) { return (tid >> 4) * 256 + (tid & 15) + 16 * k; },
-            [&](int idx) { return tid + T * (idx / RC) + 256 * (idx % RC); });
+            v, lds, lpad((tid >> 4) * 256 + (tid & 15)), [](int k) { return lpo(16 * k); }, rb,
+            [](int idx) { return lpo(T * (idx / RC) + 256 * (idx % RC)); });
         // v[q*RC + r] = element j + 256 r, j = tid + T q
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
