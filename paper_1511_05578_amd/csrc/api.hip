@@ -151,6 +151,12 @@ struct cvl_ctx {
     std::map<std::tuple<int, double, int>, std::unique_ptr<Plan>> plans;
     std::map<int, std::unique_ptr<ShtRt>> sht;
     std::map<std::pair<int, int>, std::unique_ptr<GenRt>> gen;
+    // side stream (and its fork / join events) per caller stream
+    struct Side {
+        hipStream_t s = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+    };
+    std::map<hipStream_t, Side> side;
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> pool;
@@ -377,27 +383,35 @@ int fwd_groups(const ScaleGeom &g) {
     return (g.L + gsz - 1) / gsz;
 }
 
-void curvelet_buf_elems(int L, double lam, int J0, int J, size_t *b0, size_t *b1) {
-    *b0 = *b1 = 0;
+// Elements of the two cube buffers of the scales at the top band-limit
+// (b0, b1) and of the side scales below it (sb0, sb1), which run
+// concurrently on a side stream with buffers of their own.
+void curvelet_buf_elems(int L, double lam, int J0, int J, size_t *b0, size_t *b1, size_t *sb0,
+                        size_t *sb1) {
+    *b0 = *b1 = *sb0 = *sb1 = 0;
+    const int top = scale_bandlimit(J, L, lam);
     for (int j = J0; j <= J; ++j) {
         ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
         size_t cube = (size_t)g.L * g.L * g.Nep;
         size_t w2 = (size_t)g.L * g.Nm * (g.h + 1);
         size_t part = (size_t)g.L * g.L * g.L;  // at most L_j groups
-        *b0 = std::max({*b0, cube, w2});
-        *b1 = std::max({*b1, cube, part});
+        size_t *x0 = g.L < top ? sb0 : b0, *x1 = g.L < top ? sb1 : b1;
+        *x0 = std::max({*x0, cube, w2});
+        *x1 = std::max({*x1, cube, part});
     }
 }
 
-// Workspace bytes of a curvelet call: two cube buffers (complex128, or
-// complex64 in reduced precision) and five L x L complex128 planes.
+// Workspace bytes of a curvelet call: two cube buffers for the top scales and
+// two for the side scales (complex128, or complex64 in reduced precision) and
+// six L x L complex128 planes.
 size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision) {
-    size_t b0, b1;
-    curvelet_buf_elems(L, lam, J0, J, &b0, &b1);
+    size_t b0, b1, sb0, sb1;
+    curvelet_buf_elems(L, lam, J0, J, &b0, &b1, &sb0, &sb1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     const int Lphi = scaling_bandlimit(L, lam, J0);
     size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
-    return align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) + 8 * kAlign;
+    return align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) + 8 * kAlign +
+           align_up(sb0 * esz) + align_up(sb1 * esz) + align_up((size_t)L * L * 16) + 3 * kAlign;
 }
 
 int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
@@ -622,6 +636,11 @@ void cvl_context_destroy(cvl_ctx *ctx) {
         (void)hipEventDestroy(std::get<3>(r));
     }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    for (auto &kv : ctx->side) {
+        (void)hipEventDestroy(kv.second.fork);
+        (void)hipEventDestroy(kv.second.join);
+        (void)hipStreamDestroy(kv.second.s);
+    }
     delete ctx;
 }
 
@@ -862,11 +881,13 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
 struct CurveletBufs {
     void *b0, *b1;
     cd *fpad, *facc, *s0, *s1, *fphi;
+    void *sb0, *sb1;  // cube buffers of the side scales
+    cd *sfacc;        // harmonic accumulator of the side scales' synthesis
 };
 
 static CurveletBufs carve_curvelet(const Plan *P, int precision, void *ws, size_t ws_bytes) {
-    size_t b0, b1;
-    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, &b0, &b1);
+    size_t b0, b1, sb0, sb1;
+    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, &b0, &b1, &sb0, &sb1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     Carver cv{(char *)ws, ws_bytes};
     CurveletBufs B;
@@ -878,7 +899,20 @@ static CurveletBufs carve_curvelet(const Plan *P, int precision, void *ws, size_
     B.s0 = cv.take<cd>(L2);
     B.s1 = cv.take<cd>(L2);
     B.fphi = cv.take<cd>((size_t)P->Lphi * P->Lphi);
+    B.sb0 = cv.take<char>(sb0 * esz);
+    B.sb1 = cv.take<char>(sb1 * esz);
+    B.sfacc = cv.take<cd>(L2);
     return B;
+}
+
+// The buffers a side-scale run uses: its own cubes and accumulator, the
+// shared (read-only) padded harmonic coefficients.
+static CurveletBufs side_bufs(const CurveletBufs &B) {
+    CurveletBufs S = B;
+    S.b0 = B.sb0;
+    S.b1 = B.sb1;
+    S.facc = B.sfacc;
+    return S;
 }
 
 static bool real_grids(const cvl_params *p) { return (p->flags & CVL_REAL_GRIDS) != 0; }
@@ -959,6 +993,76 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
     return CVL_OK;
 }
 
+// ---- side stream: the scales below the top band-limit run concurrently with
+// the top ones (they only meet in the sum over scales); every call forks and
+// joins it with events, so callers see plain stream order. ----
+static int get_side(cvl_ctx *ctx, hipStream_t st, cvl_ctx::Side **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->side.find(st);
+    if (it == ctx->side.end()) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(ctx->device);
+        cvl_ctx::Side sd;
+        hipError_t e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            if (sd.fork) (void)hipEventDestroy(sd.fork);
+            if (sd.s) (void)hipStreamDestroy(sd.s);
+            return fail(CVL_EDEVICE, "side stream creation failed: %s", hipGetErrorString(e));
+        }
+        it = ctx->side.emplace(st, sd).first;
+    }
+    *out = &it->second;
+    return CVL_OK;
+}
+
+static int side_fork(cvl_ctx::Side *sd, hipStream_t st) {
+    hipError_t e = hipEventRecord(sd->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sd->s, sd->fork, 0);
+    return e == hipSuccess ? CVL_OK : fail(CVL_EDEVICE, "side fork: %s", hipGetErrorString(e));
+}
+
+static int side_join(cvl_ctx::Side *sd, hipStream_t st) {
+    hipError_t e = hipEventRecord(sd->join, sd->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, sd->join, 0);
+    return e == hipSuccess ? CVL_OK : fail(CVL_EDEVICE, "side join: %s", hipGetErrorString(e));
+}
+
+// Leading scales (ordered by band-limit) below the top band-limit.
+static int side_count(const Plan *P) {
+    const int top = P->scales.back().g.L;
+    int n = 0;
+    while (n < (int)P->scales.size() && P->scales[n].g.L < top) ++n;
+    return n;
+}
+
+static int analysis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
+                           const CurveletBufs &B, void *const *grids, int s0, int s1,
+                           hipStream_t st) {
+    for (int s = s0; s < s1; ++s) {
+        int rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
+                                    grids[s], st);
+        if (rc) return rc;
+    }
+    return CVL_OK;
+}
+
+// Zeroes B.facc, then adds the synthesis of scales [s0, s1) into it.
+static int synthesis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
+                            const CurveletBufs &B, const void *const *grids, int s0, int s1,
+                            hipStream_t st) {
+    LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)P->L * P->L, st));
+    for (int s = s0; s < s1; ++s) {
+        int rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
+                                     grids[s], st);
+        if (rc) return rc;
+    }
+    return CVL_OK;
+}
+
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *maps,
                           double *scal_maps, void *const *grids, void *ws, size_t ws_bytes,
                           void *stream) {
@@ -972,17 +1076,23 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
     CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
-    const int L = P->L, Lp = P->Lphi;
+    const CurveletBufs BS = side_bufs(B);
+    const int L = P->L, Lp = P->Lphi, nside = side_count(P);
+    cvl_ctx::Side *sd = nullptr;
+    if (nside > 0 && (rc = get_side(ctx, st, &sd))) return rc;
     for (int bi = 0; bi < batch; ++bi) {
         const double *map = maps + (size_t)bi * L * (2 * L - 1);
         double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        void *const *g = grids + (size_t)bi * nJ;
         if ((rc = sht_forward_run(ctx, SL, map, B.fpad, L, B.s0, B.s1, st))) return rc;
         LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
         if ((rc = sht_inverse_run(ctx, SP, B.fphi, Lp, smap, B.s0, B.s1, st))) return rc;
-        for (int s = 0; s < nJ; ++s)
-            if ((rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
-                                         grids[(size_t)bi * nJ + s], st)))
-                return rc;
+        if (sd && (rc = side_fork(sd, st))) return rc;
+        rc = sd ? analysis_scales(ctx, P, p, BS, g, 0, nside, sd->s) : CVL_OK;
+        if (!rc) rc = analysis_scales(ctx, P, p, B, g, nside, nJ, st);
+        // joined even after an error: the next map (or call) reuses the buffers
+        const int rj = sd ? side_join(sd, st) : CVL_OK;
+        if (rc || (rc = rj)) return rc;
     }
     return CVL_OK;
 }
@@ -1000,15 +1110,22 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
     CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
-    const int L = P->L, Lp = P->Lphi;
+    const CurveletBufs BS = side_bufs(B);
+    const int L = P->L, Lp = P->Lphi, nside = side_count(P);
+    cvl_ctx::Side *sd = nullptr;
+    if (nside > 0 && (rc = get_side(ctx, st, &sd))) return rc;
     for (int bi = 0; bi < batch; ++bi) {
         const double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
         double *map = maps + (size_t)bi * L * (2 * L - 1);
-        LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
-        for (int s = 0; s < nJ; ++s)
-            if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
-                                          grids[(size_t)bi * nJ + s], st)))
-                return rc;
+        const void *const *g = grids + (size_t)bi * nJ;
+        // top scales into B.facc, side scales into their own accumulator,
+        // added in afterwards (a fixed order: results are deterministic)
+        if (sd && (rc = side_fork(sd, st))) return rc;
+        rc = sd ? synthesis_scales(ctx, P, p, BS, g, 0, nside, sd->s) : CVL_OK;
+        if (!rc) rc = synthesis_scales(ctx, P, p, B, g, nside, nJ, st);
+        const int rj = sd ? side_join(sd, st) : CVL_OK;
+        if (rc || (rc = rj)) return rc;
+        if (sd) LAUNCH(ST_MISC, launch_add(B.facc, BS.facc, (size_t)L * L, st));
         if ((rc = sht_forward_run(ctx, SP, smap, B.fphi, Lp, B.s0, B.s1, st))) return rc;
         LAUNCH(ST_MISC, launch_scale_flm(Lp, Lp, L, P->phifac, B.fphi, B.facc, 1, st));
         if ((rc = sht_inverse_run(ctx, SL, B.facc, L, map, B.s0, B.s1, st))) return rc;

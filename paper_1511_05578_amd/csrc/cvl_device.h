@@ -204,5 +204,6 @@ hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st);
 hipError_t launch_scale_flm(int Lphi, int Lsrc, int Ldst, const double *fac, const cd *src,
                             cd *dst, int accumulate, hipStream_t st);
 hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
+hipError_t launch_add(cd *dst, const cd *src, size_t n, hipStream_t st);  // dst += src
 
 }  // namespace cvl

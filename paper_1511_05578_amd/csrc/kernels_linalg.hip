@@ -807,4 +807,14 @@ hipError_t launch_zero(cd *p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
+__global__ void k_add(cd *dst, const cd *src, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = cadd(dst[i], src[i]);
+}
+hipError_t launch_add(cd *dst, const cd *src, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
 }  // namespace cvl
