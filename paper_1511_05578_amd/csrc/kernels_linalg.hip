@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
 // tile is loaded into registers while the current one is multiplied.
 typedef double cvl_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_beta_mfma(int M, int K, int ncols, int Nep,
+__global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, int Nep,
                                                    const double *__restrict__ Ae,
                                                    const double *__restrict__ Ao,
                                                    const double *__restrict__ in,
@@ -425,6 +425,8 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mfma(ScaleGeom g, int L
     if (mpb > L) mpb = L;
     int ltop = l0 + 63;
     if (ltop > g.lhi) ltop = g.lhi;
+    // every m of the tile exceeds every l: entries the reduction never reads
+    if (m0 > ltop) return;
     if (mpb > ltop + 1) mpb = ltop + 1;
     int kmax = ltop / 2;
     if (kmax > h) kmax = h;

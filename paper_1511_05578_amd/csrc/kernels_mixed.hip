@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
 // The same beta stage with split-BF16 products (BF16x3 mode): K tiles of 32,
 // one v_mfma_f32_16x16x32_bf16 triple per 16 x 16 block and tile.  Operands
 // are staged in FP32 and split in registers.
-__global__ __launch_bounds__(256) void k_beta_mfma_bf16x3(int M, int K, int ncols, int Nep,
+__global__ __launch_bounds__(256, 3) void k_beta_mfma_bf16x3(int M, int K, int ncols, int Nep,
                                                           const float *__restrict__ Ae,
                                                           const float *__restrict__ Ao,
                                                           const float *__restrict__ in,
@@ -450,6 +450,8 @@ __global__ __launch_bounds__(256) void k_contract_fwd_mx(ScaleGeom g, int Lf,
     if (mpb > L) mpb = L;
     int ltop = l0 + 63;
     if (ltop > g.lhi) ltop = g.lhi;
+    // every m of the tile exceeds every l: entries the reduction never reads
+    if (m0 > ltop) return;
     if (mpb > ltop + 1) mpb = ltop + 1;
     int kmax = ltop / 2;
     if (kmax > h) kmax = h;
