@@ -39,12 +39,6 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 256;
-// The synthesis contraction splits the m' sum into groups (one work-group
-// column each, partial sums reduced in a fixed order afterwards).  The number
-// of groups per scale is chosen so that the launch has about kFwdWGs
-// work-groups, with at least kMinGroups groups and at most L_j (one m' each).
-constexpr int kFwdWGs = 1024;
-constexpr int kMinGroups = 32;
 // Scales with L_j at least this run the analysis beta stage as an FFT
 // (O(L^3 log L)) instead of the dense parity-folded GEMM (O(L^4)).
 constexpr int kBetaFftMinL = 256;
@@ -372,16 +366,10 @@ ScaleGeom geom_of(int Lj) {
 }
 
 // Element counts of the two cube-sized workspace buffers of a curvelet call.
-// m' groups of the synthesis contraction of a scale (see kFwdWGs).
-int fwd_groups(const ScaleGeom &g) {
-    const int mt = (g.L + 63) / 64;
-    const int nl = g.lhi >= g.llo ? g.lhi - (g.llo & ~1) + 1 : 1;
-    const int lt = (nl + 63) / 64;
-    int want = (kFwdWGs + mt * lt - 1) / (mt * lt);
-    if (want < kMinGroups) want = kMinGroups;
-    const int gsz = (g.L + want - 1) / want;
-    return (g.L + gsz - 1) / gsz;
-}
+// m' groups of the synthesis contraction of a scale: one m' per group (the
+// contraction then keeps no running sum over m', and the group reduction
+// sums only the groups that can hold an m' <= l).
+int fwd_groups(const ScaleGeom &g) { return g.L; }
 
 // Elements of the two cube buffers of the scales at the top band-limit
 // (b0, b1) and of the side scales below it (sb0, sb1), which run

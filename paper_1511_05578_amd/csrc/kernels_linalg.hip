@@ -380,18 +380,64 @@ hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta, 
 // Work-group: 64 m x 32 l tile, m' restricted to one of `ngroups` groups; the
 // partial sums part[grp][l][m] are reduced in a fixed order afterwards.
 // ---------------------------------------------------------------------------
-__global__ void k_reduce_fwd(ScaleGeom g, int Lf, const cd *__restrict__ part, int ngroups,
-                             cd *__restrict__ facc) {
+// Sum of the group partials into the FP64 accumulator,
+//   facc[l][m] += i^m sum_grp part[grp][l][m],
+// over the groups that can hold an m' <= l (m' of group grp: [grp*gsz,
+// (grp+1)*gsz)).  Work-group: one l, 64 m x 4 slices of the groups; slice s
+// sums groups s, s+4, ... in FP64, the slices are then added in a fixed order.
+template <class P>
+__global__ __launch_bounds__(256) void k_reduce_groups(ScaleGeom g, int Lf,
+                                                       const P *__restrict__ part, int ngroups,
+                                                       cd *__restrict__ facc) {
+    __shared__ cd red[4][64];
     const int L = g.L;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = g.llo + blockIdx.y;
+    const int mm = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int m = blockIdx.x * 64 + mm;
+    const int gsz = (L + ngroups - 1) / ngroups;
+    int gmax = l / gsz;
+    if (gmax > ngroups - 1) gmax = ngroups - 1;
+    double sx = 0.0, sy = 0.0;
+    if (m <= l && m < L) {
+        const P *src = part + (size_t)l * L + m;
+        const size_t gs = (size_t)L * L;
+        int grp = sl;
+        // four independent loads in flight per step
+        for (; grp + 12 <= gmax; grp += 16) {
+            const P a = src[grp * gs], b = src[(grp + 4) * gs], c = src[(grp + 8) * gs],
+                    d = src[(grp + 12) * gs];
+            sx += (double)a.x;
+            sy += (double)a.y;
+            sx += (double)b.x;
+            sy += (double)b.y;
+            sx += (double)c.x;
+            sy += (double)c.y;
+            sx += (double)d.x;
+            sy += (double)d.y;
+        }
+        for (; grp <= gmax; grp += 4) {
+            const P a = src[grp * gs];
+            sx += (double)a.x;
+            sy += (double)a.y;
+        }
+    }
+    red[sl][mm] = cd{sx, sy};
+    __syncthreads();
+    if (sl == 0 && m <= l && m < L) {
+        const cd t = cadd(cadd(red[0][mm], red[1][mm]), cadd(red[2][mm], red[3][mm]));
+        cd *o = facc + (size_t)l * Lf + m;
+        *o = cadd(*o, ipow(t, m));
+    }
+}
+
+template <class P>
+static hipError_t launch_reduce_groups(const ScaleGeom &g, int Lf, const P *part, int ngroups,
+                                       cd *facc, hipStream_t st) {
     const int nl = g.lhi - g.llo + 1;
-    if (idx >= nl * L) return;
-    const int l = g.llo + idx / L, m = idx % L;
-    if (m > l) return;
-    cd s = cd{0.0, 0.0};
-    for (int grp = 0; grp < ngroups; ++grp) s = cadd(s, part[((size_t)grp * L + l) * L + m]);
-    cd *o = facc + (size_t)l * Lf + m;
-    *o = cadd(*o, ipow(s, m));
+    if (nl <= 0) return hipSuccess;
+    dim3 grid((g.L + 63) / 64, nl);
+    hipLaunchKernelGGL(k_reduce_groups<P>, grid, dim3(256), 0, st, g, Lf, part, ngroups, facc);
+    return hipGetLastError();
 }
 
 // The same contraction on FP64 MFMA.  Work-group tile: 64 l (32 of each
@@ -425,8 +471,9 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mfma(ScaleGeom g, int L
     if (mpb > L) mpb = L;
     int ltop = l0 + 63;
     if (ltop > g.lhi) ltop = g.lhi;
-    // every m of the tile exceeds every l: entries the reduction never reads
-    if (m0 > ltop) return;
+    // every m of the tile exceeds every l, or every m' of the group does:
+    // entries the reduction never reads
+    if (m0 > ltop || mpa > ltop) return;
     if (mpb > ltop + 1) mpb = ltop + 1;
     int kmax = ltop / 2;
     if (kmax > h) kmax = h;
@@ -543,11 +590,144 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mfma(ScaleGeom g, int L
         }
 }
 
+// The same tile for one m' per work-group: part[m'][l][m] = Delta^l_{m'm} T[l][m]
+// with no running sum over m', so the registers that would hold it prefetch
+// the next K chunk's operands (raw Delta, Psi and the two Z half rows) while
+// the current chunk is multiplied.
+__global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
+                                                         const double *__restrict__ delta,
+                                                         const cd *__restrict__ Z,
+                                                         const double *__restrict__ psi,
+                                                         cd *__restrict__ part) {
+    __shared__ double Bt[2][16][33];
+    __shared__ double Zr[2][16][65], Zi[2][16][65];
+    const int L = g.L, h = g.h, Nep = g.Nep;
+    const int lbase = g.llo & ~1;
+    const int nl = g.lhi - lbase + 1;
+    const int nlt = (nl + 63) / 64, nmt = (L + 63) / 64;
+    // logical tile: l tile fastest, then m tile, then m' (tiles of one
+    // (m', m tile) read the same cube rows and run on one XCD)
+    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt);
+    const int m0 = ((lg / nlt) % nmt) * 64;
+    const int l0 = lbase + (lg % nlt) * 64;
+    const int mp = lg / (nlt * nmt);
+    int ltop = l0 + 63;
+    if (ltop > g.lhi) ltop = g.lhi;
+    // entries the reduction never reads (m > l or m' > l for the whole tile)
+    if (m0 > ltop || mp > ltop) return;
+    int kmax = ltop / 2;
+    if (kmax > h) kmax = h;
+    const double smp = (mp & 1) ? -1.0 : 1.0;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wp = w & 1, wm = w >> 1;
+    const int li = lane & 15, lq = lane >> 4;
+    // staging assignment: element q of this thread
+    //   B'^T: kk = idx & 15, i = (idx >> 4) & 31, par = idx >> 9 (l = l0 + par + 2 i)
+    //   Z:    kk = idx & 15, mm = idx >> 4
+    double rd[4], rp[4];
+    cd rzp[4], rzn[4];
+    auto fetch = [&](int kb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 15, i = (idx >> 4) & 31, par = idx >> 9;
+            const int l = l0 + par + 2 * i, k = kb + kk;
+            const bool ok = k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l;
+            rd[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] : 0.0;
+            rp[q] = ok ? psi[(size_t)l * (h + 1) + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 15, mm = idx >> 4;
+            const int k = kb + kk, m = m0 + mm;
+            const bool ok = k <= kmax && m < L;
+            const cd *row = Z + ((size_t)mp * L + (ok ? m : 0)) * Nep;
+            rzp[q] = ok ? row[h + k] : cd{0.0, 0.0};
+            rzn[q] = (ok && k > 0) ? row[h - k] : cd{0.0, 0.0};
+        }
+    };
+    cvl_d4 t[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) t[a][b][c] = cvl_d4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int kb = 0; kb <= kmax; kb += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 15, i = (idx >> 4) & 31, par = idx >> 9;
+            const double v = rd[q] * rp[q];
+            Bt[par][kk][i] = (kk & 1) ? -v : v;  // (-1)^k, k = kb + kk with kb even
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 15, mm = idx >> 4;
+            // k = 0: Z^+ = Z^- = Z[h] (rzn is zero there)
+            const cd zn = cscale(rzn[q], smp);
+            const cd vp = cadd(rzp[q], zn), vm = csub(rzp[q], zn);
+            Zr[0][kk][mm] = vp.x;
+            Zi[0][kk][mm] = vp.y;
+            Zr[1][kk][mm] = vm.x;
+            Zi[1][kk][mm] = vm.y;
+        }
+        __syncthreads();
+        if (kb + 16 <= kmax) fetch(kb + 16);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = 4 * ks + lq;
+            double a[2], zr[2], zi[2];
+#pragma unroll
+            for (int lf = 0; lf < 2; ++lf) a[lf] = Bt[wp][kk][16 * lf + li];
+#pragma unroll
+            for (int mj = 0; mj < 2; ++mj) {
+                zr[mj] = Zr[wp][kk][32 * wm + 16 * mj + li];
+                zi[mj] = Zi[wp][kk][32 * wm + 16 * mj + li];
+            }
+#pragma unroll
+            for (int lf = 0; lf < 2; ++lf)
+#pragma unroll
+                for (int mj = 0; mj < 2; ++mj) {
+                    t[lf][mj][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lf], zr[mj],
+                                                                        t[lf][mj][0], 0, 0, 0);
+                    t[lf][mj][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lf], zi[mj],
+                                                                        t[lf][mj][1], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // part[m'][l][m] = Delta^l_{m'm} T[l][m]  (output layout: row 4r + lq of block lf)
+#pragma unroll
+    for (int lf = 0; lf < 2; ++lf)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int l = l0 + wp + 2 * (16 * lf + 4 * r + lq);
+            if (l > g.lhi) continue;
+            const double *drow = delta + delta_off(l) + (int64_t)mp * (l + 1);
+#pragma unroll
+            for (int mj = 0; mj < 2; ++mj) {
+                const int m = m0 + 32 * wm + 16 * mj + li;
+                if (m >= L) continue;
+                const double d = (mp <= l && m <= l) ? drow[m] : 0.0;
+                part[((size_t)mp * L + l) * L + m] =
+                    cd{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
+            }
+        }
+}
+
 hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta, const cd *Z,
                                const double *psi, cd *part, int ngroups, hipStream_t st) {
     if (g.lhi < g.llo) return hipSuccess;
     const int nl = g.lhi - (g.llo & ~1) + 1;
     dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * ngroups);
+    if (ngroups == g.L) {
+        hipLaunchKernelGGL(k_contract_fwd_m1, grid, dim3(256), 0, st, g, delta, Z, psi, part);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_contract_fwd_mfma, grid, dim3(256), 0, st, g, Lf, delta, Z, psi, part,
                        ngroups);
     return hipGetLastError();
@@ -555,12 +735,11 @@ hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta, 
 
 hipError_t launch_reduce_fwd(const ScaleGeom &g, int Lf, const cd *part, int ngroups, cd *facc,
                              hipStream_t st) {
-    const int nl = g.lhi - g.llo + 1;
-    if (nl <= 0) return hipSuccess;
-    const int n = nl * g.L;
-    hipLaunchKernelGGL(k_reduce_fwd, dim3((n + 255) / 256), dim3(256), 0, st, g, Lf, part,
-                       ngroups, facc);
-    return hipGetLastError();
+    return launch_reduce_groups(g, Lf, part, ngroups, facc, st);
+}
+hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int ngroups,
+                                cd *facc, hipStream_t st) {
+    return launch_reduce_groups(g, Lf, part, ngroups, facc, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -450,8 +450,9 @@ __global__ __launch_bounds__(256) void k_contract_fwd_mx(ScaleGeom g, int Lf,
     if (mpb > L) mpb = L;
     int ltop = l0 + 63;
     if (ltop > g.lhi) ltop = g.lhi;
-    // every m of the tile exceeds every l: entries the reduction never reads
-    if (m0 > ltop) return;
+    // every m of the tile exceeds every l, or every m' of the group does:
+    // entries the reduction never reads
+    if (m0 > ltop || mpa > ltop) return;
     if (mpb > ltop + 1) mpb = ltop + 1;
     int kmax = ltop / 2;
     if (kmax > h) kmax = h;
@@ -579,35 +580,6 @@ hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, int Lf, const do
     else
         hipLaunchKernelGGL(k_contract_fwd_mx<PREC_BF16X3>, grid, dim3(256), 0, st, g, Lf, delta,
                            Z, psi, part, ngroups);
-    return hipGetLastError();
-}
-
-// FP64 sum of the complex64 group partials into the FP64 accumulator:
-//   facc[l][m] += i^m sum_grp part[grp][l][m].
-__global__ void k_reduce_fwd_mx(ScaleGeom g, int Lf, const cf *__restrict__ part, int ngroups,
-                                cd *__restrict__ facc) {
-    const int L = g.L;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nl = g.lhi - g.llo + 1;
-    if (idx >= nl * L) return;
-    const int l = g.llo + idx / L, m = idx % L;
-    if (m > l) return;
-    cd s = cd{0.0, 0.0};
-    for (int grp = 0; grp < ngroups; ++grp) {
-        const cf v = part[((size_t)grp * L + l) * L + m];
-        s = cadd(s, cd{(double)v.x, (double)v.y});
-    }
-    cd *o = facc + (size_t)l * Lf + m;
-    *o = cadd(*o, ipow(s, m));
-}
-
-hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int ngroups,
-                                cd *facc, hipStream_t st) {
-    const int nl = g.lhi - g.llo + 1;
-    if (nl <= 0) return hipSuccess;
-    const int n = nl * g.L;
-    hipLaunchKernelGGL(k_reduce_fwd_mx, dim3((n + 255) / 256), dim3(256), 0, st, g, Lf, part,
-                       ngroups, facc);
     return hipGetLastError();
 }
 
