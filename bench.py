@@ -135,7 +135,9 @@ def kernel_symbol(stage, Lj, prec, real_grids=False):
     if stage == "contract_inv":
         return "k_contract_inv" if prec == "fp64" else "k_contract_inv_mx" + mode
     if stage == "contract_fwd":
-        return "k_contract_fwd_mfma" if prec == "fp64" else "k_contract_fwd_mx" + mode
+        return "k_contract_fwd_m1" if prec == "fp64" else "k_contract_fwd_mx1" + mode
+    if stage == "reduce_fwd":
+        return "k_reduce_groups<%s>" % c
     return stage
 
 

@@ -962,8 +962,8 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
         LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full_f, b0, b1, st));
         LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.betaf.Qp,
                                                  S.betaf.Qs, b1, b0, st));
-        LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd_mx(precision, g, L, ctx->delta, b0, S.psi,
-                                                       b1, S.ngroups, st));
+        LAUNCH(ST_CONTRACT_FWD,
+               launch_contract_fwd_mx(precision, g, ctx->delta, b0, S.psi, b1, st));
         LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, S.ngroups, B.facc, st));
         return CVL_OK;
     }
@@ -975,8 +975,7 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
     LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, S.fwd_full, b0, b1, st));
     LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, g.L * g.Nep, g.Nep, 0, 0, S.beta.Qp,
                                          S.beta.Qs, b1, b0, st));
-    LAUNCH(ST_CONTRACT_FWD,
-           launch_contract_fwd(g, L, ctx->delta, b0, S.psi, b1, S.ngroups, st));
+    LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd(g, ctx->delta, b0, S.psi, b1, st));
     LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, b1, S.ngroups, B.facc, st));
     return CVL_OK;
 }

@@ -171,18 +171,17 @@ hipError_t launch_beta_gemm_f32(int mode, int M, int K, int ncols, int Nep, cons
                                 const float *Aodd, const cf *in, cf *out, hipStream_t st);
 hipError_t launch_contract_inv_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
                                   const cd *fpad, const double *psi, cf *X, hipStream_t st);
-hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
-                                  const cf *Z, const double *psi, cf *part, int ngroups,
-                                  hipStream_t st);
+hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, const double *delta,
+                                  const cf *Z, const double *psi, cf *part, hipStream_t st);
 hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int ngroups,
                                 cd *facc, hipStream_t st);
 
 // Curvelet contractions.
 hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
                                const cd *fpad, const double *psi, cd *X, hipStream_t st);
-hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
-                               const cd *Z, const double *psi, cd *part, int ngroups,
-                               hipStream_t st);
+// part[m'][l][m] (one m' per group; the reductions take ngroups = L_j)
+hipError_t launch_contract_fwd(const ScaleGeom &g, const double *delta, const cd *Z,
+                               const double *psi, cd *part, hipStream_t st);
 hipError_t launch_reduce_fwd(const ScaleGeom &g, int Lf, const cd *part, int ngroups,
                              cd *facc, hipStream_t st);
 

@@ -377,8 +377,8 @@ hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta, 
 //   B'[k][l] = (-1)^k Delta^l_{m',2k} Psi_{l,2k},
 //   Z^{+/-}[m'][m][k] = Z[m'][m][h+k] +/- (-1)^{m'} Z[m'][m][h-k]  (k > 0),
 //   Z^{+/-}[m'][m][0] = Z[m'][m][h].
-// Work-group: 64 m x 32 l tile, m' restricted to one of `ngroups` groups; the
-// partial sums part[grp][l][m] are reduced in a fixed order afterwards.
+// One m' per work-group column: the partials part[m'][l][m] =
+// Delta^l_{m'm} T_{m'}[l][m] are summed over m' in a fixed order afterwards.
 // ---------------------------------------------------------------------------
 // Sum of the group partials into the FP64 accumulator,
 //   facc[l][m] += i^m sum_grp part[grp][l][m],
@@ -440,160 +440,15 @@ static hipError_t launch_reduce_groups(const ScaleGeom &g, int Lf, const P *part
     return hipGetLastError();
 }
 
-// The same contraction on FP64 MFMA.  Work-group tile: 64 l (32 of each
-// parity, l = l0 + par + 2i) x 64 m; m' runs over one group.  Per m':
+// The contraction on FP64 MFMA.  Work-group tile: 64 l (32 of each parity,
+// l = l0 + par + 2i) x 64 m for one m':
 //   T[l][m] = sum_k B'[k][l] Z^{par(l)}[m'][m][k]   (A = B'^T real, B = Z^T complex)
-//   acc[l][m] += Delta^l_{m'm} T[l][m]   (applied in the MFMA output layout; the
-//   Delta row of each l is contiguous in m, so those loads coalesce).
+//   part[m'][l][m] = Delta^l_{m'm} T[l][m]   (applied in the MFMA output layout;
+//   the Delta row of each l is contiguous in m, so those loads coalesce).
 // Wave (wp, wm): parity wp, 32 l x 32 m, [2 l blocks][2 m blocks][re/im].
-__global__ __launch_bounds__(256, 2) void k_contract_fwd_mfma(ScaleGeom g, int Lf,
-                                                           const double *__restrict__ delta,
-                                                           const cd *__restrict__ Z,
-                                                           const double *__restrict__ psi,
-                                                           cd *__restrict__ part, int ngroups) {
-    __shared__ double Bt[2][16][33];
-    __shared__ double Zr[2][16][65], Zi[2][16][65];
-    const int L = g.L, h = g.h, Nep = g.Nep;
-    // l tiles start at even l so that wave parity wp is the parity of its rows
-    // (rows below llo carry a zero kernel and are never read back).
-    const int lbase = g.llo & ~1;
-    const int nl = g.lhi - lbase + 1;
-    const int nlt = (nl + 63) / 64, nmt = (L + 63) / 64;
-    // logical tile: l tile fastest, then m tile, then m' group (tiles of one
-    // (group, m tile) read the same cube rows and run on one XCD)
-    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt);
-    const int m0 = ((lg / nlt) % nmt) * 64;
-    const int l0 = lbase + (lg % nlt) * 64;
-    const int grp = lg / (nlt * nmt);
-    const int gsz = (L + ngroups - 1) / ngroups;
-    const int mpa = grp * gsz;
-    int mpb = mpa + gsz;
-    if (mpb > L) mpb = L;
-    int ltop = l0 + 63;
-    if (ltop > g.lhi) ltop = g.lhi;
-    // every m of the tile exceeds every l, or every m' of the group does:
-    // entries the reduction never reads
-    if (m0 > ltop || mpa > ltop) return;
-    if (mpb > ltop + 1) mpb = ltop + 1;
-    int kmax = ltop / 2;
-    if (kmax > h) kmax = h;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wp = w & 1, wm = w >> 1;
-    const int li = lane & 15, lq = lane >> 4;
-    cvl_d4 acc[2][2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) acc[a][b][c] = cvl_d4{0.0, 0.0, 0.0, 0.0};
-    for (int mp = mpa; mp < mpb; ++mp) {
-        const double smp = (mp & 1) ? -1.0 : 1.0;
-        cvl_d4 t[2][2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) t[a][b][c] = cvl_d4{0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb <= kmax; kb += 16) {
-            // B'^T rows l = l0 + par + 2i, columns k = kb + kk (k fastest across threads)
-#pragma unroll 2
-            for (int q = 0; q < 4; ++q) {
-                const int idx = tid + 256 * q;
-                const int kk = idx & 15, i = (idx >> 4) & 31, par = idx >> 9;
-                const int l = l0 + par + 2 * i, k = kb + kk;
-                double v = 0.0;
-                if (k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l) {
-                    v = delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] *
-                        psi[(size_t)l * (h + 1) + k];
-                    if (k & 1) v = -v;
-                }
-                Bt[par][kk][i] = v;
-            }
-            // Z^{+/-}[m][k] for m = m0 + mm (k fastest across threads)
-#pragma unroll 2
-            for (int q = 0; q < 4; ++q) {
-                const int idx = tid + 256 * q;
-                const int kk = idx & 15, mm = idx >> 4;
-                const int k = kb + kk, m = m0 + mm;
-                cd vp = cd{0.0, 0.0}, vm = cd{0.0, 0.0};
-                if (k <= kmax && m < L) {
-                    const cd *row = Z + ((size_t)mp * L + m) * Nep;
-                    const cd zp = row[h + k];
-                    if (k == 0) {
-                        vp = vm = zp;
-                    } else {
-                        const cd zn = cscale(row[h - k], smp);
-                        vp = cadd(zp, zn);
-                        vm = csub(zp, zn);
-                    }
-                }
-                Zr[0][kk][mm] = vp.x;
-                Zi[0][kk][mm] = vp.y;
-                Zr[1][kk][mm] = vm.x;
-                Zi[1][kk][mm] = vm.y;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int kk = 4 * ks + lq;
-                double a[2], zr[2], zi[2];
-#pragma unroll
-                for (int lf = 0; lf < 2; ++lf) a[lf] = Bt[wp][kk][16 * lf + li];
-#pragma unroll
-                for (int mj = 0; mj < 2; ++mj) {
-                    zr[mj] = Zr[wp][kk][32 * wm + 16 * mj + li];
-                    zi[mj] = Zi[wp][kk][32 * wm + 16 * mj + li];
-                }
-#pragma unroll
-                for (int lf = 0; lf < 2; ++lf)
-#pragma unroll
-                    for (int mj = 0; mj < 2; ++mj) {
-                        t[lf][mj][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lf], zr[mj],
-                                                                            t[lf][mj][0], 0, 0, 0);
-                        t[lf][mj][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lf], zi[mj],
-                                                                            t[lf][mj][1], 0, 0, 0);
-                    }
-            }
-            __syncthreads();
-        }
-        // acc += Delta^l_{m'm} * T  (output layout: row 4r + lq of block lf, column li)
-#pragma unroll
-        for (int lf = 0; lf < 2; ++lf)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int l = l0 + wp + 2 * (16 * lf + 4 * r + lq);
-                const bool lok = l <= g.lhi && mp <= l;
-                const double *drow = delta + (lok ? delta_off(l) + (int64_t)mp * (l + 1) : 0);
-#pragma unroll
-                for (int mj = 0; mj < 2; ++mj) {
-                    const int m = m0 + 32 * wm + 16 * mj + li;
-                    const double d = (lok && m <= l) ? drow[m] : 0.0;
-                    acc[lf][mj][0][r] += d * t[lf][mj][0][r];
-                    acc[lf][mj][1][r] += d * t[lf][mj][1][r];
-                }
-            }
-    }
-#pragma unroll
-    for (int lf = 0; lf < 2; ++lf)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int l = l0 + wp + 2 * (16 * lf + 4 * r + lq);
-            if (l > g.lhi) continue;
-#pragma unroll
-            for (int mj = 0; mj < 2; ++mj) {
-                const int m = m0 + 32 * wm + 16 * mj + li;
-                if (m >= L) continue;
-                part[((size_t)grp * L + l) * L + m] = cd{acc[lf][mj][0][r], acc[lf][mj][1][r]};
-            }
-        }
-}
-
-// The same tile for one m' per work-group: part[m'][l][m] = Delta^l_{m'm} T[l][m]
-// with no running sum over m', so the registers that would hold it prefetch
-// the next K chunk's operands (raw Delta, Psi and the two Z half rows) while
-// the current chunk is multiplied.
+// With no running sum over m' held, the next K chunk's operands (raw Delta,
+// Psi and the two Z half rows) are prefetched into registers while the
+// current chunk is multiplied.
 __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
                                                          const double *__restrict__ delta,
                                                          const cd *__restrict__ Z,
@@ -719,17 +574,12 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
         }
 }
 
-hipError_t launch_contract_fwd(const ScaleGeom &g, int Lf, const double *delta, const cd *Z,
-                               const double *psi, cd *part, int ngroups, hipStream_t st) {
+hipError_t launch_contract_fwd(const ScaleGeom &g, const double *delta, const cd *Z,
+                               const double *psi, cd *part, hipStream_t st) {
     if (g.lhi < g.llo) return hipSuccess;
     const int nl = g.lhi - (g.llo & ~1) + 1;
-    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * ngroups);
-    if (ngroups == g.L) {
-        hipLaunchKernelGGL(k_contract_fwd_m1, grid, dim3(256), 0, st, g, delta, Z, psi, part);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_contract_fwd_mfma, grid, dim3(256), 0, st, g, Lf, delta, Z, psi, part,
-                       ngroups);
+    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * g.L);
+    hipLaunchKernelGGL(k_contract_fwd_m1, grid, dim3(256), 0, st, g, delta, Z, psi, part);
     return hipGetLastError();
 }
 

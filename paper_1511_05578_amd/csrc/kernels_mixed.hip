@@ -419,167 +419,150 @@ hipError_t launch_contract_inv_mx(int mode, const ScaleGeom &g, int Lf, const do
 //   B'[k][l] = (-1)^k Delta^l_{m',2k} Psi_{l,2k},
 //   Z^{+/-}[m'][m][k] = Z[m'][m][h+k] +/- (-1)^{m'} Z[m'][m][h-k]  (k > 0),
 //   Z^{+/-}[m'][m][0] = Z[m'][m][h].
-// Work-group tile: 64 l (32 of each parity, l = l0 + par + 2i) x 64 m over
-// one group of m'.  Per m': T[l][m] = sum_k B'[k][l] Z^par[m][k] on the
-// matrix cores (K chunks of 32), then acc[l][m] += Delta^l_{m'm} T[l][m] in
-// the output layout.  Wave (wp, wm): parity wp, 32 l x 32 m, [2 l blocks]
-// [2 m blocks][re/im].  The group partials part[grp][l][m] (complex64) are
-// summed in FP64 afterwards.
+// Work-group tile: 64 l (32 of each parity, l = l0 + par + 2i) x 64 m for one
+// m': T[l][m] = sum_k B'[k][l] Z^par[m][k] on the matrix cores (K chunks of
+// 32), then part[m'][l][m] = Delta^l_{m'm} T[l][m] (complex64) in the output
+// layout.  Wave (wp, wm): parity wp, 32 l x 32 m, [2 l blocks][2 m blocks]
+// [re/im].  The partials are summed over m' in FP64 afterwards.  With no
+// running sum over m' held, the next K chunk's operands (raw Delta, Psi and
+// the two Z half rows) are prefetched into registers while the current chunk
+// is multiplied.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256) void k_contract_fwd_mx(ScaleGeom g, int Lf,
-                                                         const double *__restrict__ delta,
-                                                         const cf *__restrict__ Z,
-                                                         const double *__restrict__ psi,
-                                                         cf *__restrict__ part, int ngroups) {
+__global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
+                                                           const double *__restrict__ delta,
+                                                           const cf *__restrict__ Z,
+                                                           const double *__restrict__ psi,
+                                                           cf *__restrict__ part) {
     __shared__ float Bt[2][32][34];       // [par][k][i]
     __shared__ float Zs[2][2][32][66];    // [par][re/im][k][mm]
     const int L = g.L, h = g.h, Nep = g.Nep;
     const int lbase = g.llo & ~1;
     const int nl = g.lhi - lbase + 1;
     const int nlt = (nl + 63) / 64, nmt = (L + 63) / 64;
-    // logical tile: l tile fastest, then m tile, then m' group (see
-    // k_contract_fwd_mfma)
+    // logical tile: l tile fastest, then m tile, then m'
     const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt);
     const int m0 = ((lg / nlt) % nmt) * 64;
     const int l0 = lbase + (lg % nlt) * 64;
-    const int grp = lg / (nlt * nmt);
-    const int gsz = (L + ngroups - 1) / ngroups;
-    const int mpa = grp * gsz;
-    int mpb = mpa + gsz;
-    if (mpb > L) mpb = L;
+    const int mp = lg / (nlt * nmt);
     int ltop = l0 + 63;
     if (ltop > g.lhi) ltop = g.lhi;
-    // every m of the tile exceeds every l, or every m' of the group does:
-    // entries the reduction never reads
-    if (m0 > ltop || mpa > ltop) return;
-    if (mpb > ltop + 1) mpb = ltop + 1;
+    // entries the reduction never reads (m > l or m' > l for the whole tile)
+    if (m0 > ltop || mp > ltop) return;
     int kmax = ltop / 2;
     if (kmax > h) kmax = h;
+    const float smp = (mp & 1) ? -1.f : 1.f;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wp = w & 1, wm = w >> 1;
     const int li = lane & 15, lq = lane >> 4;
-    f4v acc[2][2][2];
+    // staging assignment: element q of this thread
+    //   B'^T: kk = idx & 31, i = (idx >> 5) & 31, par = idx >> 10 (l = l0 + par + 2 i)
+    //   Z:    kk = idx & 31, mm = idx >> 5
+    double rd[8], rp[8];
+    cf rzp[8], rzn[8];
+    auto fetch = [&](int kb) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, i = (idx >> 5) & 31, par = idx >> 10;
+            const int l = l0 + par + 2 * i, k = kb + kk;
+            const bool ok = k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l;
+            rd[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] : 0.0;
+            rp[q] = ok ? psi[(size_t)l * (h + 1) + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, mm = idx >> 5;
+            const int k = kb + kk, m = m0 + mm;
+            const bool ok = k <= kmax && m < L;
+            const cf *row = Z + ((size_t)mp * L + (ok ? m : 0)) * Nep;
+            rzp[q] = ok ? row[h + k] : cf{0.f, 0.f};
+            rzn[q] = (ok && k > 0) ? row[h - k] : cf{0.f, 0.f};
+        }
+    };
+    f4v t[2][2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) acc[a][b][cc] = f4v{0.f, 0.f, 0.f, 0.f};
-    for (int mp = mpa; mp < mpb; ++mp) {
-        const float smp = (mp & 1) ? -1.f : 1.f;
-        f4v t[2][2][2];
+            for (int cc = 0; cc < 2; ++cc) t[a][b][cc] = f4v{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    for (int kb = 0; kb <= kmax; kb += 32) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, i = (idx >> 5) & 31, par = idx >> 10;
+            const double dv = rd[q] * rp[q];  // formed in FP64, rounded once
+            Bt[par][kk][i] = (float)((kk & 1) ? -dv : dv);  // (-1)^k, kb even
+        }
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, mm = idx >> 5;
+            // k = 0: Z^+ = Z^- = Z[h] (rzn is zero there)
+            const cf zn = cscale(rzn[q], smp);
+            const cf vp = cadd(rzp[q], zn), vm = csub(rzp[q], zn);
+            Zs[0][0][kk][mm] = vp.x;
+            Zs[0][1][kk][mm] = vp.y;
+            Zs[1][0][kk][mm] = vm.x;
+            Zs[1][1][kk][mm] = vm.y;
+        }
+        __syncthreads();
+        if (kb + 32 <= kmax) fetch(kb + 32);
+        Op<MODE> aop[2];
 #pragma unroll
-                for (int cc = 0; cc < 2; ++cc) t[a][b][cc] = f4v{0.f, 0.f, 0.f, 0.f};
-        for (int kb = 0; kb <= kmax; kb += 32) {
-            // B'^T: [par][k][i], l = l0 + par + 2i (k fastest across threads)
-#pragma unroll 2
-            for (int q = 0; q < 8; ++q) {
-                const int idx = tid + 256 * q;
-                const int kk = idx & 31, i = (idx >> 5) & 31, par = idx >> 10;
-                const int l = l0 + par + 2 * i, k = kb + kk;
-                float v = 0.f;
-                if (k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l) {
-                    double dv = delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] *
-                                psi[(size_t)l * (h + 1) + k];
-                    v = (float)((k & 1) ? -dv : dv);
-                }
-                Bt[par][kk][i] = v;
-            }
-            // Z^{+/-}[m][k], m = m0 + mm (k fastest across threads)
-#pragma unroll 2
-            for (int q = 0; q < 8; ++q) {
-                const int idx = tid + 256 * q;
-                const int kk = idx & 31, mm = idx >> 5;
-                const int k = kb + kk, m = m0 + mm;
-                cf vp = cf{0.f, 0.f}, vm = cf{0.f, 0.f};
-                if (k <= kmax && m < L) {
-                    const cf *row = Z + ((size_t)mp * L + m) * Nep;
-                    const cf zp = row[h + k];
-                    if (k == 0) {
-                        vp = vm = zp;
-                    } else {
-                        const cf zn = cscale(row[h - k], smp);
-                        vp = cadd(zp, zn);
-                        vm = csub(zp, zn);
-                    }
-                }
-                Zs[0][0][kk][mm] = vp.x;
-                Zs[0][1][kk][mm] = vp.y;
-                Zs[1][0][kk][mm] = vm.x;
-                Zs[1][1][kk][mm] = vm.y;
-            }
-            __syncthreads();
-            Op<MODE> aop[2];
+        for (int lf = 0; lf < 2; ++lf) {
+            float x[8];
 #pragma unroll
-            for (int lf = 0; lf < 2; ++lf) {
+            for (int e = 0; e < 8; ++e) x[e] = Bt[wp][8 * lq + e][16 * lf + li];
+            aop[lf].set(x);
+        }
+#pragma unroll
+        for (int mj = 0; mj < 2; ++mj)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
                 float x[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = Bt[wp][8 * lq + e][16 * lf + li];
-                aop[lf].set(x);
+                for (int e = 0; e < 8; ++e) x[e] = Zs[wp][cc][8 * lq + e][32 * wm + 16 * mj + li];
+                Op<MODE> bop;
+                bop.set(x);
+#pragma unroll
+                for (int lf = 0; lf < 2; ++lf) t[lf][mj][cc] = mma32(aop[lf], bop, t[lf][mj][cc]);
             }
-#pragma unroll
-            for (int mj = 0; mj < 2; ++mj)
-#pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    float x[8];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) x[e] = Zs[wp][cc][8 * lq + e][32 * wm + 16 * mj + li];
-                    Op<MODE> bop;
-                    bop.set(x);
-#pragma unroll
-                    for (int lf = 0; lf < 2; ++lf) t[lf][mj][cc] = mma32(aop[lf], bop, t[lf][mj][cc]);
-                }
-            __syncthreads();
-        }
-        // acc += Delta^l_{m'm} T: output row 4 lq + r of block lf, column li
-#pragma unroll
-        for (int lf = 0; lf < 2; ++lf)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
-                const bool lok = l <= g.lhi && mp <= l;
-                const double *drow = delta + (lok ? delta_off(l) + (int64_t)mp * (l + 1) : 0);
-#pragma unroll
-                for (int mj = 0; mj < 2; ++mj) {
-                    const int m = m0 + 32 * wm + 16 * mj + li;
-                    const float d = (lok && m <= l) ? (float)drow[m] : 0.f;
-                    acc[lf][mj][0][r] += d * t[lf][mj][0][r];
-                    acc[lf][mj][1][r] += d * t[lf][mj][1][r];
-                }
-            }
+        __syncthreads();
     }
+    // part[m'][l][m] = Delta^l_{m'm} T: output row 4 lq + r of block lf, column li
 #pragma unroll
     for (int lf = 0; lf < 2; ++lf)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
             if (l > g.lhi) continue;
+            const double *drow = delta + delta_off(l) + (int64_t)mp * (l + 1);
 #pragma unroll
             for (int mj = 0; mj < 2; ++mj) {
                 const int m = m0 + 32 * wm + 16 * mj + li;
                 if (m >= L) continue;
-                part[((size_t)grp * L + l) * L + m] = cf{acc[lf][mj][0][r], acc[lf][mj][1][r]};
+                const float d = (mp <= l && m <= l) ? (float)drow[m] : 0.f;
+                part[((size_t)mp * L + l) * L + m] =
+                    cf{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
             }
         }
 }
 
-hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, int Lf, const double *delta,
-                                  const cf *Z, const double *psi, cf *part, int ngroups,
-                                  hipStream_t st) {
+hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, const double *delta,
+                                  const cf *Z, const double *psi, cf *part, hipStream_t st) {
     if (g.lhi < g.llo) return hipSuccess;
     const int nl = g.lhi - (g.llo & ~1) + 1;
-    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * ngroups);
+    dim3 grid(((g.L + 63) / 64) * ((nl + 63) / 64) * g.L);
     if (mode == PREC_FP32)
-        hipLaunchKernelGGL(k_contract_fwd_mx<PREC_FP32>, grid, dim3(256), 0, st, g, Lf, delta, Z,
-                           psi, part, ngroups);
+        hipLaunchKernelGGL(k_contract_fwd_mx1<PREC_FP32>, grid, dim3(256), 0, st, g, delta, Z,
+                           psi, part);
     else
-        hipLaunchKernelGGL(k_contract_fwd_mx<PREC_BF16X3>, grid, dim3(256), 0, st, g, Lf, delta,
-                           Z, psi, part, ngroups);
+        hipLaunchKernelGGL(k_contract_fwd_mx1<PREC_BF16X3>, grid, dim3(256), 0, st, g, delta, Z,
+                           psi, part);
     return hipGetLastError();
 }
 
