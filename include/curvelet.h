@@ -28,6 +28,14 @@
  * - `stream` is a hipStream_t (NULL = legacy default stream).  Every call only
  *   enqueues work on that stream and returns; results are ready when the
  *   stream is.  Calls that share a workspace must be ordered on one stream.
+ *   The batched curvelet calls run the scales below the top band-limit on a
+ *   side stream of the caller's stream (created by the context on first use,
+ *   default priority), forked and joined with events inside the call, so the
+ *   caller still sees plain stream order.
+ * - Graph capture: once the tables of (L, lambda, J0) exist (cvl_prepare or a
+ *   first call) the curvelet calls allocate nothing and enqueue only kernels
+ *   and event records, so with per-stage timing off they can be captured into
+ *   a HIP graph on the caller's stream and replayed.
  * - Return value: CVL_OK, or a negative CVL_E* code.  Arguments are validated
  *   before anything is enqueued; on error nothing is written to any output and
  *   cvl_last_error() (thread-local) describes the failure.  NaN/Inf inputs are
@@ -216,6 +224,13 @@ int cvl_kernel_tables(const cvl_params *p, double *kappa, double *phi);
 int cvl_profile_enable(cvl_ctx *ctx, int on);
 int cvl_profile_read(cvl_ctx *ctx, int max, int *n, const char **names,
                      int *launches, double *ms);
+
+/* Restrict the per-launch timing to the launches of stage index `stage`
+ * (names as in cvl_profile_read) at band-limit `bandlimit`; stage -1 times
+ * every launch again.  Timing few launches keeps the events' own cost out of
+ * the work being measured.  Errors: CVL_EINVAL for a stage index outside
+ * [-1, number of stages). */
+int cvl_profile_filter(cvl_ctx *ctx, int stage, int bandlimit);
 
 /* The same times split by (stage, band-limit): row i < min(*n, max) is stage
  * index stage[i] (names as in cvl_profile_read) at band-limit bandlimit[i]

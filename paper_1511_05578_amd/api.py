@@ -68,6 +68,7 @@ SIGNATURES = {
                                                       ctypes.c_size_t, ctypes.c_void_p]),
     "cvl_kernel_tables": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_double_p, _c_double_p]),
     "cvl_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "cvl_profile_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "cvl_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p,
                                         ctypes.POINTER(ctypes.c_char_p), _c_int_p, _c_double_p]),
     "cvl_profile_read_detail": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p, _c_int_p,
@@ -407,6 +408,12 @@ class Context:
         ms = (ctypes.c_double * mx)()
         _check(lib.cvl_profile_read(self.h, mx, ctypes.byref(n), names, launches, ms))
         return {names[i].decode(): (launches[i], ms[i]) for i in range(min(n.value, mx))}
+
+    def profile_filter(self, stage=None, bandlimit=0):
+        """Time only the launches of `stage` (a name from profile_read) at
+        `bandlimit`; None times every launch again."""
+        idx = -1 if stage is None else list(self.profile_read().keys()).index(stage)
+        _check(lib.cvl_profile_filter(self.h, idx, int(bandlimit)))
 
     def profile_read_detail(self):
         """{(stage name, band-limit): (launches, ms)} of the timed launches."""

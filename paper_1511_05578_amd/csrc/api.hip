@@ -153,6 +153,7 @@ struct cvl_ctx {
     std::map<hipStream_t, Side> side;
     // profiling
     bool prof = false;
+    int pf_stage = -1, pf_tag = 0;  // only this (stage, band-limit) when pf_stage >= 0
     std::vector<hipEvent_t> pool;
     std::vector<std::tuple<int, int, hipEvent_t, hipEvent_t>> rec;  // stage, tag, events
     double stage_ms[ST_COUNT] = {0};
@@ -504,7 +505,7 @@ struct Prof {
     int stage, tag;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     Prof(cvl_ctx *c_, hipStream_t s, int stg) : c(c_), st(s), stage(stg), tag(g_tag) {
-        if (!c->prof) return;
+        if (!c->prof || (c->pf_stage >= 0 && (stage != c->pf_stage || tag != c->pf_tag))) return;
         e0 = take();
         e1 = take();
         if (e0) (void)hipEventRecord(e0, st);
@@ -1212,6 +1213,17 @@ int cvl_profile_enable(cvl_ctx *ctx, int on) {
         ctx->stage_n[i] = 0;
     }
     ctx->detail.clear();
+    return CVL_OK;
+}
+
+int cvl_profile_filter(cvl_ctx *ctx, int stage, int bandlimit) {
+    g_err.clear();
+    if (!ctx) return fail(CVL_EINVAL, "context is NULL");
+    if (stage < -1 || stage >= ST_COUNT)
+        return fail(CVL_EINVAL, "stage index %d outside [-1, %d)", stage, (int)ST_COUNT);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->pf_stage = stage;
+    ctx->pf_tag = bandlimit;
     return CVL_OK;
 }
 
