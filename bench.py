@@ -21,7 +21,7 @@ the reduced precisions the grids and the round trip are compared with the
 FP64 path (itself held to the oracle by the parity tests).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--L 256] [--batch 1]
-                       [--precision fp64] [--no-cpu]
+                       [--precision fp64] [--stream] [--real-grids] [--graph] [--no-cpu]
 """
 import argparse
 import json
@@ -137,7 +137,7 @@ def kernel_symbol(stage, Lj, prec, real_grids=False):
     if stage.startswith("beta"):
         return {"fp64": "k_beta_mfma", "fp32": "k_beta_mfma_f32", "bf16x3": "k_beta_mfma_bf16x3"}[prec]
     if stage == "contract_inv":
-        return "k_contract_inv" if prec == "fp64" else "k_contract_inv_mx" + mode
+        return "k_contract_inv_mfma" if prec == "fp64" else "k_contract_inv_mx" + mode
     if stage == "contract_fwd":
         return "k_contract_fwd_m1" if prec == "fp64" else "k_contract_fwd_mx1" + mode
     if stage == "reduce_fwd":
@@ -246,6 +246,9 @@ def main():
                     help="one scale at a time through the streaming interface (batch 1)")
     ap.add_argument("--real-grids", action="store_true",
                     help="real (float64 / float32) grids instead of complex ones")
+    ap.add_argument("--graph", action="store_true",
+                    help="also capture one step in a HIP graph and report its replay time "
+                         "(graph_replay_ms_per_step; not the headline value)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after timing, copy BYTES of device memory once (a plain copy kernel "
@@ -331,6 +334,21 @@ def main():
         detail = tdetail
         top = max((k for k in detail if k in models), key=lambda k: detail[k][1])
     print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
+
+    graph_ms = None
+    if args.graph and not args.stream:
+        # one step captured (timing events off) and replayed K times
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            step()
+        gr.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gr.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        del gr
 
     vs64 = None
     if prec != "fp64" and grids is not None:
@@ -419,6 +437,8 @@ def main():
     }
     if vs64 is not None:
         out["vs_fp64_path"] = vs64
+    if graph_ms is not None:
+        out["graph_replay_ms_per_step"] = graph_ms
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, lam, J0)
     ctx.close()

@@ -270,16 +270,26 @@ hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0
 //   P_e/o[m][k] = sum_{l even/odd} (Delta^l_{m'm} f_lm) (Delta^l_{m',2k} Psi_{l,2k})
 //   X[m'][m][h+k] = (-1)^k i^{-m} (P_e + P_o)
 //   X[m'][m][h-k] = (-1)^k i^{-m} (-1)^{m'} (P_e - P_o)
-// over l in [max(llo, m', m, 2k), lhi].  Tile 64 m x 32 k per work-group,
-// one m' per grid row; each thread owns 4 m x 2 k (x 2 parities).
+// over l in [max(llo, m', m, 2k), lhi], on FP64 MFMA.  Work-group: one m',
+// 64 m x 32 k.  The GEMM rows are (component c, m):
+// A[(c, m)][l] = c-part of Delta^l_{m'm} f_lm, B[l][k] = Delta^l_{m',2k} Psi_{l,2k}.
+// A chunk covers 32 consecutive l (16 of each parity = four K = 4 steps), the
+// next chunk's raw operands prefetched into registers.  Wave w: parity
+// p = w & 1, component c = w >> 1; 64 m x 32 k as 4 x 2 blocks of 16 x 16
+// (operand layouts: A[row = lane%16][K = lane/16], B[K = lane/16]
+// [col = lane%16], result row 4r + lane/16, column lane%16).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_contract_inv(ScaleGeom g, int Lf,
-                                                      const double *__restrict__ delta,
-                                                      const cd *__restrict__ fpad,
-                                                      const double *__restrict__ psi,
-                                                      cd *__restrict__ X) {
-    __shared__ cd Ash[8][64];
-    __shared__ double Bsh[8][32];
+__global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int Lf,
+                                                              const double *__restrict__ delta,
+                                                              const cd *__restrict__ fpad,
+                                                              const double *__restrict__ psi,
+                                                              cd *__restrict__ X) {
+    // As[p][c][i][mm] (l = lb + p + 2i), Bs[p][i][kk]; then R[p][mm][kk] for
+    // one component at a time in the epilogue.  Pads 66 / 34 spread the four
+    // 16-lane groups of an operand read over the LDS banks.
+    __shared__ double smem[2 * 2 * 16 * 66 + 2 * 16 * 34];
+    double(*As)[2][16][66] = reinterpret_cast<double(*)[2][16][66]>(smem);
+    double(*Bs)[16][34] = reinterpret_cast<double(*)[16][34]>(smem + 2 * 2 * 16 * 66);
     const int L = g.L, h = g.h;
     // logical tile: k tile fastest, then m tile, then m' (tiles of one m'
     // share its Delta rows; the tiles of one m' run on one XCD)
@@ -287,78 +297,116 @@ __global__ __launch_bounds__(256) void k_contract_inv(ScaleGeom g, int Lf,
     const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nkt * nmt);
     const int mp = lg / (nkt * nmt);
     const int m0 = ((lg / nkt) % nmt) * 64, k0 = (lg % nkt) * 32;
-    const int tid = threadIdx.x;
-    const int tm = tid % 16, tk = tid / 16;
-    cd pe[4][2], po[4][2];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int p = w & 1, c = w >> 1;
+    const int li = lane & 15, lq = lane >> 4;
+    cvl_d4 acc[4][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) pe[i][q] = po[i][q] = cd{0.0, 0.0};
+        for (int b = 0; b < 2; ++b) acc[a][b] = cvl_d4{0.0, 0.0, 0.0, 0.0};
     int lstart = g.llo;
     if (mp > lstart) lstart = mp;
     if (m0 > lstart) lstart = m0;
     if (2 * k0 > lstart) lstart = 2 * k0;
     const int lend = g.lhi;
-    for (int lb = lstart & ~1; lb <= lend; lb += 8) {
-        for (int idx = tid; idx < 512; idx += 256) {
-            const int lc = idx / 64, mm = idx % 64;
-            const int l = lb + lc, m = m0 + mm;
-            cd v = cd{0.0, 0.0};
-            if (l >= lstart && l <= lend && m <= l && m < L)
-                v = cscale(fpad[(size_t)l * Lf + m],
-                           delta[delta_off(l) + (int64_t)mp * (l + 1) + m]);
-            Ash[lc][mm] = v;
+    // The next chunk's raw operands, prefetched while the current one is
+    // multiplied: A element q: mm = idx & 63, i = (idx >> 6) & 15, pp = idx >> 10;
+    // B element q: kk = idx & 31, i = (idx >> 5) & 15, pp = idx >> 9.
+    double ra[8], rb2[4], rp[4];
+    cd rf[8];
+    auto fetch = [&](int lb) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int mm = idx & 63, i = (idx >> 6) & 15, pp = idx >> 10;
+            const int l = lb + pp + 2 * i, m = m0 + mm;
+            const bool ok = l >= lstart && l <= lend && m <= l && m < L;
+            ra[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + m] : 0.0;
+            rf[q] = ok ? fpad[(size_t)l * Lf + m] : cd{0.0, 0.0};
         }
-        {
-            const int lc = tid / 32, kk = tid % 32;
-            const int l = lb + lc, k = k0 + kk;
-            double v = 0.0;
-            if (l >= lstart && l <= lend && k <= h && 2 * k <= l)
-                v = delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] * psi[(size_t)l * (h + 1) + k];
-            Bsh[lc][kk] = v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, i = (idx >> 5) & 15, pp = idx >> 9;
+            const int l = lb + pp + 2 * i, k = k0 + kk;
+            const bool ok = l >= lstart && l <= lend && k <= h && 2 * k <= l;
+            rb2[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] : 0.0;
+            rp[q] = ok ? psi[(size_t)l * (h + 1) + k] : 0.0;
+        }
+    };
+    const int lb0 = lstart & ~1;
+    if (lb0 <= lend) fetch(lb0);
+    for (int lb = lb0; lb <= lend; lb += 32) {
+        // A: 2 parities x 16 l x 64 m complex; B: 2 parities x 16 l x 32 k
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int mm = idx & 63, i = (idx >> 6) & 15, pp = idx >> 10;
+            As[pp][0][i][mm] = ra[q] * rf[q].x;
+            As[pp][1][i][mm] = ra[q] * rf[q].y;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, i = (idx >> 5) & 15, pp = idx >> 9;
+            Bs[pp][i][kk] = rb2[q] * rp[q];
+        }
+        __syncthreads();
+        if (lb + 32 <= lend) fetch(lb + 32);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int i = 4 * ks + lq;
+            double b[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) b[cb] = Bs[p][i][16 * cb + li];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const double a = As[p][c][i][16 * rb + li];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cb], acc[rb][cb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // Epilogue, one component at a time through LDS: s = P_e + P_o, d = P_e - P_o.
+    double(*R)[64][33] = reinterpret_cast<double(*)[64][33]>(smem);
+    double sv[2][8], dv[2][8];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        if (c == cc) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        R[p][16 * rb + 4 * r + lq][16 * cb + li] = acc[rb][cb][r];
         }
         __syncthreads();
 #pragma unroll
-        for (int lc = 0; lc < 8; lc += 2) {
-            double b0[2], b1[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                b0[q] = Bsh[lc][tk + 16 * q];
-                b1[q] = Bsh[lc + 1][tk + 16 * q];
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const cd a0 = Ash[lc][tm + 16 * i];
-                const cd a1 = Ash[lc + 1][tm + 16 * i];
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    pe[i][q].x += a0.x * b0[q];
-                    pe[i][q].y += a0.y * b0[q];
-                    po[i][q].x += a1.x * b1[q];
-                    po[i][q].y += a1.y * b1[q];
-                }
-            }
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + 256 * q;
+            const int kk = idx & 31, mm = idx >> 5;
+            sv[cc][q] = R[0][mm][kk] + R[1][mm][kk];
+            dv[cc][q] = R[0][mm][kk] - R[1][mm][kk];
         }
         __syncthreads();
     }
     const int Nep = g.Nep;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + tm + 16 * i;
-        if (m >= L) continue;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int k = k0 + tk + 16 * q;
-            if (k > h) continue;
-            const double sk = (k & 1) ? -1.0 : 1.0;
-            cd *row = X + ((size_t)mp * L + m) * Nep;
-            const cd sp = cadd(pe[i][q], po[i][q]);
-            row[h + k] = ipow(cscale(sp, sk), -m);
-            if (k > 0) {
-                const double sm = (mp & 1) ? -sk : sk;
-                const cd sd = csub(pe[i][q], po[i][q]);
-                row[h - k] = ipow(cscale(sd, sm), -m);
-            }
+    for (int q = 0; q < 8; ++q) {
+        const int idx = tid + 256 * q;
+        const int kk = idx & 31, mm = idx >> 5;
+        const int m = m0 + mm, k = k0 + kk;
+        if (m >= L || k > h) continue;
+        const double sk = (k & 1) ? -1.0 : 1.0;
+        cd *row = X + ((size_t)mp * L + m) * Nep;
+        row[h + k] = ipow(cscale(cd{sv[0][q], sv[1][q]}, sk), -m);
+        if (k > 0) {
+            const double sm = (mp & 1) ? -sk : sk;
+            row[h - k] = ipow(cscale(cd{dv[0][q], dv[1][q]}, sm), -m);
         }
     }
 }
@@ -367,7 +415,7 @@ hipError_t launch_contract_inv(const ScaleGeom &g, int Lf, const double *delta, 
                                const double *psi, cd *X, hipStream_t st) {
     const int nkt = (g.h + 1 + 31) / 32;
     dim3 grid(((g.L + 63) / 64) * nkt * g.L);
-    hipLaunchKernelGGL(k_contract_inv, grid, dim3(256), 0, st, g, Lf, delta, fpad, psi, X);
+    hipLaunchKernelGGL(k_contract_inv_mfma, grid, dim3(256), 0, st, g, Lf, delta, fpad, psi, X);
     return hipGetLastError();
 }
 

@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
     float(*As)[2][32][66] = reinterpret_cast<float(*)[2][32][66]>(smem);
     float(*Bs)[32][34] = reinterpret_cast<float(*)[32][34]>(smem + 2 * 2 * 32 * 66);
     const int L = g.L, h = g.h;
-    // logical tile: k tile fastest, then m tile, then m' (see k_contract_inv)
+    // logical tile: k tile fastest, then m tile, then m' (see k_contract_inv_mfma)
     const int nkt = (h + 1 + 31) / 32, nmt = (L + 63) / 64;
     const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nkt * nmt);
     const int mp = lg / (nkt * nmt);
