@@ -1076,8 +1076,10 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
         if ((rc = sht_inverse_run(ctx, SP, B.fphi, Lp, smap, B.s0, B.s1, st))) return rc;
         if (sd && (rc = side_fork(sd, st))) return rc;
-        rc = sd ? analysis_scales(ctx, P, p, BS, g, 0, nside, sd->s) : CVL_OK;
-        if (!rc) rc = analysis_scales(ctx, P, p, B, g, nside, nJ, st);
+        // top scales enqueued first, so that the caller's stream starts on them
+        // while the side scales' launches are still being enqueued
+        rc = analysis_scales(ctx, P, p, B, g, nside, nJ, st);
+        if (!rc && sd) rc = analysis_scales(ctx, P, p, BS, g, 0, nside, sd->s);
         // joined even after an error: the next map (or call) reuses the buffers
         const int rj = sd ? side_join(sd, st) : CVL_OK;
         if (rc || (rc = rj)) return rc;
@@ -1109,8 +1111,8 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
         // top scales into B.facc, side scales into their own accumulator,
         // added in afterwards (a fixed order: results are deterministic)
         if (sd && (rc = side_fork(sd, st))) return rc;
-        rc = sd ? synthesis_scales(ctx, P, p, BS, g, 0, nside, sd->s) : CVL_OK;
-        if (!rc) rc = synthesis_scales(ctx, P, p, B, g, nside, nJ, st);
+        rc = synthesis_scales(ctx, P, p, B, g, nside, nJ, st);
+        if (!rc && sd) rc = synthesis_scales(ctx, P, p, BS, g, 0, nside, sd->s);
         const int rj = sd ? side_join(sd, st) : CVL_OK;
         if (rc || (rc = rj)) return rc;
         if (sd) LAUNCH(ST_MISC, launch_add(B.facc, BS.facc, (size_t)L * L, st));
