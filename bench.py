@@ -15,7 +15,9 @@ per-stage breakdown `stages`, `stages_by_bandlimit`, and the choice of the
 dominant kernel: the (stage, L_j) pair with the largest device time).  In the
 timed region only that kernel's launches carry events, recorded by the library
 on the launch stream, so `ms_per_step` does not pay for events on the other
-launches; `roofline` uses their average duration.  `cpu_baseline` is the CPU
+launches; `roofline` uses their average duration.  `whole_roofline` is the
+whole round trip against max(bytes / HBM peak, contraction flops / matrix
+peak + DFT flops / vector peak).  `cpu_baseline` is the CPU
 FP64 oracle timed on a bounded sample of the same workload and extrapolated.  For
 the reduced precisions the grids and the round trip are compared with the
 FP64 path (itself held to the oracle by the parity tests).
@@ -107,6 +109,40 @@ def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None):
         add("beta_gemm_fwd", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * Lj * Ne)
         add("contract_fwd", Lj, cube, 4.0 * terms)
     return m
+
+
+def whole_roofline(L, lam, J0, prec, NB, GB, ms):
+    """Roofline of the whole round trip: t_roof = max(bytes / HBM peak,
+    contraction flops / matrix peak + DFT flops / vector peak) with bytes the
+    grids written once and read once plus the maps, contraction flops 4 per
+    (l, m >= 0, m' >= 0, even n) term with l >= max(m, m', |n|) (x3 for split
+    BF16), DFT flops 5 n log2 n per complex line of length n = 2L_j - 1 over
+    the beta, alpha and gamma lines of a (2L_j - 1) x L_j x (2L_j - 1) grid in
+    both directions, halved for the real signal."""
+    gb = 2 * grid_bytes(L, lam, J0, GB)
+    Lp = min(int(math.ceil(lam ** J0)), L)
+    maps = 2 * L * (2 * L - 1) * 8 + 2 * Lp * (2 * Lp - 1) * 8
+    nbytes = NB * (gb + maps)
+    con = dft = 0.0
+    for g in scale_geoms(L, lam, J0):
+        Lj, Nm = g["L"], g["Nm"]
+        terms = sum((l + 1) * (l + 1) * (2 * (l // 2) + 1)
+                    for l in range(g["llo"], g["lhi"] + 1))
+        con += 2 * 4.0 * terms
+        fft = 5.0 * Nm * math.log2(Nm)
+        # per direction: beta lines (m, n), alpha lines (b, n), gamma lines (a, b)
+        dft += 2 * 0.5 * fft * (Nm * Nm + Lj * Nm + Nm * Lj)
+    con *= NB * (3 if prec == "bf16x3" else 1)
+    dft *= NB
+    peak_c = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS,
+              "bf16x3": BF16_MFMA_PEAK_TFLOPS}[prec]
+    peak_v = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+    t_mem = nbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_cmp = (con / (peak_c * 1e12) + dft / (peak_v * 1e12)) * 1e3
+    t_roof = max(t_mem, t_cmp)
+    return {"t_roof_ms": t_roof, "bound": "hbm" if t_mem >= t_cmp else "compute",
+            "frac": t_roof / ms, "bytes": nbytes, "contraction_flops": con,
+            "dft_flops": dft}
 
 
 def bluestein_size(Lj):
@@ -431,6 +467,7 @@ def main():
         "round_trip_rel_l2": err,
         "source": source_fingerprint(),
         "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, GB) / (HBM_PEAK_GBS * 1e9) * 1e3,
+        "whole_roofline": whole_roofline(L, lam, J0, prec, NB, GB, ms),
         "roofline": roof,
         "stages": stages,
         "stages_by_bandlimit": {"%s@%d" % k: round(v[1] / nprof, 4) for k, v in sorted(detail.items())},
