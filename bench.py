@@ -228,7 +228,8 @@ def cpu_baseline(L, lam=2.0, J0=2):
     """Oracle round-trip time at this workload, from a bounded sample: one beta
     row per scale of the analysis and one Gauss-Legendre node per scale of the
     synthesis (plus that scale's full alpha/gamma Fourier step), scaled by the
-    rows / nodes each scale has."""
+    rows / nodes each scale has.  Also returns the sampled oracle rows
+    {scale index: (row b, grid[:, b, :])} of the seed-0 map."""
     import numpy as np
     from oracle import curvelet as ocurv
     from oracle import sht as osht
@@ -239,10 +240,12 @@ def cpu_baseline(L, lam=2.0, J0=2):
     t_an = 0.0
     t_sy = 0.0
     t0 = time.perf_counter()
-    for j in plan.scales:
+    rows = {}
+    for s, j in enumerate(plan.scales):
         Lj = plan.Lj[j]
         a = time.perf_counter()
         row = ocurv.analysis_scale(plan, f, j, rows=[Lj // 2])
+        rows[s] = (Lj // 2, row)
         t_row = time.perf_counter() - a
         t_an += t_row * Lj
         # synthesis: full alpha/gamma step + one node, scaled to all nodes
@@ -265,7 +268,7 @@ def cpu_baseline(L, lam=2.0, J0=2):
             "sample": "L=%d: 1 beta row per scale of the analysis and 1 Gauss-Legendre node per "
                       "scale of the synthesis (with its full alpha/gamma step), extrapolated by "
                       "rows/nodes per scale, plus one SHT pair; %.1f s sampled, estimated %.1f s "
-                      "per round trip" % (L, wall, t_total)}
+                      "per round trip" % (L, wall, t_total)}, rows
 
 
 def main():
@@ -477,7 +480,21 @@ def main():
     if graph_ms is not None:
         out["graph_replay_ms_per_step"] = graph_ms
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(L, lam, J0)
+        out["cpu_baseline"], orows = cpu_baseline(L, lam, J0)
+        if grids is not None and not args.point_sources:
+            # the first map (seed 0) against the oracle's sampled beta rows
+            import numpy as np
+            num = den = mx = mref = 0.0
+            for s_, (b, row) in orows.items():
+                g = grids[0][s_][:, b:b + 1, :].cpu().numpy().astype(np.complex128)
+                d = g - row
+                num += float(np.sum(np.abs(d) ** 2))
+                den += float(np.sum(np.abs(row) ** 2))
+                mx = max(mx, float(np.abs(d).max()))
+                mref = max(mref, float(np.abs(row).max()))
+            out["vs_oracle_sampled"] = {"grids_rel_l2": math.sqrt(num / den),
+                                        "grids_max_abs_rel": mx / mref,
+                                        "rows": "beta row L_j/2 of every scale, map 0"}
     ctx.close()
     print(json.dumps(out), flush=True)
 
