@@ -13,6 +13,11 @@ Synthesis (Sec. II-D-2, harmonic form of exact reconstruction):
   f_lm = sqrt(4pi/(2l+1)) (W^Phi)_lm Phi_l0 + sum_j sum_n (W^(j))^l_mn Psi^(j)_ln,
 with (W^(j))^l_mn the forward Wigner transform of each grid (``so3``).
 
+Unrotated curvelets (Sec. III-A-1): ``Plan(..., rotated=False)`` builds Psi from
+zeta~ itself (|n| = l only) instead of its rotation by rho* = (0, pi/2, 0); the
+same analysis and synthesis then give W~(rho) = W(rho rho*^-1) and reconstruct
+exactly.
+
 Parameters (Sec. II-B and Sec. III-A-3): J = ceil(log_lambda L); per-scale
 band-limit L_j = min(ceil(lambda^(j+1)), L); L_Phi = min(ceil(lambda^J0), L).
 """
@@ -24,18 +29,26 @@ from . import kernels, sampling, sht, so3, wigner
 
 
 class Plan:
-    """Kernel tables for one (L, lambda, J0), spin 0."""
+    """Kernel tables for one (L, lambda, J0), spin 0.
 
-    def __init__(self, L, lam=2.0, J0=2):
+    ``rotated`` (default): the curvelets rotated so that they are centred on
+    the North pole (Sec. II-B), Psi from zeta = d(pi/2) zeta~.  With
+    rotated=False the unrotated curvelets (zeta~ itself, |n| = l only), whose
+    coefficients the fast algorithm of Sec. III-A computes:
+    W~(rho) = W(rho rho*^-1) with rho* = (0, pi/2, 0)."""
+
+    def __init__(self, L, lam=2.0, J0=2, rotated=True):
         self.L, self.lam, self.J0 = L, float(lam), J0
+        self.rotated = bool(rotated)
         self.J = kernels.num_scales(L, lam)
         if J0 > self.J:
             raise ValueError("J0 must not exceed J = ceil(log_lambda L)")
         self.scales = list(range(J0, self.J + 1))
         self.Lj = {j: kernels.scale_bandlimit(j, L, lam) for j in self.scales}
         self.Lphi = kernels.scaling_bandlimit(L, lam, J0)
-        self.psi = kernels.psi_table(L, lam, J0, self.J)     # [j-J0, l, n+L-1]
-        self.phi = kernels.phi_table(L, lam, J0)              # [l]
+        theta = math.pi / 2 if rotated else 0.0
+        self.psi = kernels.psi_table(L, lam, J0, self.J, theta)  # [j-J0, l, n+L-1]
+        self.phi = kernels.phi_table(L, lam, J0)                  # [l]
 
     def psi_j(self, j, Lj):
         """Psi^(j)_ln restricted to l < Lj, |n| < Lj: [l, n + Lj - 1]."""
