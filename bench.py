@@ -68,7 +68,7 @@ def scale_geoms(L, lam=2.0, J0=2):
     return out
 
 
-def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None):
+def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None, unrot=False):
     """Algorithmic bytes / flops of each kernel stage per round trip of one
     map, keyed (stage, L_j): one launch per scale, scales of equal L_j summed.
 
@@ -81,6 +81,11 @@ def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None):
     5 n log2 n per complex line of length n = 2L_j - 1 (from L_j =
     BETA_FFT_MIN_L on, the analysis beta stage is such a DFT stage over
     (L_j + 1) / 2 * Ne line pairs).
+
+    Unrotated curvelets (unrot): the cube holds every n (2 L_j rows of Nc
+    columns per m' plane, Nc = max(2h + 1, 2 floor(L_j / 2))), the alpha / gamma
+    planes every n >= 0; the contractions have one term per non-zero cube entry
+    (l = |n|), the synthesis one reading only the n = +-l entries.
     """
     m = {}
     GB = B if GB is None else GB
@@ -91,6 +96,26 @@ def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None):
 
     for g in scale_geoms(L, lam, J0):
         Lj, Nm, h, Ne = g["L"], g["Nm"], g["h"], g["Ne"]
+        if unrot:
+            Nc = max(2 * h + 1, 2 * (Lj // 2))
+            terms = sum((l + 1) * (l + 1) * (2 if l else 1)
+                        for l in range(g["llo"], g["lhi"] + 1))
+            cube = Lj * 2 * Lj * Nc * B
+            w2 = Lj * Nm * Lj * B
+            grid = Nm * Lj * Nm * GB
+            fft = 5.0 * Nm * math.log2(Nm)
+            add("contract_inv", Lj, cube, 4.0 * terms)
+            if Lj >= BETA_FFT_MIN_L:
+                add("beta_gemm_inv", Lj, 2 * cube, Lj * Nc * fft)
+            else:
+                add("beta_gemm_inv", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * 2 * Lj * Nc)
+            add("alpha_dft_inv", Lj, cube + w2, Lj * Lj * fft)
+            add("gamma_dft_inv", Lj, w2 + grid, Nm * Lj * fft)
+            add("gamma_dft_fwd", Lj, grid + w2, Nm * Lj * fft)
+            add("alpha_dft_fwd", Lj, w2 + cube, Lj * Lj * fft)
+            add("beta_gemm_fwd", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * 2 * Lj * Nc)
+            add("contract_fwd", Lj, terms * B, 4.0 * terms)
+            continue
         terms = sum((l + 1) * (l + 1) * (l // 2 + 1) for l in range(g["llo"], g["lhi"] + 1))
         cube = Lj * Lj * Ne * B
         w2 = Lj * Nm * (h + 1) * B
@@ -111,14 +136,15 @@ def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None):
     return m
 
 
-def whole_roofline(L, lam, J0, prec, NB, GB, ms):
+def whole_roofline(L, lam, J0, prec, NB, GB, ms, unrot=False):
     """Roofline of the whole round trip: t_roof = max(bytes / HBM peak,
     contraction flops / matrix peak + DFT flops / vector peak) with bytes the
     grids written once and read once plus the maps, contraction flops 4 per
     (l, m >= 0, m' >= 0, even n) term with l >= max(m, m', |n|) (x3 for split
     BF16), DFT flops 5 n log2 n per complex line of length n = 2L_j - 1 over
     the beta, alpha and gamma lines of a (2L_j - 1) x L_j x (2L_j - 1) grid in
-    both directions, halved for the real signal."""
+    both directions, halved for the real signal.  Unrotated curvelets: one
+    contraction term per (l, m >= 0, m' <= l, n = +-l)."""
     gb = 2 * grid_bytes(L, lam, J0, GB)
     Lp = min(int(math.ceil(lam ** J0)), L)
     maps = 2 * L * (2 * L - 1) * 8 + 2 * Lp * (2 * Lp - 1) * 8
@@ -126,8 +152,12 @@ def whole_roofline(L, lam, J0, prec, NB, GB, ms):
     con = dft = 0.0
     for g in scale_geoms(L, lam, J0):
         Lj, Nm = g["L"], g["Nm"]
-        terms = sum((l + 1) * (l + 1) * (2 * (l // 2) + 1)
-                    for l in range(g["llo"], g["lhi"] + 1))
+        if unrot:
+            terms = sum((l + 1) * (l + 1) * (2 if l else 1)
+                        for l in range(g["llo"], g["lhi"] + 1))
+        else:
+            terms = sum((l + 1) * (l + 1) * (2 * (l // 2) + 1)
+                        for l in range(g["llo"], g["lhi"] + 1))
         con += 2 * 4.0 * terms
         fft = 5.0 * Nm * math.log2(Nm)
         # per direction: beta lines (m, n), alpha lines (b, n), gamma lines (a, b)
@@ -153,13 +183,14 @@ def bluestein_size(Lj):
     return P
 
 
-def kernel_symbol(stage, Lj, prec, real_grids=False):
+def kernel_symbol(stage, Lj, prec, real_grids=False, unrot=False):
     """HIP kernel (template instance) that runs a stage at band-limit L_j."""
     c = "cd" if prec == "fp64" else "cf"
     P = bluestein_size(Lj)
-    io = {"alpha_dft_inv": "InvAlphaIO", "alpha_dft_fwd": "FwdAlphaIO",
-          "gamma_dft_inv": "InvGammaPackIO" if P >= 256 else "InvGammaIO",
-          "gamma_dft_fwd": "FwdGammaPackIO" if P >= 256 else "FwdGammaIO"}
+    u = "Unrot" if unrot else ""
+    io = {"alpha_dft_inv": u + "InvAlphaIO", "alpha_dft_fwd": u + "FwdAlphaIO",
+          "gamma_dft_inv": u + ("InvGammaPackIO" if P >= 256 else "InvGammaIO"),
+          "gamma_dft_fwd": u + ("FwdGammaPackIO" if P >= 256 else "FwdGammaIO")}
     if stage in io:
         targs = c
         if stage.startswith("gamma"):  # grid element type
@@ -172,6 +203,8 @@ def kernel_symbol(stage, Lj, prec, real_grids=False):
         return "k_blue_r16<%d, BetaInvPairIO<%s> >" % (P, c)
     if stage.startswith("beta"):
         return {"fp64": "k_beta_mfma", "fp32": "k_beta_mfma_f32", "bf16x3": "k_beta_mfma_bf16x3"}[prec]
+    if unrot and stage in ("contract_inv", "contract_fwd"):
+        return "k_unrot_%s<%s>" % (stage, c)
     if stage == "contract_inv":
         return "k_contract_inv_mfma" if prec == "fp64" else "k_contract_inv_mx" + mode
     if stage == "contract_fwd":
@@ -224,7 +257,7 @@ def grid_bytes(L, lam=2.0, J0=2, B=16.0):
     return sum(g["Nm"] * g["L"] * g["Nm"] * B for g in scale_geoms(L, lam, J0))
 
 
-def cpu_baseline(L, lam=2.0, J0=2):
+def cpu_baseline(L, lam=2.0, J0=2, unrot=False):
     """Oracle round-trip time at this workload, from a bounded sample: one beta
     row per scale of the analysis and one Gauss-Legendre node per scale of the
     synthesis (plus that scale's full alpha/gamma Fourier step), scaled by the
@@ -235,7 +268,7 @@ def cpu_baseline(L, lam=2.0, J0=2):
     from oracle import sht as osht
     from paper_1511_05578_amd import inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    plan = ocurv.Plan(L, lam, J0)
+    plan = ocurv.Plan(L, lam, J0, rotated=not unrot)
     f = inputs.gaussian_real_flm(L, seed=0)
     t_an = 0.0
     t_sy = 0.0
@@ -285,6 +318,8 @@ def main():
                     help="one scale at a time through the streaming interface (batch 1)")
     ap.add_argument("--real-grids", action="store_true",
                     help="real (float64 / float32) grids instead of complex ones")
+    ap.add_argument("--unrotated", action="store_true",
+                    help="coefficients of the unrotated curvelets (|n| = l Wigner path)")
     ap.add_argument("--graph", action="store_true",
                     help="also capture one step in a HIP graph and report its replay time "
                          "(graph_replay_ms_per_step; not the headline value)")
@@ -304,6 +339,7 @@ def main():
     L, lam, J0, NB, prec = args.L, 2.0, 2, args.batch, args.precision
     EB = 16.0 if prec == "fp64" else 8.0  # complex element of the intermediates
     RG = args.real_grids
+    UR = args.unrotated
     GB = EB / 2 if RG else EB  # grid element
     ctx = api.Context(L, 0)
     ctx.prepare(L, lam, J0)
@@ -325,17 +361,19 @@ def main():
         grids = None
 
         def step():
-            r, _ = ctx.round_trip_streamed(maps[0], lam, J0, precision=prec, real_grids=RG)
+            r, _ = ctx.round_trip_streamed(maps[0], lam, J0, precision=prec, real_grids=RG,
+                                           unrotated=UR)
             rec[0].copy_(r)
     else:
         scal, grids = ctx.alloc_outputs(L, lam, J0, NB, precision=prec, real_grids=RG)
 
         def step():
-            ctx.curvelet_analysis(maps, lam, J0, out=(scal, grids), precision=prec, real_grids=RG)
+            ctx.curvelet_analysis(maps, lam, J0, out=(scal, grids), precision=prec, real_grids=RG,
+                                  unrotated=UR)
             ctx.curvelet_synthesis(scal, grids, L, lam, J0, out=rec, precision=prec,
-                                   real_grids=RG)
+                                   real_grids=RG, unrotated=UR)
 
-    models = stage_models(L, lam, J0, EB, GB)
+    models = stage_models(L, lam, J0, EB, GB, UR)
     # Warm-up: every launch timed (per-stage breakdown, dominant kernel);
     # the first step, which may still build plans, is left out.
     if args.warmup > 0:
@@ -392,7 +430,8 @@ def main():
     vs64 = None
     if prec != "fp64" and grids is not None:
         # the first map's grids against the FP64 path's
-        s64, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64", real_grids=RG)
+        s64, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64", real_grids=RG,
+                                         unrotated=UR)
         num = den = 0.0
         mx = mref = 0.0
         for a, b in zip(grids[0], g64[0]):
@@ -424,10 +463,10 @@ def main():
         roof = {"bound": "mfma" if top[0].startswith(("contract", "beta")) else "alu",
                 "achieved": flops_per_launch / t_top / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    wkey = "L%d_b%d_%s%s%s%s" % (L, NB, prec, "_stream" if args.stream else "",
-                                 "_ps%d" % args.point_sources if args.point_sources else "",
-                                 "_rg" if RG else "")
-    sym = kernel_symbol(top[0], top[1], prec, RG)
+    wkey = "L%d_b%d_%s%s%s%s%s" % (L, NB, prec, "_stream" if args.stream else "",
+                                   "_ps%d" % args.point_sources if args.point_sources else "",
+                                   "_rg" if RG else "", "_unrot" if UR else "")
+    sym = kernel_symbol(top[0], top[1], prec, RG, UR)
     roof["traffic"] = recorded_traffic(wkey, sym)
     roof["kernel"] = sym
     roof["stage"] = top[0]
@@ -443,11 +482,12 @@ def main():
 
     gname = ("float64" if prec == "fp64" else "float32") if RG else \
         ("complex128" if prec == "fp64" else "complex64")
-    work = ("%d real spin-0 map%s%s, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, %s grids%s, %s, "
+    work = ("%d real spin-0 map%s%s, L=%d, lambda=2, J0=2, J=%d, N_j=L_j, %s%s grids%s, %s, "
             "analysis+synthesis round trip" % (
                 NB, "" if NB == 1 else "s",
                 " with %d point sources" % args.point_sources if args.point_sources else "",
-                L, api.num_scales(L), gname, " streamed one scale at a time" if args.stream else "",
+                L, api.num_scales(L), "unrotated-curvelet " if UR else "", gname,
+                " streamed one scale at a time" if args.stream else "",
                 {"fp64": "FP64 throughout",
                  "fp32": "FP32 MFMA contractions, FP32 FFT/beta",
                  "bf16x3": "split-BF16 MFMA contractions, FP32 FFT/beta"}[prec]))
@@ -465,12 +505,12 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[prec],
         "data": "synthetic: f_lm ~ N(0,(l+1)^-2) real-map coefficients, seeds 0..%d" % (NB - 1),
         "config": {"workload": work, "L": L, "lambda": lam, "J0": J0, "batch": NB,
-                   "precision": prec, "stream": bool(args.stream),
+                   "precision": prec, "stream": bool(args.stream), "unrotated": bool(UR),
                    "point_sources": args.point_sources, "grid_bytes": NB * grid_bytes(L, lam, J0, GB)},
         "round_trip_rel_l2": err,
         "source": source_fingerprint(),
         "hbm_roofline_ms": 2 * NB * grid_bytes(L, lam, J0, GB) / (HBM_PEAK_GBS * 1e9) * 1e3,
-        "whole_roofline": whole_roofline(L, lam, J0, prec, NB, GB, ms),
+        "whole_roofline": whole_roofline(L, lam, J0, prec, NB, GB, ms, UR),
         "roofline": roof,
         "stages": stages,
         "stages_by_bandlimit": {"%s@%d" % k: round(v[1] / nprof, 4) for k, v in sorted(detail.items())},
@@ -480,7 +520,7 @@ def main():
     if graph_ms is not None:
         out["graph_replay_ms_per_step"] = graph_ms
     if not args.no_cpu:
-        out["cpu_baseline"], orows = cpu_baseline(L, lam, J0)
+        out["cpu_baseline"], orows = cpu_baseline(L, lam, J0, UR)
         if grids is not None and not args.point_sources:
             # the first map (seed 0) against the oracle's sampled beta rows
             import numpy as np

@@ -69,6 +69,7 @@ enum {
 /* Flags of cvl_params. */
 #define CVL_REAL 1u        /* real map (f_{l,-m} = (-1)^m conj f_lm); required */
 #define CVL_REAL_GRIDS 2u  /* curvelet grids of real elements (see cvl_curvelet_analysis) */
+#define CVL_UNROTATED 4u   /* coefficients of the unrotated curvelets (see cvl_curvelet_analysis) */
 
 /* Precision of the curvelet calls (cvl_params.precision). */
 #define CVL_FP64 0         /* everything FP64, complex128 (or double) grids */
@@ -86,7 +87,8 @@ typedef struct cvl_ctx cvl_ctx;
  * lowest curvelet scale, J0 <= J where J = ceil(log_lambda L).  spin: must
  * be 0.  precision: CVL_FP64, CVL_FP32 or CVL_BF16X3 (curvelet calls only;
  * it selects the grid element type).  flags: CVL_REAL (required), optionally
- * CVL_REAL_GRIDS; other bits are rejected. */
+ * CVL_REAL_GRIDS and CVL_UNROTATED; other bits are rejected.  The workspace
+ * size depends on CVL_UNROTATED (cvl_workspace_bytes). */
 typedef struct {
     int L;
     int N;
@@ -163,6 +165,14 @@ int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid,
  *     CVL_REAL_GRIDS the elements are double (CVL_FP64) or float instead,
  *     holding the same real parts: the conjugate symmetry of real signals
  *     halves the grids' memory and traffic (Sec. III-A-3).
+ *   By default the curvelets are the ones rotated to the North pole (Sec.
+ *     II-B), W^(j)(rho) = <f, R_rho psi^(j)>.  With CVL_UNROTATED the grids
+ *     hold the coefficients of the unrotated curvelets psi~^(j) (directional
+ *     component zeta~, harmonic coefficients only at |n| = l) instead,
+ *     W~^(j)(rho) = <f, R_rho psi~^(j)> = W^(j)(rho rho*^-1) with
+ *     rho* = (0, pi/2, 0) (Sec. III-A-1); their Wigner transforms need one l
+ *     per (m, n) rather than a sum over l, O(L_j^3) per scale.  Same shapes,
+ *     element types and synthesis (exact reconstruction) with the same flag.
  * `grids` is a HOST array of batch * nJ device pointers. */
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
                           const double *maps, double *scal_maps,

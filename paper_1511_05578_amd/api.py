@@ -13,7 +13,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcurvelet.so")
 
 CVL_OK, CVL_EINVAL, CVL_ENOMEM, CVL_EDEVICE, CVL_EUNSUPPORTED = 0, -1, -2, -3, -4
-CVL_REAL, CVL_REAL_GRIDS = 1, 2
+CVL_REAL, CVL_REAL_GRIDS, CVL_UNROTATED = 1, 2, 4
 CVL_FP64, CVL_FP32, CVL_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": CVL_FP64, "fp32": CVL_FP32, "bf16x3": CVL_BF16X3}
 
@@ -108,9 +108,12 @@ def _prec(precision):
     return int(precision)
 
 
-def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL, precision=CVL_FP64, real_grids=False):
+def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL, precision=CVL_FP64, real_grids=False,
+           unrotated=False):
     if real_grids:
         flags |= CVL_REAL_GRIDS
+    if unrotated:
+        flags |= CVL_UNROTATED
     return CvlParams(L, N, float(lam), J0, spin, _prec(precision), flags)
 
 
@@ -132,10 +135,10 @@ def scaling_bandlimit(L, lam=2.0, J0=2):
     return v.value
 
 
-def workspace_bytes(L, lam=2.0, J0=2, batch=1, precision=CVL_FP64):
+def workspace_bytes(L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, unrotated=False):
     v = ctypes.c_size_t()
-    _check(lib.cvl_workspace_bytes(ctypes.byref(params(L, lam, J0, precision=precision)), batch,
-                                   ctypes.byref(v)))
+    p = params(L, lam, J0, precision=precision, unrotated=unrotated)
+    _check(lib.cvl_workspace_bytes(ctypes.byref(p), batch, ctypes.byref(v)))
     return v.value
 
 
@@ -265,9 +268,10 @@ class Context:
         return scal, grids
 
     def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                          real_grids=False):
+                          real_grids=False, unrotated=False):
         """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids);
-        grids of grid_dtype(precision, real_grids)."""
+        grids of grid_dtype(precision, real_grids).  unrotated: coefficients
+        of the unrotated curvelets (CVL_UNROTATED)."""
         t = self.torch
         single = maps.dim() == 2
         if single:
@@ -282,8 +286,8 @@ class Context:
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
-        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision, unrotated))
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
         _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(p), batch,
                                          maps.data_ptr(), scal.data_ptr(), arr, ws.data_ptr(),
                                          ws.numel(), _stream(t)))
@@ -292,7 +296,7 @@ class Context:
         return scal, grids
 
     def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                           real_grids=False):
+                           real_grids=False, unrotated=False):
         t = self.torch
         single = scal.dim() == 2
         if single:
@@ -306,8 +310,8 @@ class Context:
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
-        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision, unrotated))
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
         _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(p), batch,
                                           scal.data_ptr(), arr, out.data_ptr(), ws.data_ptr(),
                                           ws.numel(), _stream(t)))
@@ -315,7 +319,7 @@ class Context:
 
     # ---- streaming (one scale at a time) ----
     def analysis_scale(self, flm, L, j, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                       real_grids=False):
+                       real_grids=False, unrotated=False):
         """Grid of scale j from harmonic coefficients flm (L^2 complex128)."""
         t = self.torch
         assert flm.dtype == t.complex128 and flm.is_contiguous() and flm.numel() == L * L
@@ -324,20 +328,20 @@ class Context:
             Lj, _ = scale_shape(L, j, lam, J0)
             out = t.empty((2 * Lj - 1, Lj, 2 * Lj - 1), dtype=dt, device=self.device)
         assert out.dtype == dt and out.is_contiguous()
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
         _check(lib.cvl_curvelet_analysis_scale(self.h, ctypes.byref(p), j, flm.data_ptr(),
                                                out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(t)))
         return out
 
     def synthesis_scale(self, grid, L, j, flm_acc, lam=2.0, J0=2, precision=CVL_FP64,
-                        real_grids=False):
+                        real_grids=False, unrotated=False):
         """flm_acc += f^(j)_lm from scale j's grid."""
         t = self.torch
         assert grid.dtype == self.grid_dtype(precision, real_grids) and grid.is_contiguous()
         assert flm_acc.dtype == t.complex128 and flm_acc.numel() == L * L
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids)
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
         _check(lib.cvl_curvelet_synthesis_scale(self.h, ctypes.byref(p), j, grid.data_ptr(),
                                                 flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
                                                 _stream(t)))
@@ -345,28 +349,30 @@ class Context:
 
     # The scaling part is FP64 at every precision; `precision` only names the
     # streaming workspace (cvl_workspace_bytes of the same parameters) to use.
-    def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None, precision=CVL_FP64):
+    def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None, precision=CVL_FP64,
+                         unrotated=False):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
         if out is None:
             out = t.empty((Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
-        p = params(L, lam, J0, precision=precision)
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        p = params(L, lam, J0, precision=precision, unrotated=unrotated)
         _check(lib.cvl_curvelet_scaling_analysis(self.h, ctypes.byref(p), flm.data_ptr(),
                                                  out.data_ptr(), ws.data_ptr(), ws.numel(),
                                                  _stream(t)))
         return out
 
-    def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2, precision=CVL_FP64):
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision))
-        p = params(L, lam, J0, precision=precision)
+    def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2, precision=CVL_FP64,
+                          unrotated=False):
+        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        p = params(L, lam, J0, precision=precision, unrotated=unrotated)
         _check(lib.cvl_curvelet_scaling_synthesis(self.h, ctypes.byref(p), scal.data_ptr(),
                                                   flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
                                                   _stream(self.torch)))
         return flm_acc
 
     def round_trip_streamed(self, fmap, lam=2.0, J0=2, precision=CVL_FP64, on_grid=None,
-                            real_grids=False):
+                            real_grids=False, unrotated=False):
         """Analysis + synthesis of one real map, one scale at a time (a single
         grid buffer of the largest scale is reused).  on_grid(j, grid), if
         given, sees each scale's grid between its analysis and synthesis."""
@@ -374,7 +380,7 @@ class Context:
         L = fmap.shape[-2]
         flm = self.sht_forward(fmap)
         acc = t.zeros(L * L, dtype=t.complex128, device=self.device)
-        scal = self.scaling_analysis(flm, L, lam, J0, precision=precision)
+        scal = self.scaling_analysis(flm, L, lam, J0, precision=precision, unrotated=unrotated)
         J = num_scales(L, lam, J0)
         Lt, _ = scale_shape(L, J, lam, J0)
         buf = t.empty((2 * Lt - 1) * Lt * (2 * Lt - 1),
@@ -383,12 +389,12 @@ class Context:
             Lj, _ = scale_shape(L, j, lam, J0)
             g = buf[:(2 * Lj - 1) * Lj * (2 * Lj - 1)].view(2 * Lj - 1, Lj, 2 * Lj - 1)
             self.analysis_scale(flm, L, j, lam, J0, out=g, precision=precision,
-                                real_grids=real_grids)
+                                real_grids=real_grids, unrotated=unrotated)
             if on_grid is not None:
                 on_grid(j, g)
             self.synthesis_scale(g, L, j, acc, lam, J0, precision=precision,
-                                 real_grids=real_grids)
-        self.scaling_synthesis(scal, L, acc, lam, J0, precision=precision)
+                                 real_grids=real_grids, unrotated=unrotated)
+        self.scaling_synthesis(scal, L, acc, lam, J0, precision=precision, unrotated=unrotated)
         return self.sht_inverse(acc, L), scal
 
     def delta_block(self, l):

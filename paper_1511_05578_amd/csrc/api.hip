@@ -99,6 +99,7 @@ struct ScaleRt {
     int j;
     ScaleGeom g;
     double *psi;  // [l][k]: Psi^(j)_{l,2k}
+    double *psi2; // [l]: Psi~^(j)_{l,l} of the unrotated curvelets
     BetaTabs beta;
     BluesteinDev inv_full, fwd_full;
     BetaTabsF betaf;
@@ -348,7 +349,7 @@ int check_params(const cvl_params *p, int *J) {
     if (p->precision != CVL_FP64 && p->precision != CVL_FP32 && p->precision != CVL_BF16X3)
         return fail(CVL_EINVAL, "precision=%d is not CVL_FP64, CVL_FP32 or CVL_BF16X3",
                     p->precision);
-    if (p->flags & ~(CVL_REAL | CVL_REAL_GRIDS))
+    if (p->flags & ~(CVL_REAL | CVL_REAL_GRIDS | CVL_UNROTATED))
         return fail(CVL_EINVAL, "flags=0x%x: unknown bits", p->flags);
     if (J) *J = JJ;
     return CVL_OK;
@@ -375,15 +376,17 @@ int fwd_groups(const ScaleGeom &g) { return g.L; }
 // Elements of the two cube buffers of the scales at the top band-limit
 // (b0, b1) and of the side scales below it (sb0, sb1), which run
 // concurrently on a side stream with buffers of their own.
-void curvelet_buf_elems(int L, double lam, int J0, int J, size_t *b0, size_t *b1, size_t *sb0,
-                        size_t *sb1) {
+void curvelet_buf_elems(int L, double lam, int J0, int J, bool unrot, size_t *b0, size_t *b1,
+                        size_t *sb0, size_t *sb1) {
     *b0 = *b1 = *sb0 = *sb1 = 0;
     const int top = scale_bandlimit(J, L, lam);
     for (int j = J0; j <= J; ++j) {
         ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
-        size_t cube = (size_t)g.L * g.L * g.Nep;
-        size_t w2 = (size_t)g.L * g.Nm * (g.h + 1);
-        size_t part = (size_t)g.L * g.L * g.L;  // at most L_j groups
+        // unrotated: 2 L_j cube rows per plane, W2 / V1 rows of L_j entries,
+        // no partial sums
+        size_t cube = (size_t)g.L * (unrot ? 2 * g.L : g.L) * g.Nep;
+        size_t w2 = (size_t)g.L * g.Nm * (unrot ? g.L : g.h + 1);
+        size_t part = unrot ? 0 : (size_t)g.L * g.L * g.L;  // at most L_j groups
         size_t *x0 = g.L < top ? sb0 : b0, *x1 = g.L < top ? sb1 : b1;
         *x0 = std::max({*x0, cube, w2});
         *x1 = std::max({*x1, cube, part});
@@ -393,9 +396,9 @@ void curvelet_buf_elems(int L, double lam, int J0, int J, size_t *b0, size_t *b1
 // Workspace bytes of a curvelet call: two cube buffers for the top scales and
 // two for the side scales (complex128, or complex64 in reduced precision) and
 // six L x L complex128 planes.
-size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision) {
+size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision, bool unrot) {
     size_t b0, b1, sb0, sb1;
-    curvelet_buf_elems(L, lam, J0, J, &b0, &b1, &sb0, &sb1);
+    curvelet_buf_elems(L, lam, J0, J, unrot, &b0, &b1, &sb0, &sb1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     const int Lphi = scaling_bandlimit(L, lam, J0);
     size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
@@ -447,6 +450,11 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
                 psi[(size_t)l * (h + 1) + k] = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) *
                                                kj[l] * std::sqrt(2.0) * acol[(size_t)l * L + 2 * k];
         if ((rc = c->arena.upload(psi, &S.psi))) return rc;
+        // unrotated: Psi~_{l,l} = sqrt((2l+1)/(8 pi^2)) kappa_j(l) zeta~_{l,l}, zeta~_{l,l} = 1/sqrt 2
+        std::vector<double> psi2(Lj);
+        for (int l = 0; l < Lj; ++l)
+            psi2[l] = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) * kj[l] / std::sqrt(2.0);
+        if ((rc = c->arena.upload(psi2, &S.psi2))) return rc;
         if ((rc = get_beta(c, Lj, 0, &S.beta))) return rc;
         const int Nm = 2 * Lj - 1;
         if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full))) return rc;
@@ -665,7 +673,8 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
     if (rc) return rc;
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision);
+    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision,
+                               (p->flags & CVL_UNROTATED) != 0);
     return CVL_OK;
 }
 
@@ -857,7 +866,8 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
     if (!a || !b || !grids || !ws) return fail(CVL_EINVAL, "NULL pointer argument");
     if ((rc = set_device(ctx))) return rc;
     if ((rc = get_plan(ctx, p, P))) return rc;
-    const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, p->precision);
+    const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, p->precision,
+                                          (p->flags & CVL_UNROTATED) != 0);
     if (ws_bytes < need)
         return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -874,9 +884,10 @@ struct CurveletBufs {
     cd *sfacc;        // harmonic accumulator of the side scales' synthesis
 };
 
-static CurveletBufs carve_curvelet(const Plan *P, int precision, void *ws, size_t ws_bytes) {
+static CurveletBufs carve_curvelet(const Plan *P, int precision, bool unrot, void *ws,
+                                   size_t ws_bytes) {
     size_t b0, b1, sb0, sb1;
-    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, &b0, &b1, &sb0, &sb1);
+    curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, unrot, &b0, &b1, &sb0, &sb1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     Carver cv{(char *)ws, ws_bytes};
     CurveletBufs B;
@@ -905,15 +916,72 @@ static CurveletBufs side_bufs(const CurveletBufs &B) {
 }
 
 static bool real_grids(const cvl_params *p) { return (p->flags & CVL_REAL_GRIDS) != 0; }
+static bool unrotated(const cvl_params *p) { return (p->flags & CVL_UNROTATED) != 0; }
+
+// Analysis of one scale of the unrotated curvelets (same buffers and stages
+// as the rotated one, on the unrotated cube layout).
+extern "C++" {
+template <class C, class G, class BT>
+static int unrot_analysis_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                            const BT &full, const BT &beta_inv, const CurveletBufs &B, G *grid,
+                            hipStream_t st) {
+    const ScaleGeom &g = S.g;
+    C *b0 = (C *)B.b0, *b1 = (C *)B.b1;
+    LAUNCH(ST_CONTRACT_INV, launch_unrot_contract_inv(g, P->L, ctx->delta, B.fpad, S.psi2, b0, st));
+    const int ncols = 2 * g.L * g.Nep;
+    if (S.beta_fft)
+        LAUNCH(ST_BETA_INV, launch_unrot_inv_beta_dft(g, beta_inv, b0, b1, st));
+    else if (precision == CVL_FP64)
+        LAUNCH(ST_BETA_INV, launch_beta_gemm(g.L, g.L, ncols, g.Nep, 0, 0, S.beta.Cinv,
+                                             S.beta.Sinv, (const cd *)b0, (cd *)b1, st));
+    else
+        LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(precision, g.L, g.L, ncols, g.Nep, S.betaf.Cinv,
+                                                 S.betaf.Sinv, (const cf *)b0, (cf *)b1, st));
+    LAUNCH(ST_ALPHA_INV, launch_unrot_inv_alpha(g, full, b1, b0, st));
+    LAUNCH(ST_GAMMA_INV, launch_unrot_inv_gamma(g, full, b0, grid, st));
+    return CVL_OK;
+}
+
+template <class C, class G, class BT>
+static int unrot_synthesis_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                             const BT &full, const CurveletBufs &B, const G *grid,
+                             hipStream_t st) {
+    const ScaleGeom &g = S.g;
+    C *b0 = (C *)B.b0, *b1 = (C *)B.b1;
+    LAUNCH(ST_GAMMA_FWD, launch_unrot_fwd_gamma(g, full, grid, b0, st));
+    LAUNCH(ST_ALPHA_FWD, launch_unrot_fwd_alpha(g, full, b0, b1, st));
+    const int ncols = 2 * g.L * g.Nep;
+    if (precision == CVL_FP64)
+        LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, ncols, g.Nep, 0, 0, S.beta.Qp, S.beta.Qs,
+                                             (const cd *)b1, (cd *)b0, st));
+    else
+        LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(precision, g.L, g.L, ncols, g.Nep, S.betaf.Qp,
+                                                 S.betaf.Qs, (const cf *)b1, (cf *)b0, st));
+    LAUNCH(ST_CONTRACT_FWD,
+           launch_unrot_contract_fwd(g, P->L, ctx->delta, (const C *)b0, S.psi2, B.facc, st));
+    return CVL_OK;
+}
+}  // extern "C++"
 
 // Analysis of one scale from the padded harmonic coefficients B.fpad into a
 // complex (zero imaginary parts) or, with real_grid, a real grid.
 static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
-                              bool real_grid, const CurveletBufs &B, void *grid_out,
+                              bool real_grid, bool unrot, const CurveletBufs &B, void *grid_out,
                               hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
     TagScope tag(g.L);
+    if (unrot) {
+        if (precision == CVL_FP64)
+            return real_grid ? unrot_analysis_t<cd>(ctx, P, S, precision, S.inv_full, S.beta_inv, B,
+                                                    (double *)grid_out, st)
+                             : unrot_analysis_t<cd>(ctx, P, S, precision, S.inv_full, S.beta_inv, B,
+                                                    (cd *)grid_out, st);
+        return real_grid ? unrot_analysis_t<cf>(ctx, P, S, precision, S.inv_full_f, S.beta_inv_f, B,
+                                                (float *)grid_out, st)
+                         : unrot_analysis_t<cf>(ctx, P, S, precision, S.inv_full_f, S.beta_inv_f, B,
+                                                (cf *)grid_out, st);
+    }
     if (precision != CVL_FP64) {
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         LAUNCH(ST_CONTRACT_INV,
@@ -948,11 +1016,22 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
 // Synthesis of one scale (real parts of a complex grid, or a real grid): adds
 // f^(j)_lm into the padded accumulator B.facc.
 static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
-                               bool real_grid, const CurveletBufs &B, const void *grid_in,
-                               hipStream_t st) {
+                               bool real_grid, bool unrot, const CurveletBufs &B,
+                               const void *grid_in, hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
     TagScope tag(g.L);
+    if (unrot) {
+        if (precision == CVL_FP64)
+            return real_grid ? unrot_synthesis_t<cd>(ctx, P, S, precision, S.fwd_full, B,
+                                                     (const double *)grid_in, st)
+                             : unrot_synthesis_t<cd>(ctx, P, S, precision, S.fwd_full, B,
+                                                     (const cd *)grid_in, st);
+        return real_grid ? unrot_synthesis_t<cf>(ctx, P, S, precision, S.fwd_full_f, B,
+                                                 (const float *)grid_in, st)
+                         : unrot_synthesis_t<cf>(ctx, P, S, precision, S.fwd_full_f, B,
+                                                 (const cf *)grid_in, st);
+    }
     if (precision != CVL_FP64) {
         cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
         const BluesteinF &F = S.fwd_full_f;
@@ -1031,7 +1110,8 @@ static int analysis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
                            const CurveletBufs &B, void *const *grids, int s0, int s1,
                            hipStream_t st) {
     for (int s = s0; s < s1; ++s) {
-        int rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
+        int rc = analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p),
+                                    unrotated(p), B,
                                     grids[s], st);
         if (rc) return rc;
     }
@@ -1044,7 +1124,8 @@ static int synthesis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
                             hipStream_t st) {
     LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)P->L * P->L, st));
     for (int s = s0; s < s1; ++s) {
-        int rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B,
+        int rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p),
+                                     unrotated(p), B,
                                      grids[s], st);
         if (rc) return rc;
     }
@@ -1063,7 +1144,7 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
     const CurveletBufs BS = side_bufs(B);
     const int L = P->L, Lp = P->Lphi, nside = side_count(P);
     cvl_ctx::Side *sd = nullptr;
@@ -1099,7 +1180,7 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
         if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
     const CurveletBufs BS = side_bufs(B);
     const int L = P->L, Lp = P->Lphi, nside = side_count(P);
     cvl_ctx::Side *sd = nullptr;
@@ -1141,9 +1222,10 @@ int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const 
     int s, rc = check_scale_call(ctx, p, j, flm, grid, ws, ws_bytes, &P, &s);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
     LAUNCH(ST_MISC, launch_flm_pack(P->L, (const cd *)flm, B.fpad, st));
-    return analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B, grid, st);
+    return analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), unrotated(p), B,
+                              grid, st);
 }
 
 int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const void *grid,
@@ -1153,10 +1235,12 @@ int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const
     int s, rc = check_scale_call(ctx, p, j, grid, flm_acc, ws, ws_bytes, &P, &s);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
     const int L = P->L;
     LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
-    if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), B, grid, st))) return rc;
+    if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), unrotated(p),
+                                  B, grid, st)))
+        return rc;
     LAUNCH(ST_MISC, launch_flm_unpack(L, B.facc, (cd *)flm_acc, 1, st));
     return CVL_OK;
 }
@@ -1169,7 +1253,7 @@ int cvl_curvelet_scaling_analysis(cvl_ctx *ctx, const cvl_params *p, const cvl_c
     if (rc) return rc;
     ShtRt *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
     const int L = P->L, Lp = P->Lphi;
     LAUNCH(ST_MISC, launch_flm_pack(L, (const cd *)flm, B.fpad, st));
     LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
@@ -1184,7 +1268,7 @@ int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p, const doub
     if (rc) return rc;
     ShtRt *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
     const int L = P->L, Lp = P->Lphi;
     if ((rc = sht_forward_run(ctx, SP, scal_map, B.fphi, Lp, B.s0, B.s1, st))) return rc;
     LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));

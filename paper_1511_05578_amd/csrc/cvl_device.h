@@ -104,6 +104,24 @@ struct ScaleGeom {
     int llo, lhi;  // l range where the curvelet kernel is non-zero (inclusive)
 };
 
+// Cube of the unrotated curvelets (Sec. III-A-1: kernel coefficients only at
+// |n| = l, so every n in (-L, L) occurs): m >= 0 only (the reality condition
+// gives m < 0), element (m, n) in row 2m + ((m + n) & 1), so that each row
+// has one parity of m + n (the parity of the beta extension), at the column
+// of n within its parity class: h + n/2 for even n, L/2 + (n - 1)/2 (floor)
+// for odd n.  Row length Nep (>= both class sizes), 2L rows per plane.
+__host__ __device__ __forceinline__ int unrot_col(const ScaleGeom &g, int n) {
+    return (n & 1) ? (g.L >> 1) + ((n - 1) >> 1) : g.h + (n >> 1);
+}
+__host__ __device__ __forceinline__ size_t unrot_off(const ScaleGeom &g, int m, int n) {
+    return (size_t)(2 * m + ((m + n) & 1)) * g.Nep + unrot_col(g, n);
+}
+// Columns in use in an unrotated-cube row: max(2h + 1, 2 (L/2)).
+__host__ __device__ __forceinline__ int unrot_cols(const ScaleGeom &g) {
+    const int e = 2 * g.h + 1, o = 2 * (g.L >> 1);
+    return e > o ? e : o;
+}
+
 // ---- launch wrappers (defined in the .hip files) ----
 hipError_t launch_delta_toprows(double *tab, int Lmax, hipStream_t st);
 hipError_t launch_delta_fill(double *tab, int Lmax, hipStream_t st);
@@ -184,6 +202,46 @@ hipError_t launch_contract_fwd(const ScaleGeom &g, const double *delta, const cd
                                const double *psi, cd *part, hipStream_t st);
 hipError_t launch_reduce_fwd(const ScaleGeom &g, int Lf, const cd *part, int ngroups,
                              cd *facc, hipStream_t st);
+
+// Unrotated curvelets: the stages on the unrotated cube layout (unrot_off).
+// W2 / V1 planes: [b][a][n], n in [0, L) (n < 0 by the reality condition).
+// psi2[l] = Psi~_{l,l} (Psi~_{l,-l} = (-1)^l psi2[l], zero for other n).
+hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cd *fpad, const double *psi2, cd *X, hipStream_t st);
+hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cd *fpad, const double *psi2, cf *X, hipStream_t st);
+hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cd *Y, const double *psi2, cd *facc, hipStream_t st);
+hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cf *Y, const double *psi2, cd *facc, hipStream_t st);
+hipError_t launch_unrot_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const cd *X,
+                                     cd *W1, hipStream_t st);
+hipError_t launch_unrot_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X,
+                                     cf *W1, hipStream_t st);
+hipError_t launch_unrot_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
+                                  cd *W2, hipStream_t st);
+hipError_t launch_unrot_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1,
+                                  cf *W2, hipStream_t st);
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                                  cd *grid, hipStream_t st);
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                                  double *grid, hipStream_t st);
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
+                                  cf *grid, hipStream_t st);
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
+                                  float *grid, hipStream_t st);
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                                  cd *V1, hipStream_t st);
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B,
+                                  const double *grid, cd *V1, hipStream_t st);
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid,
+                                  cf *V1, hipStream_t st);
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const float *grid,
+                                  cf *V1, hipStream_t st);
+hipError_t launch_unrot_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
+                                  cd *V2, hipStream_t st);
+hipError_t launch_unrot_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1,
+                                  cf *V2, hipStream_t st);
 
 // General Wigner contractions (dense F^l_mn).
 hipError_t launch_gen_contract_inv(int L, int N, const double *delta, const cd *F,

@@ -838,6 +838,8 @@ struct FwdAlphaIO {
 // -beta (k' -> -k'):  W1_e(beta) = (Z(beta) + Z(-beta))/2,
 // W1_o(beta) = (Z(beta) - Z(-beta))/2, stored for b = L-1-k, k = 0..L-1.
 // X, W1: [row][m][nn] with row m' (input) or b (output), row length L*Nep.
+// The unrotated cube (2L rows of alternating parity per plane) is transformed
+// by the same pairs: `rows` cube rows per plane, plane stride `plane`.
 template <class C_>
 struct BetaInvPairIO {
     using C = C_;
@@ -845,7 +847,8 @@ struct BetaInvPairIO {
     static constexpr int kBatch = 8;  // two loads per element
     const C *X;
     C *W1;
-    int L, Ne, Nep;
+    int L, Ne, Nep, rows;
+    size_t plane;
     struct Ctx {
         const C *xe, *xo;  // X[0][2p][nn], X[0][2p+1][nn]
         C *we, *wo;        // W1[0][2p][nn], W1[0][2p+1][nn] (wo null past the last m)
@@ -856,22 +859,201 @@ struct BetaInvPairIO {
         const int me = 2 * p, mo = 2 * p + 1;
         const size_t oe = (size_t)me * Nep + nn, oo = (size_t)mo * Nep + nn;
         // a lone last (even) m reads its own row as the odd partner, weighted 0
-        return Ctx{X + oe, X + (mo < L ? oo : oe), W1 + oe, mo < L ? W1 + oo : nullptr,
-                   (real_t<C>)(mo < L ? 1 : 0)};
+        return Ctx{X + oe, X + (mo < rows ? oo : oe), W1 + oe, mo < rows ? W1 + oo : nullptr,
+                   (real_t<C>)(mo < rows ? 1 : 0)};
     }
     __device__ C load(const Ctx &c, int j) const {
         const int mp = j < 0 ? -j : j;
-        const size_t row = (size_t)mp * L * Nep;
+        const size_t row = (size_t)mp * plane;
         const C e = c.xe[row], o = c.xo[row];
         const real_t<C> se = (mp & 1) ? -1 : 1;
         const real_t<C> so = (j < 0 ? -c.wo_on : c.wo_on) * se;
         return C{se * e.x + so * o.x, se * e.y + so * o.y};
     }
     __device__ void store_pair(const Ctx &c, int k, C zk, C zmk) const {
-        const size_t row = (size_t)(L - 1 - k) * L * Nep;  // b = L-1-k: Z(beta_b) = zmk
+        const size_t row = (size_t)(L - 1 - k) * plane;  // b = L-1-k: Z(beta_b) = zmk
         const real_t<C> h = (real_t<C>)0.5;
         c.we[row] = C{(zmk.x + zk.x) * h, (zmk.y + zk.y) * h};
         if (c.wo) c.wo[row] = C{(zmk.x - zk.x) * h, (zmk.y - zk.y) * h};
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Unrotated curvelets (every n in (-L, L)).  Cube rows per unrot_off; W2 and
+// V1 planes [b][a][n] with n in [0, L): the grid is real, so the coefficient
+// of -n is the conjugate of that of n, and the cube of m < 0 follows from
+// W1(b, -m, -n) = conj W1(b, m, n).
+// ---------------------------------------------------------------------------
+
+// alpha DFT of the analysis: line (b, n >= 0), input m in (-L, L), output a.
+template <class C_>
+struct UnrotInvAlphaIO {
+    using C = C_;
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const C *W1;
+    C *W2;
+    ScaleGeom g;
+    struct Ctx {
+        const C *plane;  // W1[b]
+        C *out;          // W2[b][0][n]
+        int n;
+    };
+    __device__ Ctx at(int line) const {
+        const int b = line / g.L, n = line % g.L;
+        return Ctx{W1 + (size_t)b * 2 * g.L * g.Nep, W2 + (size_t)b * g.Nm * g.L + n, n};
+    }
+    __device__ C load(const Ctx &c, int m) const {
+        const bool pos = m >= 0;
+        const C v = c.plane[pos ? unrot_off(g, m, c.n) : unrot_off(g, -m, -c.n)];
+        return C{v.x, pos ? v.y : -v.y};
+    }
+    __device__ void store(const Ctx &c, int a, C v) const { c.out[(size_t)a * g.L] = v; }
+};
+
+// gamma DFT of the analysis, one real line (a, b) of the grid.
+template <class C_, class G>
+struct UnrotInvGammaIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const C *W2;
+    G *grid;
+    int L, Nm;
+    struct Ctx {
+        const C *src;
+        G *dst;
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        return Ctx{W2 + ((size_t)b * Nm + a) * L, grid + (size_t)line * Nm};
+    }
+    __device__ C load(const Ctx &c, int n) const {
+        const C v = c.src[n < 0 ? -n : n];
+        return C{v.x, n < 0 ? -v.y : v.y};
+    }
+    __device__ void store(const Ctx &c, int g, C v) const { grid_put(c.dst + g, v.x); }
+};
+
+// gamma DFT of the analysis, two real lines (2p, 2p+1) per complex transform
+// (z_n = c1_n + i c2_n; real part to line 2p, imaginary part to line 2p+1).
+template <class C_, class G>
+struct UnrotInvGammaPackIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 8;  // two loads per element
+    const C *W2;
+    G *grid;
+    int L, Nm, nreal;
+    struct Ctx {
+        const C *s1, *s2;
+        G *d1, *d2;
+        bool two;
+    };
+    __device__ Ctx at(int p) const {
+        const int l1 = 2 * p, l2 = 2 * p + 1;
+        const bool two = l2 < nreal;
+        const int a1 = l1 / L, b1 = l1 % L;
+        const int a2 = two ? l2 / L : a1, b2 = two ? l2 % L : b1;
+        return Ctx{W2 + ((size_t)b1 * Nm + a1) * L, W2 + ((size_t)b2 * Nm + a2) * L,
+                   grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm, two};
+    }
+    __device__ C load(const Ctx &c, int n) const {
+        // s2 is a valid pointer even for a lone last line (it then repeats s1)
+        const int k = n < 0 ? -n : n;
+        const C c1 = c.s1[k], c2 = c.s2[k];
+        const real_t<C> w2 = c.two ? 1 : 0;   // no second line: zero
+        const real_t<C> sg = n < 0 ? -1 : 1;  // conjugate both for n < 0
+        return C{c1.x - sg * w2 * c2.y, sg * c1.y + w2 * c2.x};
+    }
+    __device__ void store(const Ctx &c, int g, C v) const {
+        grid_put(c.d1 + g, v.x);
+        if (c.two) grid_put(c.d2 + g, v.y);
+    }
+};
+
+// gamma DFT of the synthesis on line (a, b) of the real grid: n >= 0 kept.
+template <class C_, class G>
+struct UnrotFwdGammaIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const G *grid;
+    C *V1;
+    int L, Nm;
+    struct Ctx {
+        const G *src;
+        C *dst;  // V1[b][a][0]
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        return Ctx{grid + (size_t)line * Nm, V1 + ((size_t)b * Nm + a) * L};
+    }
+    __device__ C load(const Ctx &c, int g) const { return C{grid_get(c.src + g), 0}; }
+    __device__ void store(const Ctx &c, int n, C v) const {
+        if (n >= 0) c.dst[n] = v;
+    }
+};
+
+// gamma DFT of the synthesis, real lines (2p, 2p+1) packed as z = w1 + i w2
+// and separated as c1_n = (Z_n + conj Z_-n)/2, c2_n = (Z_n - conj Z_-n)/(2i).
+template <class C_, class G>
+struct UnrotFwdGammaPackIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const G *grid;
+    C *V1;
+    int L, Nm, nreal;
+    struct Ctx {
+        const G *s1, *s2;
+        C *d1, *d2;  // V1[b][a][0] of both lines
+        bool two;
+    };
+    __device__ Ctx at(int p) const {
+        const int l1 = 2 * p, l2 = 2 * p + 1;
+        const bool two = l2 < nreal;
+        const int a1 = l1 / L, b1 = l1 % L;
+        const int a2 = two ? l2 / L : a1, b2 = two ? l2 % L : b1;
+        return Ctx{grid + (size_t)l1 * Nm, grid + (size_t)(two ? l2 : l1) * Nm,
+                   V1 + ((size_t)b1 * Nm + a1) * L, V1 + ((size_t)b2 * Nm + a2) * L, two};
+    }
+    __device__ C load(const Ctx &c, int g) const {
+        // s2 is a valid pointer even for a lone last line (it then repeats s1)
+        const real_t<C> a = grid_get(c.s1 + g), b = grid_get(c.s2 + g);
+        return C{a, (real_t<C>)(c.two ? 1 : 0) * b};
+    }
+    __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
+        const C czm = cconj(zmn);
+        const C s = cadd(zn, czm), d = csub(zn, czm);
+        c.d1[n] = C{s.x * (real_t<C>)0.5, s.y * (real_t<C>)0.5};
+        if (c.two) c.d2[n] = C{d.y * (real_t<C>)0.5, d.x * (real_t<C>)-0.5};
+    }
+};
+
+// alpha DFT of the synthesis: line (b, n >= 0), all m in (-L, L); m >= 0 to
+// (m, n), m <= 0 mirrored as conj to (-m, -n) (n > 0).
+template <class C_>
+struct UnrotFwdAlphaIO {
+    using C = C_;
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const C *V1;
+    C *V2;
+    ScaleGeom g;
+    struct Ctx {
+        const C *src;  // V1[b][0][n]
+        C *plane;      // V2[b]
+        int n;
+    };
+    __device__ Ctx at(int line) const {
+        const int b = line / g.L, n = line % g.L;
+        return Ctx{V1 + (size_t)b * g.Nm * g.L + n, V2 + (size_t)b * 2 * g.L * g.Nep, n};
+    }
+    __device__ C load(const Ctx &c, int a) const { return c.src[(size_t)a * g.L]; }
+    __device__ void store(const Ctx &c, int m, C v) const {
+        if (m >= 0) c.plane[unrot_off(g, m, c.n)] = v;
+        if (m <= 0 && c.n > 0) c.plane[unrot_off(g, -m, -c.n)] = cconj(v);
     }
 };
 
@@ -948,7 +1130,7 @@ static hipError_t fwd_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *V1
 template <class C>
 static hipError_t inv_beta_t(const ScaleGeom &g, const BlueT<C> &B, const C *X, C *W1,
                              hipStream_t st) {
-    BetaInvPairIO<C> io{X, W1, g.L, g.Ne, g.Nep};
+    BetaInvPairIO<C> io{X, W1, g.L, g.Ne, g.Nep, g.L, (size_t)g.L * g.Nep};
     return run_bluestein(io, ((g.L + 1) / 2) * g.Ne, B, st);
 }
 hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const cd *X, cd *W1,
@@ -1008,6 +1190,105 @@ hipError_t launch_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V
                             hipStream_t st) {
     return fwd_alpha_t(g, B, V1, V2, st);
 }
+// ---- unrotated curvelet stages ----
+template <class C>
+static hipError_t unrot_inv_beta_t(const ScaleGeom &g, const BlueT<C> &B, const C *X, C *W1,
+                                   hipStream_t st) {
+    const int ne = unrot_cols(g);
+    BetaInvPairIO<C> io{X, W1, g.L, ne, g.Nep, 2 * g.L, (size_t)2 * g.L * g.Nep};
+    return run_bluestein(io, g.L * ne, B, st);
+}
+template <class C>
+static hipError_t unrot_inv_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *W1, C *W2,
+                                    hipStream_t st) {
+    UnrotInvAlphaIO<C> io{W1, W2, g};
+    return run_bluestein(io, g.L * g.L, B, st);
+}
+template <class C, class G>
+static hipError_t unrot_inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2, G *grid,
+                                    hipStream_t st) {
+    const int nreal = g.Nm * g.L;
+    if (B.P >= 256) {
+        UnrotInvGammaPackIO<C, G> io{W2, grid, g.L, g.Nm, nreal};
+        return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
+    }
+    UnrotInvGammaIO<C, G> io{W2, grid, g.L, g.Nm};
+    return run_bluestein(io, nreal, B, st);
+}
+template <class C, class G>
+static hipError_t unrot_fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const G *grid, C *V1,
+                                    hipStream_t st) {
+    const int nreal = g.Nm * g.L;
+    if (B.P >= 256) {
+        UnrotFwdGammaPackIO<C, G> io{grid, V1, g.L, g.Nm, nreal};
+        return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
+    }
+    UnrotFwdGammaIO<C, G> io{grid, V1, g.L, g.Nm};
+    return run_bluestein(io, nreal, B, st);
+}
+template <class C>
+static hipError_t unrot_fwd_alpha_t(const ScaleGeom &g, const BlueT<C> &B, const C *V1, C *V2,
+                                    hipStream_t st) {
+    UnrotFwdAlphaIO<C> io{V1, V2, g};
+    return run_bluestein(io, g.L * g.L, B, st);
+}
+hipError_t launch_unrot_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const cd *X,
+                                     cd *W1, hipStream_t st) {
+    return unrot_inv_beta_t(g, B, X, W1, st);
+}
+hipError_t launch_unrot_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X,
+                                     cf *W1, hipStream_t st) {
+    return unrot_inv_beta_t(g, B, X, W1, st);
+}
+hipError_t launch_unrot_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1,
+                                  cd *W2, hipStream_t st) {
+    return unrot_inv_alpha_t(g, B, W1, W2, st);
+}
+hipError_t launch_unrot_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1,
+                                  cf *W2, hipStream_t st) {
+    return unrot_inv_alpha_t(g, B, W1, W2, st);
+}
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                                  cd *grid, hipStream_t st) {
+    return unrot_inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *W2,
+                                  double *grid, hipStream_t st) {
+    return unrot_inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
+                                  cf *grid, hipStream_t st) {
+    return unrot_inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_unrot_inv_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *W2,
+                                  float *grid, hipStream_t st) {
+    return unrot_inv_gamma_t(g, B, W2, grid, st);
+}
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                                  cd *V1, hipStream_t st) {
+    return unrot_fwd_gamma_t(g, B, grid, V1, st);
+}
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinDev &B,
+                                  const double *grid, cd *V1, hipStream_t st) {
+    return unrot_fwd_gamma_t(g, B, grid, V1, st);
+}
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const cf *grid,
+                                  cf *V1, hipStream_t st) {
+    return unrot_fwd_gamma_t(g, B, grid, V1, st);
+}
+hipError_t launch_unrot_fwd_gamma(const ScaleGeom &g, const BluesteinF &B, const float *grid,
+                                  cf *V1, hipStream_t st) {
+    return unrot_fwd_gamma_t(g, B, grid, V1, st);
+}
+hipError_t launch_unrot_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *V1,
+                                  cd *V2, hipStream_t st) {
+    return unrot_fwd_alpha_t(g, B, V1, V2, st);
+}
+hipError_t launch_unrot_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1,
+                                  cf *V2, hipStream_t st) {
+    return unrot_fwd_alpha_t(g, B, V1, V2, st);
+}
+
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,
                               hipStream_t st) {
     ShtInvPhiIO io{G, map, L, 2 * L - 1};

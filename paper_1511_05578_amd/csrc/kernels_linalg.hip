@@ -641,6 +641,132 @@ hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int 
 }
 
 // ---------------------------------------------------------------------------
+// Unrotated curvelets (Sec. III-A-1): the kernel Psi~_ln is zero unless
+// |n| = l, so each Fourier-cube entry takes one l and the contractions are
+// O(L^3) per scale.  psi2[l] = Psi~_{l,l}; Psi~_{l,-l} = (-1)^l psi2[l];
+// Delta^l_{m',-l} = (-1)^(l+m') Delta^l_{m',l}.
+//
+// Analysis: X[m'][m][n] = i^(n-m) s Delta^l_{m'm} Delta^l_{m'l} f_lm psi2[l],
+// l = |n|, s = (-1)^m' for n < 0 (the two signs above), zero unless
+// max(m, m') <= l and l is in the kernel support; every cube entry is written
+// (zeros included, unused columns too).  One thread per entry, a plane m' per
+// run of work-groups (xcd_group keeps a plane's Delta rows in one L2).
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(256) void k_unrot_contract_inv(ScaleGeom g, int Lf,
+                                                            const double *__restrict__ delta,
+                                                            const cd *__restrict__ fpad,
+                                                            const double *__restrict__ psi2,
+                                                            C *__restrict__ X, int nbx) {
+    const int lg = xcd_group(blockIdx.x, gridDim.x);
+    const int mp = lg / nbx;
+    const int idx = (lg % nbx) * 256 + threadIdx.x;
+    const int L = g.L, Nep = g.Nep;
+    if (idx >= 2 * L * Nep) return;
+    const int rho = idx / Nep, c = idx % Nep;
+    const int m = rho >> 1, pn = ((rho & 1) + m) & 1;  // parity of n
+    const int ho = L >> 1;
+    cd out = cd{0.0, 0.0};
+    if (pn ? c < 2 * ho : c <= 2 * g.h) {
+        const int n = pn ? 2 * (c - ho) + 1 : 2 * (c - g.h);
+        const int l = n < 0 ? -n : n;
+        if (m <= l && mp <= l && l >= g.llo && l <= g.lhi) {
+            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            double w = row[m] * row[l] * psi2[l];
+            if (n < 0 && (mp & 1)) w = -w;
+            const cd f = fpad[(size_t)l * Lf + m];
+            out = ipow(cd{w * f.x, w * f.y}, n - m);
+        }
+    }
+    X[((size_t)mp * 2 * L + rho) * Nep + c] = cmk<C>(out.x, out.y);
+}
+
+template <class C>
+static hipError_t unrot_contract_inv_t(const ScaleGeom &g, int Lf, const double *delta,
+                                       const cd *fpad, const double *psi2, C *X, hipStream_t st) {
+    const int nbx = (2 * g.L * g.Nep + 255) / 256;
+    hipLaunchKernelGGL(k_unrot_contract_inv<C>, dim3(nbx * g.L), dim3(256), 0, st, g, Lf, delta,
+                       fpad, psi2, X, nbx);
+    return hipGetLastError();
+}
+hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cd *fpad, const double *psi2, cd *X, hipStream_t st) {
+    return unrot_contract_inv_t(g, Lf, delta, fpad, psi2, X, st);
+}
+hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cd *fpad, const double *psi2, cf *X, hipStream_t st) {
+    return unrot_contract_inv_t(g, Lf, delta, fpad, psi2, X, st);
+}
+
+// Synthesis: with Y the beta-projected cube (m' >= 0, the -m' half folded in),
+//   F~^l_{m,+-l} = i^(m-+l) sum_{m'<=l} Delta^l_{m'm} Delta^l_{m',+-l} Y[m'][m][+-l]
+// and f_lm = psi2[l] (F~^l_{m,l} + (-1)^l F~^l_{m,-l}), i.e.
+//   facc[l][m] += psi2[l] i^(m-l) sum_{m'<=l} Delta^l_{m'm} Delta^l_{m'l}
+//                 (Y[m'][m][l] + (-1)^(l+m') Y[m'][m][-l])      (n = 0 once).
+// Work-group: one m, 64 consecutive l (lanes), the m' sum split over the four
+// waves (m' = w mod 4) and added in LDS in wave order, in FP64.  Y[.][m][+-l]
+// of neighbouring l sit in two cube rows (one per parity), so the loads of a
+// wave touch few cache lines.
+template <class C>
+__global__ __launch_bounds__(256) void k_unrot_contract_fwd(ScaleGeom g, int Lf,
+                                                            const double *__restrict__ delta,
+                                                            const C *__restrict__ Y,
+                                                            const double *__restrict__ psi2,
+                                                            cd *__restrict__ facc) {
+    __shared__ double red[4][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = blockIdx.y;
+    const int l = blockIdx.x * 64 + lane;
+    const int L = g.L;
+    const bool live = l < L && l >= m && l >= g.llo && l <= g.lhi;
+    double sx = 0.0, sy = 0.0;
+    if (live) {
+        const size_t plane = (size_t)2 * L * g.Nep;
+        const C *yp = Y + unrot_off(g, m, l);
+        const C *ym = Y + unrot_off(g, m, -l);
+        const double *blk = delta + delta_off(l);
+        const double both = l > 0 ? 1.0 : 0.0;
+        for (int mp = w; mp <= l; mp += 4) {
+            const double *row = blk + (int64_t)mp * (l + 1);
+            const double d = row[m] * row[l];
+            const C a = yp[mp * plane], b = ym[mp * plane];
+            const double sb = ((l + mp) & 1) ? -both : both;
+            sx += d * ((double)a.x + sb * (double)b.x);
+            sy += d * ((double)a.y + sb * (double)b.y);
+        }
+    }
+    red[w][lane][0] = sx;
+    red[w][lane][1] = sy;
+    __syncthreads();
+    if (w == 0 && live) {
+        double tx = red[0][lane][0], ty = red[0][lane][1];
+        for (int q = 1; q < 4; ++q) {
+            tx += red[q][lane][0];
+            ty += red[q][lane][1];
+        }
+        const double ps = psi2[l];
+        cd *o = facc + (size_t)l * Lf + m;
+        *o = cadd(*o, ipow(cd{ps * tx, ps * ty}, m - l));
+    }
+}
+
+template <class C>
+static hipError_t unrot_contract_fwd_t(const ScaleGeom &g, int Lf, const double *delta,
+                                       const C *Y, const double *psi2, cd *facc, hipStream_t st) {
+    hipLaunchKernelGGL(k_unrot_contract_fwd<C>, dim3((g.L + 63) / 64, g.L), dim3(256), 0, st, g,
+                       Lf, delta, Y, psi2, facc);
+    return hipGetLastError();
+}
+hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cd *Y, const double *psi2, cd *facc, hipStream_t st) {
+    return unrot_contract_fwd_t(g, Lf, delta, Y, psi2, facc, st);
+}
+hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
+                                     const cf *Y, const double *psi2, cd *facc, hipStream_t st) {
+    return unrot_contract_fwd_t(g, Lf, delta, Y, psi2, facc, st);
+}
+
+// ---------------------------------------------------------------------------
 // General Wigner contractions (dense F^l_mn, any m, n).  Delta^l_{m',-k} =
 // (-1)^(l+m') Delta^l_{m',k}.  Layouts: F[l][m+L-1][n+N-1] (row 2N-1),
 // X / Z[m'][m+L-1][n+N-1] (row Nnp).

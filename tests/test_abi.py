@@ -62,7 +62,7 @@ def test_workspace_grows_with_L():
     (dict(L=32, J0=6), api.CVL_EINVAL),
     (dict(L=32, spin=2), api.CVL_EUNSUPPORTED),
     (dict(L=32, flags=0), api.CVL_EUNSUPPORTED),
-    (dict(L=32, flags=api.CVL_REAL | 4), api.CVL_EINVAL),
+    (dict(L=32, flags=api.CVL_REAL | 8), api.CVL_EINVAL),
 ])
 def test_parameter_validation(kw, code):
     L = kw.pop("L")
@@ -80,6 +80,17 @@ def test_real_grids_flag_accepted():
     J = ctypes.c_int(-7)
     assert api.lib.cvl_num_scales(ctypes.byref(p), ctypes.byref(J)) == api.CVL_OK
     assert J.value == 5
+
+
+def test_unrotated_flag_accepted_and_sizes_workspace():
+    p = api.params(32, unrotated=True)
+    assert p.flags == api.CVL_REAL | api.CVL_UNROTATED
+    J = ctypes.c_int(-7)
+    assert api.lib.cvl_num_scales(ctypes.byref(p), ctypes.byref(J)) == api.CVL_OK
+    assert J.value == 5
+    # the unrotated cube holds every n (2 L_j rows per plane): a larger workspace
+    for L in (32, 256):
+        assert api.workspace_bytes(L, unrotated=True) > api.workspace_bytes(L)
 
 
 def test_null_arguments_rejected():
