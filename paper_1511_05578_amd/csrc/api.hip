@@ -99,7 +99,7 @@ struct ScaleRt {
     int j;
     ScaleGeom g;
     double *psi;  // [l][k]: Psi^(j)_{l,2k}
-    double *psi2; // [l]: Psi~^(j)_{l,l} of the unrotated curvelets
+    double *pd;   // [m'][l]: Delta^l_{m'l} Psi~^(j)_{l,l} (unrotated curvelets)
     BetaTabs beta;
     BluesteinDev inv_full, fwd_full;
     BetaTabsF betaf;
@@ -450,11 +450,16 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
                 psi[(size_t)l * (h + 1) + k] = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) *
                                                kj[l] * std::sqrt(2.0) * acol[(size_t)l * L + 2 * k];
         if ((rc = c->arena.upload(psi, &S.psi))) return rc;
-        // unrotated: Psi~_{l,l} = sqrt((2l+1)/(8 pi^2)) kappa_j(l) zeta~_{l,l}, zeta~_{l,l} = 1/sqrt 2
-        std::vector<double> psi2(Lj);
-        for (int l = 0; l < Lj; ++l)
-            psi2[l] = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) * kj[l] / std::sqrt(2.0);
-        if ((rc = c->arena.upload(psi2, &S.psi2))) return rc;
+        // unrotated: Psi~_{l,l} = sqrt((2l+1)/(8 pi^2)) kappa_j(l) zeta~_{l,l},
+        // zeta~_{l,l} = 1/sqrt 2, times Delta^l_{m'l} (zero for m' > l)
+        std::vector<double> pd((size_t)Lj * Lj, 0.0);
+        for (int l = 0; l < Lj; ++l) {
+            const double ps = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) * kj[l] /
+                              std::sqrt(2.0);
+            for (int mp = 0; mp <= l; ++mp)
+                pd[(size_t)mp * Lj + l] = acol[(size_t)l * L + mp] * ps;
+        }
+        if ((rc = c->arena.upload(pd, &S.pd))) return rc;
         if ((rc = get_beta(c, Lj, 0, &S.beta))) return rc;
         const int Nm = 2 * Lj - 1;
         if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full))) return rc;
@@ -927,7 +932,8 @@ static int unrot_analysis_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int p
                             hipStream_t st) {
     const ScaleGeom &g = S.g;
     C *b0 = (C *)B.b0, *b1 = (C *)B.b1;
-    LAUNCH(ST_CONTRACT_INV, launch_unrot_contract_inv(g, P->L, ctx->delta, B.fpad, S.psi2, b0, st));
+    LAUNCH(ST_CONTRACT_INV,
+           launch_unrot_contract_inv(g, P->L, ctx->delta, B.fpad, S.pd, b0, !S.beta_fft, st));
     const int ncols = 2 * g.L * g.Nep;
     if (S.beta_fft)
         LAUNCH(ST_BETA_INV, launch_unrot_inv_beta_dft(g, beta_inv, b0, b1, st));
@@ -952,13 +958,13 @@ static int unrot_synthesis_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int 
     LAUNCH(ST_ALPHA_FWD, launch_unrot_fwd_alpha(g, full, b0, b1, st));
     const int ncols = 2 * g.L * g.Nep;
     if (precision == CVL_FP64)
-        LAUNCH(ST_BETA_FWD, launch_beta_gemm(g.L, g.L, ncols, g.Nep, 0, 0, S.beta.Qp, S.beta.Qs,
-                                             (const cd *)b1, (cd *)b0, st));
+        LAUNCH(ST_BETA_FWD, launch_beta_gemm_unrot_fwd(g, S.beta.Qp, S.beta.Qs, (const cd *)b1,
+                                                       (cd *)b0, st));
     else
         LAUNCH(ST_BETA_FWD, launch_beta_gemm_f32(precision, g.L, g.L, ncols, g.Nep, S.betaf.Qp,
                                                  S.betaf.Qs, (const cf *)b1, (cf *)b0, st));
     LAUNCH(ST_CONTRACT_FWD,
-           launch_unrot_contract_fwd(g, P->L, ctx->delta, (const C *)b0, S.psi2, B.facc, st));
+           launch_unrot_contract_fwd(g, P->L, ctx->delta, (const C *)b0, S.pd, B.facc, st));
     return CVL_OK;
 }
 }  // extern "C++"

@@ -184,6 +184,12 @@ hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0
                             const double *Aeven, const double *Aodd, const cd *in,
                             cd *out, hipStream_t st);
 
+// The same GEMM (FP64) for the synthesis cube of the unrotated curvelets
+// (2 L_j rows of Nep columns per plane): only the outputs at m' <= l, m <= l
+// (l = |n|) are computed, the others are left unwritten.
+hipError_t launch_beta_gemm_unrot_fwd(const ScaleGeom &g, const double *Aeven,
+                                     const double *Aodd, const cd *in, cd *out, hipStream_t st);
+
 // Reduced-precision dense stages (FP32 data; see kernels_mixed.hip).
 hipError_t launch_beta_gemm_f32(int mode, int M, int K, int ncols, int Nep, const float *Aeven,
                                 const float *Aodd, const cf *in, cf *out, hipStream_t st);
@@ -205,15 +211,20 @@ hipError_t launch_reduce_fwd(const ScaleGeom &g, int Lf, const cd *part, int ngr
 
 // Unrotated curvelets: the stages on the unrotated cube layout (unrot_off).
 // W2 / V1 planes: [b][a][n], n in [0, L) (n < 0 by the reality condition).
-// psi2[l] = Psi~_{l,l} (Psi~_{l,-l} = (-1)^l psi2[l], zero for other n).
+// pd[m'][l] = Delta^l_{m'l} Psi~_{l,l}, L_j x L_j (Psi~_{l,-l} = (-1)^l Psi~_{l,l},
+// zero for other n).
+// dense: write every cube entry (the beta GEMM reads them all); otherwise only
+// those with m <= l and m' <= l, the ones the beta FFT reads
 hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cd *fpad, const double *psi2, cd *X, hipStream_t st);
+                                     const cd *fpad, const double *pd, cd *X, bool dense,
+                                     hipStream_t st);
 hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cd *fpad, const double *psi2, cf *X, hipStream_t st);
+                                     const cd *fpad, const double *pd, cf *X, bool dense,
+                                     hipStream_t st);
 hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cd *Y, const double *psi2, cd *facc, hipStream_t st);
+                                     const cd *Y, const double *pd, cd *facc, hipStream_t st);
 hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cf *Y, const double *psi2, cd *facc, hipStream_t st);
+                                     const cf *Y, const double *pd, cd *facc, hipStream_t st);
 hipError_t launch_unrot_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const cd *X,
                                      cd *W1, hipStream_t st);
 hipError_t launch_unrot_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X,

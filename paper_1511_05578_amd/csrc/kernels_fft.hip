@@ -17,9 +17,20 @@
 // (STAGED through LDS so that global accesses stay coalesced).  Each policy
 // resolves a line to a context (base pointers) once; element accesses are then
 // plain offsets.
+#include <type_traits>
+#include <utility>
+
 #include "cvl_device.h"
 
 namespace cvl {
+
+// An IO policy may declare `bool live(int line)`: a line for which it returns
+// false is all zero on input and its output is never read, so a work-group of
+// the register engine whose lines are all dead returns at once.
+template <class T, class = void>
+struct HasLive : std::false_type {};
+template <class T>
+struct HasLive<T, std::void_t<decltype(std::declval<const T &>().live(0))>> : std::true_type {};
 
 // Output modes: IO_PAIR hands the policy output pairs (k, -k) of a symmetric
 // window, line by line; IO_STAGED_PAIR does the same with the work-group's
@@ -406,6 +417,11 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     R *smem_d = reinterpret_cast<R *>(smem_raw);
     const int li = threadIdx.x / T, tid = threadIdx.x % T;
     const int line0 = xcd_group(blockIdx.x, gridDim.x) * LINES;
+    if constexpr (HasLive<IO>::value) {
+        bool any = false;  // uniform over the work-group
+        for (int i = 0; i < LINES; ++i) any = any || (line0 + i < nlines && io.live(line0 + i));
+        if (!any) return;
+    }
     const int line = line0 + li;
     R *lds = smem_d + li * LW;
     // The chirp spectrum is read by every line between the two FFTs: one copy
@@ -904,11 +920,67 @@ struct UnrotInvAlphaIO {
         return Ctx{W1 + (size_t)b * 2 * g.L * g.Nep, W2 + (size_t)b * g.Nm * g.L + n, n};
     }
     __device__ C load(const Ctx &c, int m) const {
+        // W1(b, m, n) = 0 for |m| > |n| (every cube term has m <= l = |n|);
+        // those entries need not have been written
         const bool pos = m >= 0;
-        const C v = c.plane[pos ? unrot_off(g, m, c.n) : unrot_off(g, -m, -c.n)];
+        const bool nz = (pos ? m : -m) <= c.n;
+        const C v = nz ? c.plane[pos ? unrot_off(g, m, c.n) : unrot_off(g, -m, -c.n)] : C{0, 0};
         return C{v.x, pos ? v.y : -v.y};
     }
     __device__ void store(const Ctx &c, int a, C v) const { c.out[(size_t)a * g.L] = v; }
+};
+
+// beta DFT of the analysis on the unrotated cube (the pairing of
+// BetaInvPairIO: rows 2m and 2m + 1, the two parities of m + n, share a
+// column).  Only the structurally non-zero entries are read (m' <= l and
+// m <= l, l = |n|: the others are not written by the contraction); a line
+// whose two rows are both zero is dead, and its output is never read.
+template <class C_>
+struct UnrotBetaInvPairIO {
+    using C = C_;
+    static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED_PAIR;
+    static constexpr int kBatch = 8;  // two loads per element
+    const C *X;
+    C *W1;
+    ScaleGeom g;
+    int ne;  // columns in use per row
+    struct Ctx {
+        const C *xe, *xo;  // X[0][2m][nn], X[0][2m+1][nn]
+        C *we, *wo;
+        int ke, ko;        // largest m' with a non-zero entry in each row, or -1
+    };
+    // l = |n| of column nn in row (m, s) when that entry can be non-zero, else -1
+    __device__ int lim(int m, int s, int nn) const {
+        const int pn = (s + m) & 1, ho = g.L >> 1;
+        if (pn ? nn >= 2 * ho : nn > 2 * g.h) return -1;
+        const int n = pn ? 2 * (nn - ho) + 1 : 2 * (nn - g.h);
+        const int l = n < 0 ? -n : n;
+        return m <= l ? l : -1;
+    }
+    __device__ bool live(int line) const {
+        const int m = line / ne, nn = line % ne;
+        return lim(m, 0, nn) >= 0 || lim(m, 1, nn) >= 0;
+    }
+    __device__ Ctx at(int line) const {
+        const int m = line / ne, nn = line % ne;
+        const size_t oe = (size_t)2 * m * g.Nep + nn, oo = oe + g.Nep;
+        return Ctx{X + oe, X + oo, W1 + oe, W1 + oo, lim(m, 0, nn), lim(m, 1, nn)};
+    }
+    __device__ C load(const Ctx &c, int j) const {
+        const int mp = j < 0 ? -j : j;
+        const size_t row = (size_t)mp * 2 * g.L * g.Nep;
+        const C e = mp <= c.ke ? c.xe[row] : C{0, 0};
+        const C o = mp <= c.ko ? c.xo[row] : C{0, 0};
+        const real_t<C> se = (mp & 1) ? -1 : 1;
+        const real_t<C> so = j < 0 ? -se : se;
+        return C{se * e.x + so * o.x, se * e.y + so * o.y};
+    }
+    __device__ void store_pair(const Ctx &c, int k, C zk, C zmk) const {
+        const size_t row = (size_t)(g.L - 1 - k) * 2 * g.L * g.Nep;  // b = L-1-k
+        const real_t<C> h = (real_t<C>)0.5;
+        c.we[row] = C{(zmk.x + zk.x) * h, (zmk.y + zk.y) * h};
+        c.wo[row] = C{(zmk.x - zk.x) * h, (zmk.y - zk.y) * h};
+    }
 };
 
 // gamma DFT of the analysis, one real line (a, b) of the grid.
@@ -1051,9 +1123,11 @@ struct UnrotFwdAlphaIO {
         return Ctx{V1 + (size_t)b * g.Nm * g.L + n, V2 + (size_t)b * 2 * g.L * g.Nep, n};
     }
     __device__ C load(const Ctx &c, int a) const { return c.src[(size_t)a * g.L]; }
+    // only |m| <= |n| is stored: the synthesis contraction reads (m, +-l) with
+    // m <= l, and the beta GEMM between keeps columns apart
     __device__ void store(const Ctx &c, int m, C v) const {
-        if (m >= 0) c.plane[unrot_off(g, m, c.n)] = v;
-        if (m <= 0 && c.n > 0) c.plane[unrot_off(g, -m, -c.n)] = cconj(v);
+        if (m >= 0 && m <= c.n) c.plane[unrot_off(g, m, c.n)] = v;
+        if (m <= 0 && -m <= c.n && c.n > 0) c.plane[unrot_off(g, -m, -c.n)] = cconj(v);
     }
 };
 
@@ -1195,7 +1269,7 @@ template <class C>
 static hipError_t unrot_inv_beta_t(const ScaleGeom &g, const BlueT<C> &B, const C *X, C *W1,
                                    hipStream_t st) {
     const int ne = unrot_cols(g);
-    BetaInvPairIO<C> io{X, W1, g.L, ne, g.Nep, 2 * g.L, (size_t)2 * g.L * g.Nep};
+    UnrotBetaInvPairIO<C> io{X, W1, g, ne};
     return run_bluestein(io, g.L * ne, B, st);
 }
 template <class C>

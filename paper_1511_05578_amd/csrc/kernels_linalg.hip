@@ -158,13 +158,16 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
 // layout is A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].  The factor i of
 // odd parity is applied while staging B: (re, im) -> (-im, re).  The next K
 // tile is loaded into registers while the current one is multiplied.
+// uL > 0: the synthesis cube of the unrotated curvelets at band-limit uL,
+// whose outputs are read only at m' <= l and m <= l (l = |n|); a tile with
+// none of those is skipped (its outputs are left unwritten).
 typedef double cvl_d4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, int Nep,
                                                    const double *__restrict__ Ae,
                                                    const double *__restrict__ Ao,
                                                    const double *__restrict__ in,
-                                                   double *__restrict__ out) {
+                                                   double *__restrict__ out, int uL) {
     __shared__ double As[128][17];
     __shared__ double Bs[16][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -174,6 +177,19 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, i
     const int lg = xcd_group(blockIdx.x, gridDim.x);
     const int r0 = (lg % nrt) * 128;
     const int c0 = (lg / nrt) * 32;  // complex column base
+    if (uL > 0) {  // uniform over the work-group
+        const int rho = c0 / Nep, m = rho >> 1, pn = ((rho & 1) + m) & 1;
+        const int h = (uL - 1) >> 1, ho = uL >> 1;
+        const int cb = c0 % Nep, clast = pn ? 2 * ho - 1 : 2 * h;  // last column in use
+        int lmax = -1;  // n is monotone in the column, so max |n| is at an end
+        if (cb <= clast) {
+            const int ce = cb + 31 < clast ? cb + 31 : clast;
+            const int n0 = pn ? 2 * (cb - ho) + 1 : 2 * (cb - h);
+            const int n1 = pn ? 2 * (ce - ho) + 1 : 2 * (ce - h);
+            lmax = max(n0 < 0 ? -n0 : n0, n1 < 0 ? -n1 : n1);
+        }
+        if (m > lmax || r0 > lmax) return;
+    }
     const size_t ld = 2 * (size_t)ncols;
     const int par = (c0 / Nep) & 1;
     const double *A = par ? Ao : Ae;
@@ -250,13 +266,23 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, i
             }
 }
 
+hipError_t launch_beta_gemm_unrot_fwd(const ScaleGeom &g, const double *Aeven,
+                                     const double *Aodd, const cd *in, cd *out, hipStream_t st) {
+    const int ncols = 2 * g.L * g.Nep;
+    if (g.Nep % 32 != 0) return hipErrorInvalidValue;
+    dim3 grid(((ncols + 31) / 32) * ((g.L + 127) / 128));
+    hipLaunchKernelGGL(k_beta_mfma, grid, dim3(256), 0, st, g.L, g.L, ncols, g.Nep, Aeven, Aodd,
+                       (const double *)in, (double *)out, g.L);
+    return hipGetLastError();
+}
+
 hipError_t launch_beta_gemm(int M, int K, int ncols, int Nep, int mode, int par0,
                             const double *Aeven, const double *Aodd, const cd *in, cd *out,
                             hipStream_t st) {
     if (mode == 0 && Nep % 32 == 0) {
         dim3 g(((ncols + 31) / 32) * ((M + 127) / 128));
         hipLaunchKernelGGL(k_beta_mfma, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
-                           (const double *)in, (double *)out);
+                           (const double *)in, (double *)out, 0);
         return hipGetLastError();
     }
     dim3 grid((ncols + 31) / 32, (M + 63) / 64);
@@ -643,75 +669,112 @@ hipError_t launch_reduce_fwd_mx(const ScaleGeom &g, int Lf, const cf *part, int 
 // ---------------------------------------------------------------------------
 // Unrotated curvelets (Sec. III-A-1): the kernel Psi~_ln is zero unless
 // |n| = l, so each Fourier-cube entry takes one l and the contractions are
-// O(L^3) per scale.  psi2[l] = Psi~_{l,l}; Psi~_{l,-l} = (-1)^l psi2[l];
-// Delta^l_{m',-l} = (-1)^(l+m') Delta^l_{m',l}.
+// O(L^3) per scale.  pd[m'][l] = Delta^l_{m'l} Psi~_{l,l} (zero for m' > l and
+// outside the kernel support; row length L_j); Psi~_{l,-l} = (-1)^l Psi~_{l,l}
+// and Delta^l_{m',-l} = (-1)^(l+m') Delta^l_{m',l}.
 //
-// Analysis: X[m'][m][n] = i^(n-m) s Delta^l_{m'm} Delta^l_{m'l} f_lm psi2[l],
-// l = |n|, s = (-1)^m' for n < 0 (the two signs above), zero unless
-// max(m, m') <= l and l is in the kernel support; every cube entry is written
-// (zeros included, unused columns too).  One thread per entry, a plane m' per
-// run of work-groups (xcd_group keeps a plane's Delta rows in one L2).
+// Analysis: X[m'][m][n] = i^(n-m) s Delta^l_{m'm} pd[m'][l] f_lm, l = |n|,
+// s = (-1)^m' for n < 0 (the two signs above), zero unless m <= l and m' <= l.
+// dense: every cube entry is written (zeros included, unused columns too), as
+// the beta GEMM reads them all; otherwise only the entries with m <= l and
+// m' <= l (the ones the beta FFT reads).  Work-group: one m'
+// and two m (four cube rows, all columns).  The per-l factors of those rows
+// (Delta^l_{m'm}, pd[m'][l], f_lm) are staged in LDS first, one read per l,
+// so each cube entry costs LDS reads and one coalesced store.  xcd_group keeps
+// a plane's Delta rows in one L2.
 // ---------------------------------------------------------------------------
 template <class C>
 __global__ __launch_bounds__(256) void k_unrot_contract_inv(ScaleGeom g, int Lf,
                                                             const double *__restrict__ delta,
                                                             const cd *__restrict__ fpad,
-                                                            const double *__restrict__ psi2,
-                                                            C *__restrict__ X, int nbx) {
-    const int lg = xcd_group(blockIdx.x, gridDim.x);
-    const int mp = lg / nbx;
-    const int idx = (lg % nbx) * 256 + threadIdx.x;
+                                                            const double *__restrict__ pd,
+                                                            C *__restrict__ X, int nmb,
+                                                            int dense) {
+    extern __shared__ __align__(16) char smem_raw[];
     const int L = g.L, Nep = g.Nep;
-    if (idx >= 2 * L * Nep) return;
-    const int rho = idx / Nep, c = idx % Nep;
-    const int m = rho >> 1, pn = ((rho & 1) + m) & 1;  // parity of n
-    const int ho = L >> 1;
-    cd out = cd{0.0, 0.0};
-    if (pn ? c < 2 * ho : c <= 2 * g.h) {
-        const int n = pn ? 2 * (c - ho) + 1 : 2 * (c - g.h);
-        const int l = n < 0 ? -n : n;
-        if (m <= l && mp <= l && l >= g.llo && l <= g.lhi) {
+    cd *fv = reinterpret_cast<cd *>(smem_raw);                   // [2][L]: f_{l, m0 + i}
+    double *dmm = reinterpret_cast<double *>(smem_raw) + 4 * L;  // [2][L]: Delta^l_{m', m0 + i}
+    double *dml = dmm + 2 * L;                                   // [L]: pd[m'][l]
+    const int lg = xcd_group(blockIdx.x, gridDim.x);
+    const int mp = lg / nmb, m0 = 2 * (lg % nmb);
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        const double p = pd[(size_t)mp * L + l];
+        const bool on = p != 0.0;  // implies m' <= l
+        double d0 = 0.0, d1 = 0.0;
+        cd f0 = cd{0.0, 0.0}, f1 = cd{0.0, 0.0};
+        if (on && m0 <= l) {
             const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
-            double w = row[m] * row[l] * psi2[l];
-            if (n < 0 && (mp & 1)) w = -w;
-            const cd f = fpad[(size_t)l * Lf + m];
-            out = ipow(cd{w * f.x, w * f.y}, n - m);
+            d0 = row[m0];
+            f0 = fpad[(size_t)l * Lf + m0];
+            if (m0 + 1 <= l) {
+                d1 = row[m0 + 1];
+                f1 = fpad[(size_t)l * Lf + m0 + 1];
+            }
         }
+        dmm[l] = d0;
+        dmm[L + l] = d1;
+        fv[l] = f0;
+        fv[L + l] = f1;
+        dml[l] = p;
     }
-    X[((size_t)mp * 2 * L + rho) * Nep + c] = cmk<C>(out.x, out.y);
+    __syncthreads();
+    const int ho = L >> 1;
+    const int nrow = m0 + 1 < L ? 4 : 2;
+    for (int e = threadIdx.x; e < nrow * Nep; e += blockDim.x) {
+        const int r = e / Nep, c = e % Nep;
+        const int mi = r >> 1, m = m0 + mi;
+        const int pn = ((r & 1) + m) & 1;  // parity of n
+        cd out = cd{0.0, 0.0};
+        bool keep = dense != 0;
+        if (pn ? c < 2 * ho : c <= 2 * g.h) {
+            const int n = pn ? 2 * (c - ho) + 1 : 2 * (c - g.h);
+            const int l = n < 0 ? -n : n;
+            double w = dmm[mi * L + l] * dml[l];
+            if (n < 0 && (mp & 1)) w = -w;
+            const cd f = fv[mi * L + l];
+            out = ipow(cd{w * f.x, w * f.y}, n - m);
+            keep = keep || (m <= l && mp <= l);
+        }
+        if (keep) X[((size_t)mp * 2 * L + 2 * m0 + r) * Nep + c] = cmk<C>(out.x, out.y);
+    }
 }
 
 template <class C>
 static hipError_t unrot_contract_inv_t(const ScaleGeom &g, int Lf, const double *delta,
-                                       const cd *fpad, const double *psi2, C *X, hipStream_t st) {
-    const int nbx = (2 * g.L * g.Nep + 255) / 256;
-    hipLaunchKernelGGL(k_unrot_contract_inv<C>, dim3(nbx * g.L), dim3(256), 0, st, g, Lf, delta,
-                       fpad, psi2, X, nbx);
+                                       const cd *fpad, const double *pd, C *X, bool dense,
+                                       hipStream_t st) {
+    const int nmb = (g.L + 1) / 2;
+    const size_t lds = (size_t)7 * g.L * sizeof(double);  // <= 56 KiB for L_j <= 1024
+    if (lds > 65536) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_unrot_contract_inv<C>, dim3(nmb * g.L), dim3(256), lds, st, g, Lf, delta,
+                       fpad, pd, X, nmb, dense ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cd *fpad, const double *psi2, cd *X, hipStream_t st) {
-    return unrot_contract_inv_t(g, Lf, delta, fpad, psi2, X, st);
+                                     const cd *fpad, const double *pd, cd *X, bool dense,
+                                     hipStream_t st) {
+    return unrot_contract_inv_t(g, Lf, delta, fpad, pd, X, dense, st);
 }
 hipError_t launch_unrot_contract_inv(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cd *fpad, const double *psi2, cf *X, hipStream_t st) {
-    return unrot_contract_inv_t(g, Lf, delta, fpad, psi2, X, st);
+                                     const cd *fpad, const double *pd, cf *X, bool dense,
+                                     hipStream_t st) {
+    return unrot_contract_inv_t(g, Lf, delta, fpad, pd, X, dense, st);
 }
 
 // Synthesis: with Y the beta-projected cube (m' >= 0, the -m' half folded in),
 //   F~^l_{m,+-l} = i^(m-+l) sum_{m'<=l} Delta^l_{m'm} Delta^l_{m',+-l} Y[m'][m][+-l]
-// and f_lm = psi2[l] (F~^l_{m,l} + (-1)^l F~^l_{m,-l}), i.e.
-//   facc[l][m] += psi2[l] i^(m-l) sum_{m'<=l} Delta^l_{m'm} Delta^l_{m'l}
+// and f_lm = Psi~_{l,l} F~^l_{m,l} + Psi~_{l,-l} F~^l_{m,-l}, i.e.
+//   facc[l][m] += i^(m-l) sum_{m'<=l} Delta^l_{m'm} pd[m'][l]
 //                 (Y[m'][m][l] + (-1)^(l+m') Y[m'][m][-l])      (n = 0 once).
 // Work-group: one m, 64 consecutive l (lanes), the m' sum split over the four
-// waves (m' = w mod 4) and added in LDS in wave order, in FP64.  Y[.][m][+-l]
-// of neighbouring l sit in two cube rows (one per parity), so the loads of a
-// wave touch few cache lines.
+// waves (m' = w mod 4), four m' per wave in flight, the wave sums added in
+// LDS in wave order, all in FP64.  Y[.][m][+-l] and pd[m'][.] of neighbouring
+// l are neighbours in memory (Y: two cube rows, one per parity of l).
 template <class C>
 __global__ __launch_bounds__(256) void k_unrot_contract_fwd(ScaleGeom g, int Lf,
                                                             const double *__restrict__ delta,
                                                             const C *__restrict__ Y,
-                                                            const double *__restrict__ psi2,
+                                                            const double *__restrict__ pd,
                                                             cd *__restrict__ facc) {
     __shared__ double red[4][64][2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -724,11 +787,29 @@ __global__ __launch_bounds__(256) void k_unrot_contract_fwd(ScaleGeom g, int Lf,
         const size_t plane = (size_t)2 * L * g.Nep;
         const C *yp = Y + unrot_off(g, m, l);
         const C *ym = Y + unrot_off(g, m, -l);
-        const double *blk = delta + delta_off(l);
+        const double *dm = delta + delta_off(l) + m;  // Delta^l_{m'm} at dm[m' (l + 1)]
+        const double *pl = pd + l;                    // pd[m'][l] at pl[m' L]
         const double both = l > 0 ? 1.0 : 0.0;
-        for (int mp = w; mp <= l; mp += 4) {
-            const double *row = blk + (int64_t)mp * (l + 1);
-            const double d = row[m] * row[l];
+        int mp = w;
+        for (; mp + 12 <= l; mp += 16) {
+            double dd[4];
+            C a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = mp + 4 * u;
+                dd[u] = dm[(int64_t)q * (l + 1)] * pl[(size_t)q * L];
+                a[u] = yp[q * plane];
+                b[u] = ym[q * plane];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double sb = ((l + mp + 4 * u) & 1) ? -both : both;
+                sx += dd[u] * ((double)a[u].x + sb * (double)b[u].x);
+                sy += dd[u] * ((double)a[u].y + sb * (double)b[u].y);
+            }
+        }
+        for (; mp <= l; mp += 4) {
+            const double d = dm[(int64_t)mp * (l + 1)] * pl[(size_t)mp * L];
             const C a = yp[mp * plane], b = ym[mp * plane];
             const double sb = ((l + mp) & 1) ? -both : both;
             sx += d * ((double)a.x + sb * (double)b.x);
@@ -744,26 +825,25 @@ __global__ __launch_bounds__(256) void k_unrot_contract_fwd(ScaleGeom g, int Lf,
             tx += red[q][lane][0];
             ty += red[q][lane][1];
         }
-        const double ps = psi2[l];
         cd *o = facc + (size_t)l * Lf + m;
-        *o = cadd(*o, ipow(cd{ps * tx, ps * ty}, m - l));
+        *o = cadd(*o, ipow(cd{tx, ty}, m - l));
     }
 }
 
 template <class C>
 static hipError_t unrot_contract_fwd_t(const ScaleGeom &g, int Lf, const double *delta,
-                                       const C *Y, const double *psi2, cd *facc, hipStream_t st) {
+                                       const C *Y, const double *pd, cd *facc, hipStream_t st) {
     hipLaunchKernelGGL(k_unrot_contract_fwd<C>, dim3((g.L + 63) / 64, g.L), dim3(256), 0, st, g,
-                       Lf, delta, Y, psi2, facc);
+                       Lf, delta, Y, pd, facc);
     return hipGetLastError();
 }
 hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cd *Y, const double *psi2, cd *facc, hipStream_t st) {
-    return unrot_contract_fwd_t(g, Lf, delta, Y, psi2, facc, st);
+                                     const cd *Y, const double *pd, cd *facc, hipStream_t st) {
+    return unrot_contract_fwd_t(g, Lf, delta, Y, pd, facc, st);
 }
 hipError_t launch_unrot_contract_fwd(const ScaleGeom &g, int Lf, const double *delta,
-                                     const cf *Y, const double *psi2, cd *facc, hipStream_t st) {
-    return unrot_contract_fwd_t(g, Lf, delta, Y, psi2, facc, st);
+                                     const cf *Y, const double *pd, cd *facc, hipStream_t st) {
+    return unrot_contract_fwd_t(g, Lf, delta, Y, pd, facc, st);
 }
 
 // ---------------------------------------------------------------------------
