@@ -68,6 +68,22 @@ def scale_geoms(L, lam=2.0, J0=2):
     return out
 
 
+def _unrot_live_lines(Lj):
+    """Line pairs (m, column) of the unrotated cube with a non-zero entry:
+    row (m, s) holds n of parity (m + s) mod 2 at column c (even n = 2(c - h),
+    c <= 2h; odd n = 2(c - floor(L_j/2)) + 1, c < 2 floor(L_j/2)); the entry
+    can be non-zero only if m <= |n|."""
+    import numpy as np
+    h, ho = (Lj - 1) // 2, Lj // 2
+    Nc = max(2 * h + 1, 2 * ho)
+    c = np.arange(Nc)
+    le = np.where(c <= 2 * h, np.abs(2 * (c - h)), -1)       # even-n class
+    lo = np.where(c < 2 * ho, np.abs(2 * (c - ho) + 1), -1)  # odd-n class
+    m = np.arange(Lj)[:, None]
+    # rows (m, 0) and (m, 1) hold the two classes, in an order set by m's parity
+    return int(np.count_nonzero((m <= le[None, :]) | (m <= lo[None, :])))
+
+
 def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None, unrot=False):
     """Algorithmic bytes / flops of each kernel stage per round trip of one
     map, keyed (stage, L_j): one launch per scale, scales of equal L_j summed.
@@ -82,10 +98,15 @@ def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None, unrot=False):
     BETA_FFT_MIN_L on, the analysis beta stage is such a DFT stage over
     (L_j + 1) / 2 * Ne line pairs).
 
-    Unrotated curvelets (unrot): the cube holds every n (2 L_j rows of Nc
-    columns per m' plane, Nc = max(2h + 1, 2 floor(L_j / 2))), the alpha / gamma
-    planes every n >= 0; the contractions have one term per non-zero cube entry
-    (l = |n|), the synthesis one reading only the n = +-l entries.
+    Unrotated curvelets (unrot): only what the method needs is counted.  A
+    cube entry (m', m >= 0, n) is non-zero only for m, m' <= l = |n| (nnz of
+    them, one contraction term each); the analysis beta DFT transforms the
+    line pairs (m, column) holding one (live lines), the alpha DFTs read or
+    write the |m| <= |n| entries, and the synthesis beta GEMM needs, for each
+    column with m <= |n|, the |n| + 1 outputs m' <= |n| (2 flops per
+    multiply-add of the real L_j-long rows on the two real parts).  Below
+    BETA_FFT_MIN_L the analysis beta stage is the dense GEMM on the whole cube
+    (2 L_j rows of Nc columns per plane, Nc = max(2h + 1, 2 floor(L_j / 2))).
     """
     m = {}
     GB = B if GB is None else GB
@@ -100,20 +121,24 @@ def stage_models(L, lam=2.0, J0=2, B=16.0, GB=None, unrot=False):
             Nc = max(2 * h + 1, 2 * (Lj // 2))
             terms = sum((l + 1) * (l + 1) * (2 if l else 1)
                         for l in range(g["llo"], g["lhi"] + 1))
+            nnz = sum((l + 1) * (l + 1) * (2 if l else 1) for l in range(Lj))
+            cols = sum(abs(n) + 1 for n in range(-(Lj - 1), Lj))  # columns with m <= |n|
+            live = _unrot_live_lines(Lj)
             cube = Lj * 2 * Lj * Nc * B
             w2 = Lj * Nm * Lj * B
             grid = Nm * Lj * Nm * GB
             fft = 5.0 * Nm * math.log2(Nm)
-            add("contract_inv", Lj, cube, 4.0 * terms)
             if Lj >= BETA_FFT_MIN_L:
-                add("beta_gemm_inv", Lj, 2 * cube, Lj * Nc * fft)
+                add("contract_inv", Lj, nnz * B, 4.0 * terms)
+                add("beta_gemm_inv", Lj, nnz * B + 2 * live * Lj * B, live * fft)
             else:
+                add("contract_inv", Lj, cube, 4.0 * terms)
                 add("beta_gemm_inv", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * 2 * Lj * Nc)
-            add("alpha_dft_inv", Lj, cube + w2, Lj * Lj * fft)
+            add("alpha_dft_inv", Lj, Lj * cols * B + w2, Lj * Lj * fft)
             add("gamma_dft_inv", Lj, w2 + grid, Nm * Lj * fft)
             add("gamma_dft_fwd", Lj, grid + w2, Nm * Lj * fft)
-            add("alpha_dft_fwd", Lj, w2 + cube, Lj * Lj * fft)
-            add("beta_gemm_fwd", Lj, 2 * cube, 2.0 * Lj * Lj * 2 * 2 * Lj * Nc)
+            add("alpha_dft_fwd", Lj, w2 + Lj * cols * B, Lj * Lj * fft)
+            add("beta_gemm_fwd", Lj, Lj * cols * B + nnz * B, 2.0 * 2 * Lj * nnz)
             add("contract_fwd", Lj, terms * B, 4.0 * terms)
             continue
         terms = sum((l + 1) * (l + 1) * (l // 2 + 1) for l in range(g["llo"], g["lhi"] + 1))
