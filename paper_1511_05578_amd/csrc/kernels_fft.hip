@@ -853,9 +853,8 @@ struct FwdAlphaIO {
 // z = X_{2p} + X_{2p+1} and splits the result by parity of beta ->
 // -beta (k' -> -k'):  W1_e(beta) = (Z(beta) + Z(-beta))/2,
 // W1_o(beta) = (Z(beta) - Z(-beta))/2, stored for b = L-1-k, k = 0..L-1.
-// X, W1: [row][m][nn] with row m' (input) or b (output), row length L*Nep.
-// The unrotated cube (2L rows of alternating parity per plane) is transformed
-// by the same pairs: `rows` cube rows per plane, plane stride `plane`.
+// X, W1: [row][m][nn] with row m' (input) or b (output): `rows` (= L) cube
+// rows of Nep per plane, plane stride `plane` (= L*Nep).
 template <class C_>
 struct BetaInvPairIO {
     using C = C_;

@@ -194,3 +194,32 @@ def test_unrotated_odd_bandlimit_fft_beta():
     finally:
         torch.cuda.synchronize()
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_unrotated_l512_reduced_precision(prec):
+    # L = 512, the reduced-precision configuration's band-limit: oracle beta
+    # rows of the finest scale, full round trip, at the precision's bar.
+    L, lam, J0 = 512, 2.0, 2
+    bound = BOUND[prec]
+    c = api.Context(L, 0)
+    try:
+        plan = ocurv.Plan(L, lam, J0, rotated=False)
+        f = inputs.gaussian_real_flm(L, seed=4)
+        fmap = osht.inverse(f, L).real
+        say("unrotated L=512 %s: GPU analysis" % prec)
+        scal, grids = c.curvelet_analysis(dev(fmap), lam, J0, precision=prec, unrotated=True)
+        s, j = len(plan.scales) - 1, plan.scales[-1]
+        rows = [3, 400]
+        say("  oracle rows %s of scale %d" % (rows, j))
+        ref = ocurv.analysis_scale(plan, f, j, rows=rows)
+        e = rel_l2(host(grids[s])[:, rows, :], ref)
+        say("  rows rel L2 %.2e" % e)
+        assert e < bound
+        rec = host(c.curvelet_synthesis(scal, grids, L, lam, J0, precision=prec, unrotated=True))
+        e = rel_l2(rec, fmap)
+        say("  round trip rel L2 %.2e" % e)
+        assert e < bound
+    finally:
+        torch.cuda.synchronize()
+        c.close()
