@@ -251,9 +251,11 @@ def source_fingerprint():
     return hsh.hexdigest()[:16]
 
 
-def recorded_traffic(workload_key, kernel):
+def recorded_traffic(workload_key, kernel, finest=False):
     """HBM bytes per launch of `kernel` from a committed counter summary of
-    this workload and this source fingerprint, else None."""
+    this workload and this source fingerprint, else None.  finest: the launch
+    of interest is one of the finest scales', and a kernel that every scale
+    shares has its largest launches recorded separately ("top")."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -273,6 +275,8 @@ def recorded_traffic(workload_key, kernel):
                     continue
                 k = rec.get("kernels", {}).get(kernel)
                 if k:
+                    if finest and "top" in k:
+                        k = k["top"]
                     return k["fetch_bytes"] + k["write_bytes"]
     return None
 
@@ -492,7 +496,7 @@ def main():
                                    "_ps%d" % args.point_sources if args.point_sources else "",
                                    "_rg" if RG else "", "_unrot" if UR else "")
     sym = kernel_symbol(top[0], top[1], prec, RG, UR)
-    roof["traffic"] = recorded_traffic(wkey, sym)
+    roof["traffic"] = recorded_traffic(wkey, sym, finest=top[1] == L)
     roof["kernel"] = sym
     roof["stage"] = top[0]
     roof["L_j"] = top[1]
