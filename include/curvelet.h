@@ -119,8 +119,17 @@ int cvl_scale_shape(const cvl_params *p, int j, int *Lj, int *Nj);
 int cvl_scaling_bandlimit(const cvl_params *p, int *Lphi);
 
 /* Workspace bytes needed by cvl_curvelet_analysis / cvl_curvelet_synthesis
- * for `batch` maps (the workspace is reused map after map). */
+ * for `batch` maps (the workspace is reused map after map).  It includes the
+ * buffers of the scales those calls run concurrently on side streams. */
 int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes);
+
+/* Workspace bytes needed by the per-scale calls of the streaming interface
+ * (cvl_curvelet_analysis_scale, cvl_curvelet_synthesis_scale,
+ * cvl_curvelet_scaling_analysis, cvl_curvelet_scaling_synthesis): they run
+ * on the caller's stream alone, so they need no side-stream buffers and this
+ * is at most cvl_workspace_bytes(p, 1, ...).  Errors: CVL_EINVAL for invalid
+ * parameters or a NULL `bytes`. */
+int cvl_scale_workspace_bytes(const cvl_params *p, size_t *bytes);
 
 /* Workspace bytes needed by the SHT (L) and Wigner (L, N) entry points. */
 int cvl_sht_workspace_bytes(int L, size_t *bytes);
@@ -193,7 +202,7 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
  * one scale's grid need be resident (Sec. II-D; the synthesis is a sum over
  * scales in harmonic space, Sec. II-D-2).  flm / flm_acc are L^2 complex128
  * harmonic coefficients in the layout of cvl_sht_forward (negative m by the
- * reality condition).  Workspace: cvl_workspace_bytes(p, 1).  A round trip is
+ * reality condition).  Workspace: cvl_scale_workspace_bytes(p).  A round trip is
  *   cvl_sht_forward(map) -> flm;  cvl_curvelet_scaling_analysis(flm) -> scal;
  *   per scale j: cvl_curvelet_analysis_scale(flm, j) -> grid,
  *                cvl_curvelet_synthesis_scale(grid, j) adds into flm_acc;

@@ -36,6 +36,7 @@ SIGNATURES = {
     "cvl_scale_shape": (ctypes.c_int, [ctypes.POINTER(CvlParams), ctypes.c_int, _c_int_p, _c_int_p]),
     "cvl_scaling_bandlimit": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_int_p]),
     "cvl_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(CvlParams), ctypes.c_int, _c_size_p]),
+    "cvl_scale_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(CvlParams), _c_size_p]),
     "cvl_sht_workspace_bytes": (ctypes.c_int, [ctypes.c_int, _c_size_p]),
     "cvl_wigner_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_size_p]),
     "cvl_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams)]),
@@ -139,6 +140,14 @@ def workspace_bytes(L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, unrotated=Fal
     v = ctypes.c_size_t()
     p = params(L, lam, J0, precision=precision, unrotated=unrotated)
     _check(lib.cvl_workspace_bytes(ctypes.byref(p), batch, ctypes.byref(v)))
+    return v.value
+
+
+def scale_workspace_bytes(L, lam=2.0, J0=2, precision=CVL_FP64, unrotated=False):
+    """Workspace of the per-scale (streaming) calls."""
+    v = ctypes.c_size_t()
+    p = params(L, lam, J0, precision=precision, unrotated=unrotated)
+    _check(lib.cvl_scale_workspace_bytes(ctypes.byref(p), ctypes.byref(v)))
     return v.value
 
 
@@ -328,7 +337,7 @@ class Context:
             Lj, _ = scale_shape(L, j, lam, J0)
             out = t.empty((2 * Lj - 1, Lj, 2 * Lj - 1), dtype=dt, device=self.device)
         assert out.dtype == dt and out.is_contiguous()
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
         p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
         _check(lib.cvl_curvelet_analysis_scale(self.h, ctypes.byref(p), j, flm.data_ptr(),
                                                out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(t)))
@@ -340,7 +349,7 @@ class Context:
         t = self.torch
         assert grid.dtype == self.grid_dtype(precision, real_grids) and grid.is_contiguous()
         assert flm_acc.dtype == t.complex128 and flm_acc.numel() == L * L
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
         p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
         _check(lib.cvl_curvelet_synthesis_scale(self.h, ctypes.byref(p), j, grid.data_ptr(),
                                                 flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
@@ -348,14 +357,14 @@ class Context:
         return flm_acc
 
     # The scaling part is FP64 at every precision; `precision` only names the
-    # streaming workspace (cvl_workspace_bytes of the same parameters) to use.
+    # streaming workspace (cvl_scale_workspace_bytes of the same parameters) to use.
     def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None, precision=CVL_FP64,
                          unrotated=False):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
         if out is None:
             out = t.empty((Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
         p = params(L, lam, J0, precision=precision, unrotated=unrotated)
         _check(lib.cvl_curvelet_scaling_analysis(self.h, ctypes.byref(p), flm.data_ptr(),
                                                  out.data_ptr(), ws.data_ptr(), ws.numel(),
@@ -364,7 +373,7 @@ class Context:
 
     def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2, precision=CVL_FP64,
                           unrotated=False):
-        ws = self.workspace(workspace_bytes(L, lam, J0, 1, precision, unrotated))
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
         p = params(L, lam, J0, precision=precision, unrotated=unrotated)
         _check(lib.cvl_curvelet_scaling_synthesis(self.h, ctypes.byref(p), scal.data_ptr(),
                                                   flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),

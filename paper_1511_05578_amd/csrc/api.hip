@@ -394,16 +394,22 @@ void curvelet_buf_elems(int L, double lam, int J0, int J, bool unrot, size_t *b0
 }
 
 // Workspace bytes of a curvelet call: two cube buffers for the top scales and
-// two for the side scales (complex128, or complex64 in reduced precision) and
-// six L x L complex128 planes.
-size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision, bool unrot) {
+// four L x L (plus the scaling band-limit's) complex128 planes; the batched
+// calls add two cube buffers and a plane for the side scales (cube elements
+// complex128, or complex64 in reduced precision).  The per-scale calls
+// (scale_call) need only the first part: they run on one stream.
+size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision, bool unrot,
+                         bool scale_call) {
     size_t b0, b1, sb0, sb1;
     curvelet_buf_elems(L, lam, J0, J, unrot, &b0, &b1, &sb0, &sb1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     const int Lphi = scaling_bandlimit(L, lam, J0);
     size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
-    return align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) + 8 * kAlign +
-           align_up(sb0 * esz) + align_up(sb1 * esz) + align_up((size_t)L * L * 16) + 3 * kAlign;
+    const size_t base = align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) +
+                        8 * kAlign;
+    if (scale_call) return base;
+    const size_t plane = align_up((size_t)L * L * 16);
+    return base + align_up(sb0 * esz) + align_up(sb1 * esz) + plane + 3 * kAlign;
 }
 
 int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
@@ -679,7 +685,17 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
     *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision,
-                               (p->flags & CVL_UNROTATED) != 0);
+                               (p->flags & CVL_UNROTATED) != 0, false);
+    return CVL_OK;
+}
+
+int cvl_scale_workspace_bytes(const cvl_params *p, size_t *bytes) {
+    g_err.clear();
+    int J, rc = check_params(p, &J);
+    if (rc) return rc;
+    if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
+    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision,
+                               (p->flags & CVL_UNROTATED) != 0, true);
     return CVL_OK;
 }
 
@@ -864,7 +880,7 @@ int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid, cvl_c12
 
 static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, const void *a,
                                const void *b, const void *grids, void *ws, size_t ws_bytes,
-                               Plan **P) {
+                               Plan **P, bool scale_call = false) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
@@ -872,7 +888,7 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
     if ((rc = set_device(ctx))) return rc;
     if ((rc = get_plan(ctx, p, P))) return rc;
     const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, p->precision,
-                                          (p->flags & CVL_UNROTATED) != 0);
+                                          (p->flags & CVL_UNROTATED) != 0, scale_call);
     if (ws_bytes < need)
         return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -894,6 +910,8 @@ static CurveletBufs carve_curvelet(const Plan *P, int precision, bool unrot, voi
     size_t b0, b1, sb0, sb1;
     curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, unrot, &b0, &b1, &sb0, &sb1);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
+    // the per-scale calls may pass the first part only (through fphi): the
+    // side-stream buffers then come out null, and those calls do not use them
     Carver cv{(char *)ws, ws_bytes};
     CurveletBufs B;
     B.b0 = cv.take<char>(b0 * esz);
@@ -1082,6 +1100,7 @@ static int get_side(cvl_ctx *ctx, hipStream_t st, cvl_ctx::Side **out) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
         (void)hipSetDevice(prev);
         if (e != hipSuccess) {
+            if (sd.join) (void)hipEventDestroy(sd.join);
             if (sd.fork) (void)hipEventDestroy(sd.fork);
             if (sd.s) (void)hipStreamDestroy(sd.s);
             return fail(CVL_EDEVICE, "side stream creation failed: %s", hipGetErrorString(e));
@@ -1213,7 +1232,7 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
 // ---- streaming interface: one scale at a time, harmonic-space accumulator ----
 static int check_scale_call(cvl_ctx *ctx, const cvl_params *p, int j, const void *a,
                             const void *b, void *ws, size_t ws_bytes, Plan **P, int *s) {
-    int rc = check_curvelet_call(ctx, p, 1, a, b, a, ws, ws_bytes, P);
+    int rc = check_curvelet_call(ctx, p, 1, a, b, a, ws, ws_bytes, P, true);
     if (rc) return rc;
     if (j < (*P)->J0 || j > (*P)->J)
         return fail(CVL_EINVAL, "scale j=%d outside [J0=%d, J=%d]", j, (*P)->J0, (*P)->J);
@@ -1255,7 +1274,7 @@ int cvl_curvelet_scaling_analysis(cvl_ctx *ctx, const cvl_params *p, const cvl_c
                                   double *scal_map, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
     Plan *P;
-    int rc = check_curvelet_call(ctx, p, 1, flm, scal_map, flm, ws, ws_bytes, &P);
+    int rc = check_curvelet_call(ctx, p, 1, flm, scal_map, flm, ws, ws_bytes, &P, true);
     if (rc) return rc;
     ShtRt *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
@@ -1270,7 +1289,7 @@ int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p, const doub
                                    cvl_c128 *flm_acc, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
     Plan *P;
-    int rc = check_curvelet_call(ctx, p, 1, scal_map, flm_acc, scal_map, ws, ws_bytes, &P);
+    int rc = check_curvelet_call(ctx, p, 1, scal_map, flm_acc, scal_map, ws, ws_bytes, &P, true);
     if (rc) return rc;
     ShtRt *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;

@@ -93,6 +93,21 @@ def test_unrotated_flag_accepted_and_sizes_workspace():
         assert api.workspace_bytes(L, unrotated=True) > api.workspace_bytes(L)
 
 
+def test_scale_workspace_excludes_side_stream_buffers():
+    # the per-scale calls run on one stream: no side-stream cube buffers
+    for L, prec, unrot in [(32, "fp64", False), (256, "fp64", False), (256, "fp32", True),
+                           (1024, "fp32", False)]:
+        full = api.workspace_bytes(L, precision=prec, unrotated=unrot)
+        scale = api.scale_workspace_bytes(L, precision=prec, unrotated=unrot)
+        assert 0 < scale < full
+    p = api.params(32)
+    assert api.lib.cvl_scale_workspace_bytes(ctypes.byref(p), None) == api.CVL_EINVAL
+    bad = api.params(32, lam=1.0)
+    v = ctypes.c_size_t(7)
+    assert api.lib.cvl_scale_workspace_bytes(ctypes.byref(bad), ctypes.byref(v)) == api.CVL_EINVAL
+    assert v.value == 7
+
+
 def test_null_arguments_rejected():
     assert api.lib.cvl_num_scales(None, None) == api.CVL_EINVAL
     p = api.params(32)
