@@ -2,9 +2,9 @@
 
 Bar (plain FP64 path): relative L2 error <= 1e-10 on every compared output
 (the oracle and the HIP path differ only by rounding; observed errors are
-~1e-14).  Sizes span several tiles and ragged tails; C2 (L = 256) is checked
-on sampled beta rows the oracle computes one by one, plus round-trip
-reconstruction at full size.
+~1e-14).  Sizes span several tiles and ragged tails; the one-map L = 256
+benchmark workload is checked on sampled beta rows the oracle computes one by
+one, plus round-trip reconstruction at full size.
 """
 import math
 import sys
@@ -133,9 +133,9 @@ def test_curvelet_analysis_and_synthesis(ctx, L, lam, J0):
     assert rel_l2(frec, f) < TOL
 
 
-def test_curvelet_c1_elementwise_and_deterministic(ctx):
+def test_curvelet_l32_elementwise_and_deterministic(ctx):
     L, lam, J0 = 32, 2.0, 2
-    say("C1 determinism")
+    say("L=32 determinism")
     fmap = osht.inverse(inputs.gaussian_real_flm(L, 0), L).real
     d = dev(fmap)
     s1, g1 = ctx.curvelet_analysis(d, lam, J0)
@@ -179,15 +179,15 @@ def test_batch_equals_single(ctx):
     assert rel_l2(rec, maps) < TOL
 
 
-def test_c2_sampled_rows_and_round_trip(ctx):
-    # L = 256 (configuration C2): oracle beta rows of the two finest scales,
+def test_l256_sampled_rows_and_round_trip(ctx):
+    # L = 256 (the one-map benchmark workload): oracle beta rows of the two finest scales,
     # every grid's realness, full round-trip reconstruction.
     L, lam, J0 = 256, 2.0, 2
-    say("C2 L=256: building oracle plan")
+    say("L=256: building oracle plan")
     plan = ocurv.Plan(L, lam, J0)
     f = inputs.gaussian_real_flm(L, seed=0)
     fmap = osht.inverse(f, L).real
-    say("C2: GPU analysis")
+    say("L=256: GPU analysis")
     scal, grids = ctx.curvelet_analysis(dev(fmap), lam, J0)
     ref_scal = osht.inverse(ocurv.scaling_flm(plan, f), plan.Lphi).real
     assert rel_l2(host(scal), ref_scal) < TOL
@@ -197,13 +197,13 @@ def test_c2_sampled_rows_and_round_trip(ctx):
         if Lj < 128:
             continue
         rr = [r for r in rows if r < Lj]
-        say("C2: oracle rows %s of scale %d" % (rr, j))
+        say("L=256: oracle rows %s of scale %d" % (rr, j))
         ref = ocurv.analysis_scale(plan, f, j, rows=rr)
         g = host(grids[s])
         e = rel_l2(g[:, rr, :], ref)
         say("  scale %d rows rel L2 %.2e" % (j, e))
         assert e < TOL
-    say("C2: GPU synthesis")
+    say("L=256: GPU synthesis")
     rec = host(ctx.curvelet_synthesis(scal, grids, L, lam, J0))
     e = rel_l2(rec, fmap)
     say("  round trip rel L2 %.2e" % e)
