@@ -57,7 +57,8 @@ def host(t):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("L,lam,J0", [(32, 2.0, 2), (13, 2.0, 1), (20, 1.5, 2), (33, 2.0, 2),
-                                      (8, 2.0, 3)])
+                                      (8, 2.0, 3), (2, 2.0, 1), (3, 2.0, 1), (4, 2.0, 2),
+                                      (27, 3.0, 1)])
 def test_unrotated_analysis_and_synthesis(ctx, L, lam, J0, prec):
     say("unrotated L=%d lambda=%g J0=%d %s" % (L, lam, J0, prec))
     bound = BOUND[prec]
