@@ -1143,6 +1143,24 @@ static int analysis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
     return CVL_OK;
 }
 
+// Scaling part of the analysis: (W^Phi)_lm = phifac_l f_lm, then the inverse
+// SHT at L_Phi into the scaling map (scratch X.s0, X.s1).
+static int scaling_analysis_run(cvl_ctx *ctx, const Plan *P, ShtRt *SP, const CurveletBufs &X,
+                                double *smap, hipStream_t st) {
+    LAUNCH(ST_MISC, launch_scale_flm(P->Lphi, P->L, P->Lphi, P->phifac, X.fpad, X.fphi, 0, st));
+    return sht_inverse_run(ctx, SP, X.fphi, P->Lphi, smap, X.s0, X.s1, st);
+}
+
+// Scaling part of the synthesis: forward SHT of the scaling map at L_Phi, then
+// X.facc[l][m] += phifac_l (W^Phi)_lm.
+static int scaling_synthesis_run(cvl_ctx *ctx, const Plan *P, ShtRt *SP, const CurveletBufs &X,
+                                 const double *smap, hipStream_t st) {
+    int rc = sht_forward_run(ctx, SP, smap, X.fphi, P->Lphi, X.s0, X.s1, st);
+    if (rc) return rc;
+    LAUNCH(ST_MISC, launch_scale_flm(P->Lphi, P->Lphi, P->L, P->phifac, X.fphi, X.facc, 1, st));
+    return CVL_OK;
+}
+
 // Zeroes B.facc, then adds the synthesis of scales [s0, s1) into it.
 static int synthesis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
                             const CurveletBufs &B, const void *const *grids, int s0, int s1,
@@ -1179,12 +1197,14 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
         double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
         void *const *g = grids + (size_t)bi * nJ;
         if ((rc = sht_forward_run(ctx, SL, map, B.fpad, L, B.s0, B.s1, st))) return rc;
-        LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
-        if ((rc = sht_inverse_run(ctx, SP, B.fphi, Lp, smap, B.s0, B.s1, st))) return rc;
+        // the scaling part goes with the side scales when there is a side stream
+        // (it only reads the padded coefficients), else on the caller's stream
+        if (!sd && (rc = scaling_analysis_run(ctx, P, SP, B, smap, st))) return rc;
         if (sd && (rc = side_fork(sd, st))) return rc;
         // top scales enqueued first, so that the caller's stream starts on them
         // while the side scales' launches are still being enqueued
         rc = analysis_scales(ctx, P, p, B, g, nside, nJ, st);
+        if (!rc && sd) rc = scaling_analysis_run(ctx, P, SP, BS, smap, sd->s);
         if (!rc && sd) rc = analysis_scales(ctx, P, p, BS, g, 0, nside, sd->s);
         // joined even after an error: the next map (or call) reuses the buffers
         const int rj = sd ? side_join(sd, st) : CVL_OK;
@@ -1214,16 +1234,17 @@ int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const d
         const double *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
         double *map = maps + (size_t)bi * L * (2 * L - 1);
         const void *const *g = grids + (size_t)bi * nJ;
-        // top scales into B.facc, side scales into their own accumulator,
-        // added in afterwards (a fixed order: results are deterministic)
+        // top scales into B.facc; the side scales and then the scaling part
+        // into the side accumulator, added in afterwards (a fixed order:
+        // results are deterministic)
         if (sd && (rc = side_fork(sd, st))) return rc;
         rc = synthesis_scales(ctx, P, p, B, g, nside, nJ, st);
         if (!rc && sd) rc = synthesis_scales(ctx, P, p, BS, g, 0, nside, sd->s);
+        if (!rc && sd) rc = scaling_synthesis_run(ctx, P, SP, BS, smap, sd->s);
         const int rj = sd ? side_join(sd, st) : CVL_OK;
         if (rc || (rc = rj)) return rc;
         if (sd) LAUNCH(ST_MISC, launch_add(B.facc, BS.facc, (size_t)L * L, st));
-        if ((rc = sht_forward_run(ctx, SP, smap, B.fphi, Lp, B.s0, B.s1, st))) return rc;
-        LAUNCH(ST_MISC, launch_scale_flm(Lp, Lp, L, P->phifac, B.fphi, B.facc, 1, st));
+        if (!sd && (rc = scaling_synthesis_run(ctx, P, SP, B, smap, st))) return rc;
         if ((rc = sht_inverse_run(ctx, SL, B.facc, L, map, B.s0, B.s1, st))) return rc;
     }
     return CVL_OK;
