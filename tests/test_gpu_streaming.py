@@ -73,6 +73,39 @@ def test_streamed_equals_all_scales(ctx, L, prec):
     assert d <= 1e-14
 
 
+def test_scale_workspace_is_enough_for_the_per_scale_calls(ctx):
+    # The per-scale calls run with exactly cvl_scale_workspace_bytes (no side-
+    # stream buffers) and give the same grid as with the full workspace; one
+    # byte less, or the batched call with that size, is refused before any
+    # launch (CVL_ENOMEM, nothing written).
+    import ctypes
+    L, lam, J0, j = 64, 2.0, 2, 5
+    fmap = dev(osht.inverse(inputs.gaussian_real_flm(L, 3), L).real)
+    flm = ctx.sht_forward(fmap)
+    ref = ctx.analysis_scale(flm, L, j, lam, J0)
+    torch.cuda.synchronize()
+    n = api.scale_workspace_bytes(L, lam, J0)
+    assert n < api.workspace_bytes(L, lam, J0)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    p = api.params(L, lam, J0)
+    out = torch.full_like(ref, 7.0)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = api.lib.cvl_curvelet_analysis_scale(ctx.h, ctypes.byref(p), j, flm.data_ptr(),
+                                             out.data_ptr(), ws.data_ptr(), n - 1, s)
+    assert rc == api.CVL_ENOMEM
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+    api._check(api.lib.cvl_curvelet_analysis_scale(ctx.h, ctypes.byref(p), j, flm.data_ptr(),
+                                                   out.data_ptr(), ws.data_ptr(), n, s))
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    scal, grids = ctx.alloc_outputs(L, lam, J0)
+    arr = (ctypes.c_void_p * len(grids[0]))(*[g.data_ptr() for g in grids[0]])
+    rc = api.lib.cvl_curvelet_analysis(ctx.h, ctypes.byref(p), 1, fmap.data_ptr(),
+                                       scal.data_ptr(), arr, ws.data_ptr(), n, s)
+    assert rc == api.CVL_ENOMEM
+
+
 def test_point_sources_against_oracle(ctx):
     # Gaussian field plus 64 point sources, projected onto band-limit L by each
     # side's own SHT pair, then analysed by both.
