@@ -21,7 +21,8 @@
  *   e^{-ing}, Condon-Shortley phase, Y_lm = sqrt((2l+1)/4pi) d^l_{m0} e^{imphi}.
  * - All data pointers are DEVICE pointers owned by the caller.  The library
  *   never allocates or frees them.  Scratch memory is the caller's workspace
- *   `ws` of `ws_bytes` bytes (size from cvl_workspace_bytes); the library
+ *   `ws` of `ws_bytes` bytes (size from cvl_workspace_bytes, or for the
+ *   per-scale streaming calls cvl_scale_workspace_bytes); the library
  *   itself allocates only inside cvl_context_create (the resident Delta table)
  *   and on the first use of a new (L, lambda, J0) (its kernel and DFT tables,
  *   kept until cvl_context_destroy; cvl_prepare builds them ahead of time).
