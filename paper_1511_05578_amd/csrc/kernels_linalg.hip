@@ -930,56 +930,86 @@ hipError_t launch_gen_contract_fwd(int L, int N, const double *delta, const cd *
 //   forward: f_lm = i^m c_l sum_{m'<=l} Delta^l_{m'm} Delta^l_{m'0} Z[m'][m]
 // (Delta^l_{m'0} = 0 when l + m' is odd.)
 // ---------------------------------------------------------------------------
-__global__ void k_sht_inv_delta(int L, int Lf, const double *__restrict__ delta,
-                                const cd *__restrict__ fpad, cd *__restrict__ F) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= L * L) return;
-    const int mp = idx / L, m = idx % L;
-    int l0 = m > mp ? m : mp;
-    if ((l0 + mp) & 1) ++l0;
-    cd s = cd{0.0, 0.0};
-    for (int l = l0; l < L; l += 2) {
-        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
-        const double w = sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * row[m] * row[0];
-        const cd f = fpad[(size_t)l * Lf + m];
-        s.x += w * f.x;
-        s.y += w * f.y;
+// Work-group: 64 consecutive m (lanes) of one m' (inverse) or one l
+// (forward), the sum split over the four waves (every fourth term) and the
+// wave sums added in LDS in wave order: four times the work-groups of one
+// thread per output, which at L = 256 would leave one work-group per CU.
+__global__ __launch_bounds__(256) void k_sht_inv_delta(int L, int Lf,
+                                                       const double *__restrict__ delta,
+                                                       const cd *__restrict__ fpad,
+                                                       cd *__restrict__ F) {
+    __shared__ double red[4][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mp = blockIdx.y, m = blockIdx.x * 64 + lane;
+    double sx = 0.0, sy = 0.0;
+    if (m < L) {
+        int l0 = m > mp ? m : mp;
+        if ((l0 + mp) & 1) ++l0;
+        for (int l = l0 + 2 * w; l < L; l += 8) {
+            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double c = sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * row[m] * row[0];
+            const cd f = fpad[(size_t)l * Lf + m];
+            sx += c * f.x;
+            sy += c * f.y;
+        }
     }
-    F[(size_t)mp * L + m] = ipow(s, -m);
+    red[w][lane][0] = sx;
+    red[w][lane][1] = sy;
+    __syncthreads();
+    if (w == 0 && m < L) {
+        double tx = red[0][lane][0], ty = red[0][lane][1];
+        for (int q = 1; q < 4; ++q) {
+            tx += red[q][lane][0];
+            ty += red[q][lane][1];
+        }
+        F[(size_t)mp * L + m] = ipow(cd{tx, ty}, -m);
+    }
 }
 
-__global__ void k_sht_fwd_delta(int L, int Lf, const double *__restrict__ delta,
-                                const cd *__restrict__ Z, cd *__restrict__ fpad) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= L * L) return;
-    const int l = idx / L, m = idx % L;
-    cd *o = fpad + (size_t)l * Lf + m;
-    if (m > l) {
-        *o = cd{0.0, 0.0};
-        return;
+__global__ __launch_bounds__(256) void k_sht_fwd_delta(int L, int Lf,
+                                                       const double *__restrict__ delta,
+                                                       const cd *__restrict__ Z,
+                                                       cd *__restrict__ fpad) {
+    __shared__ double red[4][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int l = blockIdx.y, m = blockIdx.x * 64 + lane;
+    double sx = 0.0, sy = 0.0;
+    if (m <= l) {
+        for (int mp = (l & 1) + 2 * w; mp <= l; mp += 8) {
+            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double c = row[m] * row[0];
+            const cd z = Z[(size_t)mp * L + m];
+            sx += c * z.x;
+            sy += c * z.y;
+        }
     }
-    cd s = cd{0.0, 0.0};
-    for (int mp = (l & 1); mp <= l; mp += 2) {
-        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
-        const double w = row[m] * row[0];
-        const cd z = Z[(size_t)mp * L + m];
-        s.x += w * z.x;
-        s.y += w * z.y;
+    red[w][lane][0] = sx;
+    red[w][lane][1] = sy;
+    __syncthreads();
+    if (w == 0 && m < L) {
+        cd *o = fpad + (size_t)l * Lf + m;
+        if (m > l) {
+            *o = cd{0.0, 0.0};
+        } else {
+            double tx = red[0][lane][0], ty = red[0][lane][1];
+            for (int q = 1; q < 4; ++q) {
+                tx += red[q][lane][0];
+                ty += red[q][lane][1];
+            }
+            *o = ipow(cscale(cd{tx, ty}, sqrt((2.0 * l + 1.0) / (4.0 * M_PI))), m);
+        }
     }
-    *o = ipow(cscale(s, sqrt((2.0 * l + 1.0) / (4.0 * M_PI))), m);
 }
 
 hipError_t launch_sht_inv_delta(int L, int Lf, const double *delta, const cd *fpad, cd *F,
                                 hipStream_t st) {
-    const int n = L * L;
-    hipLaunchKernelGGL(k_sht_inv_delta, dim3((n + 255) / 256), dim3(256), 0, st, L, Lf, delta,
+    hipLaunchKernelGGL(k_sht_inv_delta, dim3((L + 63) / 64, L), dim3(256), 0, st, L, Lf, delta,
                        fpad, F);
     return hipGetLastError();
 }
 hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z, cd *fpad,
                                 hipStream_t st) {
-    const int n = L * L;
-    hipLaunchKernelGGL(k_sht_fwd_delta, dim3((n + 255) / 256), dim3(256), 0, st, L, Lf, delta,
+    hipLaunchKernelGGL(k_sht_fwd_delta, dim3((L + 63) / 64, L), dim3(256), 0, st, L, Lf, delta,
                        Z, fpad);
     return hipGetLastError();
 }
