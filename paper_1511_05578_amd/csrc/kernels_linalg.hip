@@ -1014,35 +1014,39 @@ hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z,
     return hipGetLastError();
 }
 // theta stage of the SHT: out[r][m] = (i^(m&1)) sum_k A^{m&1}[r][k] in[k][m],
-// r < Mrows, k < Kdim, m < L.  One output per thread, 16 x 16 tiles (enough
-// work-groups to fill the device at small L), K in chunks of 32 through LDS.
+// r < Mrows, k < Kdim, m < L.  Work-group: an 8 x 8 output tile, K in chunks
+// of 32 through LDS, each chunk's 32 terms split over the four waves (8 each)
+// and the wave sums added in LDS in wave order; small tiles so that there are
+// enough work-groups to fill the device at the band-limits of the SHT.
 __global__ __launch_bounds__(256) void k_sht_theta(int L, int Mrows, int Kdim,
                                                    const double *__restrict__ Ae,
                                                    const double *__restrict__ Ao,
                                                    const cd *__restrict__ in,
                                                    cd *__restrict__ out) {
-    __shared__ double As[2][16][33];
-    __shared__ cd Bs[32][17];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int m = blockIdx.x * 16 + tx, r = blockIdx.y * 16 + ty;
+    __shared__ double As[2][8][33];
+    __shared__ cd Bs[32][9];
+    __shared__ double red[4][64][2];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx = lane & 7, ty = lane >> 3;
+    const int m = blockIdx.x * 8 + tx, r = blockIdx.y * 8 + ty;
     const int par = m & 1;
     double re = 0.0, im = 0.0;
     for (int k0 = 0; k0 < Kdim; k0 += 32) {
-        for (int i = threadIdx.x; i < 512; i += 256) {
+        {
+            const int i = threadIdx.x;  // 256 = 8 rows x 32 k
             const int rr = i >> 5, kk = i & 31;
-            const int rg = blockIdx.y * 16 + rr, k = k0 + kk;
+            const int rg = blockIdx.y * 8 + rr, k = k0 + kk;
             const bool ok = rg < Mrows && k < Kdim;
             As[0][rr][kk] = ok ? Ae[(size_t)rg * Kdim + k] : 0.0;
             As[1][rr][kk] = ok ? Ao[(size_t)rg * Kdim + k] : 0.0;
-        }
-        for (int i = threadIdx.x; i < 512; i += 256) {
-            const int kk = i >> 4, mm = i & 15;
-            const int k = k0 + kk, mg = blockIdx.x * 16 + mm;
-            Bs[kk][mm] = (k < Kdim && mg < L) ? in[(size_t)k * L + mg] : cd{0.0, 0.0};
+            const int kb = i >> 3, mm = i & 7;  // 256 = 32 k x 8 m
+            const int kg = k0 + kb, mg = blockIdx.x * 8 + mm;
+            Bs[kb][mm] = (kg < Kdim && mg < L) ? in[(size_t)kg * L + mg] : cd{0.0, 0.0};
         }
         __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = 8 * w + q;
             const double a = As[par][ty][kk];
             const cd b = Bs[kk][tx];
             re += a * b.x;
@@ -1050,12 +1054,22 @@ __global__ __launch_bounds__(256) void k_sht_theta(int L, int Mrows, int Kdim,
         }
         __syncthreads();
     }
-    if (r < Mrows && m < L) out[(size_t)r * L + m] = par ? cd{-im, re} : cd{re, im};
+    red[w][lane][0] = re;
+    red[w][lane][1] = im;
+    __syncthreads();
+    if (w == 0 && r < Mrows && m < L) {
+        double sr = red[0][lane][0], si = red[0][lane][1];
+        for (int q = 1; q < 4; ++q) {
+            sr += red[q][lane][0];
+            si += red[q][lane][1];
+        }
+        out[(size_t)r * L + m] = par ? cd{-si, sr} : cd{sr, si};
+    }
 }
 
 hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int, const double *Aeven,
                             const double *Aodd, const cd *in, cd *out, hipStream_t st) {
-    dim3 grid((L + 15) / 16, (Mrows + 15) / 16);
+    dim3 grid((L + 7) / 8, (Mrows + 7) / 8);
     hipLaunchKernelGGL(k_sht_theta, grid, dim3(256), 0, st, L, Mrows, Kdim, Aeven, Aodd, in, out);
     return hipGetLastError();
 }
