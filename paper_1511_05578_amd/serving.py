@@ -88,10 +88,13 @@ class Request:
 
 class CurveletServer:
     def __init__(self, L_max=512, lam=2.0, J0=2, slots=4, hbm_budget=None, max_batch=4,
-                 keep_grids=False, device=0):
+                 keep_grids=False, device=0, unrotated=False):
+        """unrotated: every request gets the coefficients of the unrotated
+        curvelets (CVL_UNROTATED) instead of the rotated ones."""
         import torch
         self.torch = torch
         self.lam, self.J0 = lam, J0
+        self.unrotated = bool(unrotated)
         self.ctx = api.Context(L_max, device)
         self.dev = self.ctx.device
         self.slots = slots
@@ -116,7 +119,8 @@ class CurveletServer:
         Ls = sorted(set(int(x) for x in Ls))
         for L in Ls:
             self.ctx.prepare(L, self.lam, self.J0)
-        nb = max(api.workspace_bytes(L, self.lam, self.J0, self.cap(L)) for L in Ls)
+        nb = max(api.workspace_bytes(L, self.lam, self.J0, self.cap(L), unrotated=self.unrotated)
+                 for L in Ls)
         for s in range(self.slots):
             if self.ws[s] is None or self.ws[s].numel() < nb:
                 self.ws[s] = None
@@ -135,13 +139,14 @@ class CurveletServer:
             maps = t.stack([r.fmap for r in reqs]).contiguous()
             scal, grids = self.ctx.alloc_outputs(L, lam, J0, B)
             ws = self.ws[slot]
-            if ws is None or ws.numel() < api.workspace_bytes(L, lam, J0, B):
+            if ws is None or ws.numel() < api.workspace_bytes(L, lam, J0, B,
+                                                              unrotated=self.unrotated):
                 raise RuntimeError("band-limit %d was not prepared" % L)
             flat = [g for per in grids for g in per]
             import ctypes
             arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
             out = t.empty((B, L, 2 * L - 1), dtype=t.float64, device=self.dev)
-            p = api.params(L, lam, J0)
+            p = api.params(L, lam, J0, unrotated=self.unrotated)
             s = ctypes.c_void_p(st.cuda_stream)
             api._check(api.lib.cvl_curvelet_analysis(self.ctx.h, ctypes.byref(p), B, maps.data_ptr(),
                                                      scal.data_ptr(), arr, ws.data_ptr(), ws.numel(), s))
@@ -239,15 +244,18 @@ def main():
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.7, 0.9])
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--bandlimits", type=int, nargs="+", default=[64, 128, 256, 512])
+    ap.add_argument("--unrotated", action="store_true",
+                    help="serve the coefficients of the unrotated curvelets")
     args = ap.parse_args()
-    server = CurveletServer(L_max=max(args.bandlimits), slots=args.slots)
+    server = CurveletServer(L_max=max(args.bandlimits), slots=args.slots,
+                            unrotated=args.unrotated)
     server.prepare(args.bandlimits)
     _, Ls = inputs.serving_trace(args.requests, tuple(args.bandlimits), 1.0, seed_arrivals=1,
                                  seed_sizes=2)
     cap = measure_capacity(server, Ls)
     print("capacity %.1f req/s" % cap, file=sys.stderr, flush=True)
     out = {"capacity_req_per_s": cap, "slots": args.slots, "budget_bytes": server.budget,
-           "bandlimits": args.bandlimits, "runs": []}
+           "bandlimits": args.bandlimits, "unrotated": bool(args.unrotated), "runs": []}
     for rho in args.loads:
         arr, Ls = inputs.serving_trace(args.requests, tuple(args.bandlimits), rho * cap,
                                        seed_arrivals=1, seed_sizes=2)

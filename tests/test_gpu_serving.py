@@ -51,3 +51,31 @@ def test_budget_serialises_when_tight():
             assert b.admitted >= a.done - 1e-9
     finally:
         srv.close()
+
+
+def test_unrotated_server_alone_equals_in_mix():
+    # A server of unrotated-curvelet coefficients: each request's result is
+    # bitwise the library's direct unrotated call, and reconstructs exactly.
+    Ls = [32, 16, 32, 16, 64, 32]
+    arrivals = np.cumsum([0.0, 1e-4, 0, 3e-4, 0, 1e-3])
+    srv = serving.CurveletServer(L_max=64, slots=3, max_batch=2, keep_grids=True,
+                                 unrotated=True)
+    try:
+        srv.prepare(set(Ls))
+        reqs = serving.make_requests(srv, len(Ls), Ls, arrivals, seed_base=300)
+        done = srv.run(reqs)
+        assert len(done) == len(Ls)
+        ctx = srv.ctx
+        for r in sorted(done, key=lambda r: r.rid):
+            scal, grids = ctx.curvelet_analysis(r.fmap, unrotated=True)
+            rec = ctx.curvelet_synthesis(scal, grids, r.L, unrotated=True)
+            torch.cuda.synchronize()
+            assert torch.equal(rec, r.out), r.rid
+            for a, b in zip(grids, r.grids):
+                assert torch.equal(a, b)
+            _, rot = ctx.curvelet_analysis(r.fmap)
+            assert not torch.equal(rot[-1], r.grids[-1])
+            err = (torch.linalg.norm(rec - r.fmap) / torch.linalg.norm(r.fmap)).item()
+            assert err < 1e-10
+    finally:
+        srv.close()
