@@ -28,8 +28,8 @@ curvelets on the sphere", IEEE TSP 65(1), 2017):
   the forward direction.
 
 Every function cites the passage it follows.  The pins that tie each function
-to something other than itself live in ``tests/test_oracle_*.py``.  The only
-part with no pin beyond two independent quadratures is the absolute value of
-the k_lambda integral (no closed form exists): "parity unpinned" for that
-single number, see ``kernels``.
+to something other than itself live in ``tests/test_oracle_*.py``.  The
+k_lambda integral has no closed form; its integrand is pinned by values the
+definition fixes and by the ratio of k_lambda's slopes at two points (see
+``kernels``), so every function here has a pin.
 """

@@ -5,8 +5,10 @@ Test infrastructure (see ``oracle/__init__.py``).
 * ``s_bump``, ``s_lambda``: the Schwartz bump and its mapped form.
 * ``k_lambda``: ratio of two integrals of s_lambda(t)^2 / t, evaluated by
   tanh-sinh quadrature (mpmath) at 30 significant digits.  No closed form
-  exists, so the absolute value of this integral is pinned only by a second,
-  independent quadrature in the tests ("parity unpinned" beyond that).
+  exists; the tests pin the integrand by values the definition fixes (s and
+  s_lambda at the ends, the midpoint and x = +-1/2) and by the ratio of the
+  slopes of k_lambda at two points, which equals the ratio of the integrand
+  there (k' = -integrand / denominator), plus a second, independent quadrature.
 * ``kappa(j, l)`` = kappa_lambda(l / lambda^j),
   kappa_lambda(t) = sqrt(k_lambda(t / lambda) - k_lambda(t)).
 * ``phi_l0(l)`` = sqrt((2l+1)/(4 pi)) sqrt(k_lambda(l / lambda^J0)).

@@ -132,3 +132,56 @@ def test_scale_parameters():
     assert [kernels.scale_bandlimit(j, 256, 2.0) for j in range(2, 9)] == \
         [8, 16, 32, 64, 128, 256, 256]
     assert kernels.scaling_bandlimit(256, 2.0, 2) == 4
+
+
+# ---- pins of the integrand of k_lambda (Sec. II-B) by values the definition fixes ----
+# s(x) = exp(-1/(1-x^2)) on (-1, 1): s(0) = e^-1, s(1/2) = e^(-4/3), s(+-1) = 0.
+# s_lambda(t) = s(2 lambda/(lambda-1) (t - 1/lambda) - 1) maps t = 1/lambda to
+# x = -1, t = 1 to x = +1 and the midpoint (1 + 1/lambda)/2 to x = 0.
+
+def test_s_bump_values():
+    assert float(kernels.s_bump(0)) == pytest.approx(math.exp(-1.0), rel=1e-15)
+    assert float(kernels.s_bump(0.5)) == pytest.approx(math.exp(-4.0 / 3.0), rel=1e-15)
+    assert float(kernels.s_bump(-0.5)) == pytest.approx(math.exp(-4.0 / 3.0), rel=1e-15)
+    assert float(kernels.s_bump(1)) == 0.0 and float(kernels.s_bump(-1)) == 0.0
+    assert float(kernels.s_bump(1.5)) == 0.0
+
+
+@pytest.mark.parametrize("lam", [1.5, 2.0, 3.0])
+def test_s_lambda_values(lam):
+    assert float(kernels.s_lambda(1 / lam, lam)) == 0.0
+    assert float(kernels.s_lambda(1.0, lam)) == 0.0
+    mid = (1 + 1 / lam) / 2
+    assert float(kernels.s_lambda(mid, lam)) == pytest.approx(math.exp(-1.0), rel=1e-14)
+    # x = +-1/2 at t = 1/lambda + (1 +- 1/2)(lambda-1)/(2 lambda)
+    for x in (-0.5, 0.5):
+        t = 1 / lam + (x + 1) * (lam - 1) / (2 * lam)
+        assert float(kernels.s_lambda(t, lam)) == pytest.approx(math.exp(-4.0 / 3.0), rel=1e-13)
+    # zero outside (1/lambda, 1)
+    assert float(kernels.s_lambda(0.99 / lam, lam)) == 0.0
+    assert float(kernels.s_lambda(1.01, lam)) == 0.0
+
+
+@pytest.mark.parametrize("lam", [1.5, 2.0, 3.0])
+def test_k_lambda_strictly_decreasing_inside(lam):
+    ts = np.linspace(1 / lam, 1.0, 23)[1:-1]
+    ks = [kernels.k_lambda(t, lam) for t in ts]
+    assert all(0.0 < k < 1.0 for k in ks)
+    assert all(a > b for a, b in zip(ks, ks[1:]))
+
+
+@pytest.mark.parametrize("lam", [1.5, 2.0, 3.0])
+def test_k_lambda_slope_ratio(lam):
+    # k_lambda(t) = int_t^1 g / int_{1/lambda}^1 g with g(u) = s_lambda(u)^2 / u, so
+    # k'(t) = -g(t) / D and the ratio of slopes at two points is g(t_a) / g(t_b),
+    # which the definition fixes without any quadrature: at the midpoint t_a
+    # g = e^-2 / t_a, at x = 1/2 (t_b) g = e^(-8/3) / t_b.  The slopes are taken
+    # from the oracle's k_lambda by central differences (error O(h^2)).
+    ta = (1 + 1 / lam) / 2
+    tb = 1 / lam + 1.5 * (lam - 1) / (2 * lam)
+    h = 1e-4 * (1 - 1 / lam)
+    slope = lambda t: (kernels.k_lambda(t + h, lam) - kernels.k_lambda(t - h, lam)) / (2 * h)
+    ratio = slope(ta) / slope(tb)
+    expect = (math.exp(-2.0) / ta) / (math.exp(-8.0 / 3.0) / tb)
+    assert ratio == pytest.approx(expect, rel=1e-6)
+    assert slope(ta) < 0
