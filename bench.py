@@ -200,6 +200,25 @@ def whole_roofline(L, lam, J0, prec, NB, GB, ms, unrot=False):
             "dft_flops": dft}
 
 
+def rule_roofline(stage, Lj, GB, flops_per_launch, t_launch, peak_tf):
+    """Roofline of one launch by the measurement rule: the algorithmic bytes
+    are the grid elements a launch writes (analysis) or reads (synthesis) once
+    -- only the gamma DFT stages touch the grids, one scale's grid per launch,
+    (2L_j-1) x L_j x (2L_j-1) elements of GB bytes -- and the algorithmic flops
+    those the method needs (``stage_models``).  A stage without grid IO is
+    priced by its flops against the matrix cores (contractions, beta GEMMs) or
+    the vector units (the other DFT stages)."""
+    if stage.startswith("gamma"):
+        nbytes = (2 * Lj - 1) * Lj * (2 * Lj - 1) * GB
+        r = {"bound": "hbm", "achieved": nbytes / t_launch / 1e9, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "bytes_per_launch": nbytes}
+    else:
+        r = {"bound": "mfma" if stage.startswith(("contract", "beta_gemm")) else "alu",
+             "achieved": flops_per_launch / t_launch / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
+
+
 def bluestein_size(Lj):
     n = 2 * (2 * Lj - 1) - 1
     P = 8
@@ -286,6 +305,137 @@ def grid_bytes(L, lam=2.0, J0=2, B=16.0):
     return sum(g["Nm"] * g["L"] * g["Nm"] * B for g in scale_geoms(L, lam, J0))
 
 
+def point_source_flm(L, theta, phi, amp):
+    """Harmonic coefficients sum_k amp_k conj(Y_lm(theta_k, phi_k)) of
+    band-limited point sources (flat, length L^2), for building the large
+    workload's input.  Y_lm from the fully normalised associated Legendre
+    functions (Condon-Shortley phase), by the standard recurrences:
+    P_00 = 1/sqrt(4 pi), P_mm = -sqrt((2m+1)/(2m)) sin(t) P_{m-1,m-1},
+    P_{m+1,m} = sqrt(2m+3) cos(t) P_mm and, for l >= m+2,
+    P_lm = a (cos(t) P_{l-1,m} - b P_{l-2,m}) with a = sqrt((4l^2-1)/(l^2-m^2)),
+    b = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)); vectorised over m and the sources."""
+    import numpy as np
+    x = np.cos(np.asarray(theta, dtype=np.float64))[None, :]
+    sx = np.sin(np.asarray(theta, dtype=np.float64))[None, :]
+    K = x.shape[1]
+    m = np.arange(L, dtype=np.float64)[:, None]
+    fac = np.ones((L, 1))
+    fac[1:, 0] = -np.sqrt((2 * m[1:, 0] + 1) / (2 * m[1:, 0]))
+    steps = fac * sx * np.ones((L, K))
+    steps[0] = 1.0
+    diag = np.cumprod(steps, axis=0) / math.sqrt(4 * math.pi)  # P_mm
+    ph = np.exp(-1j * np.outer(np.arange(L), np.asarray(phi, dtype=np.float64)))  # [m, k]
+    w = ph * np.asarray(amp, dtype=np.float64)[None, :]
+    out = np.zeros(L * L, dtype=np.complex128)
+    p2 = np.zeros((L, K))
+    p1 = np.zeros((L, K))
+    for l in range(L):
+        p0 = np.zeros((L, K))
+        if l >= 2:
+            mm = m[:l - 1]
+            a = np.sqrt((4.0 * l * l - 1) / (l * l - mm * mm))
+            b = np.sqrt(((l - 1.0) ** 2 - mm * mm) / (4.0 * (l - 1) ** 2 - 1))
+            p0[:l - 1] = a * (x * p1[:l - 1] - b * p2[:l - 1])
+        if l >= 1:
+            p0[l - 1] = math.sqrt(2 * l + 1) * x[0] * diag[l - 1]
+        p0[l] = diag[l]
+        vals = np.sum(p0[:l + 1] * w[:l + 1], axis=1)  # m = 0..l
+        base = l * l + l
+        out[base:base + l + 1] = vals
+        ms = np.arange(1, l + 1)
+        out[base - ms] = ((-1.0) ** ms) * np.conj(vals[1:])
+        p2, p1 = p1, p0
+    return out
+
+
+def large_leg(steps=3, L=1024, n_sources=64):
+    """The large workload: one real map at L = 1024 (Gaussian field, seed 0,
+    plus 64 band-limited point sources, seed 1, peaks 1..10 x the field's rms)
+    through the streaming interface (one complex64 grid resident at a time),
+    FP32 MFMA contractions, FP64 Delta and final accumulation.  One warm-up
+    round trip, then `steps` timed ones."""
+    import torch
+    from paper_1511_05578_amd import api, inputs
+    lam, J0 = 2.0, 2
+    t_setup = time.perf_counter()
+    ctx = api.Context(L, 0)
+    try:
+        ctx.prepare(L, lam, J0)
+        f = inputs.gaussian_real_flm(L, seed=0)
+        th, ph, a = inputs.point_sources(n_sources, seed=1)
+        f = f + point_source_flm(L, th, ph, inputs.source_amplitudes(a, f, L))
+        fmap = ctx.sht_inverse(torch.from_numpy(f).cuda(), L)
+        rec, _ = ctx.round_trip_streamed(fmap, lam, J0, precision="fp32")
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t_setup
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rec, _ = ctx.round_trip_streamed(fmap, lam, J0, precision="fp32")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = (torch.linalg.norm(rec - fmap) / torch.linalg.norm(fmap)).item()
+        del rec, fmap
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+        torch.cuda.empty_cache()
+    return {"workload": "1 real spin-0 map with %d point sources, L=%d, lambda=2, J0=2, J=%d, "
+                        "complex64 grids streamed one scale at a time, FP32 MFMA contractions, "
+                        "FP64 Delta and final accumulation" % (n_sources, L, api.num_scales(L)),
+            "value": 1e3 / ms, "unit": "transforms/s", "ms_per_step": ms, "steps": steps,
+            "warmup": 1, "round_trip_rel_l2": err, "setup_s": setup_s}
+
+
+def serving_leg(n=128, rho=0.7, bandlimits=(64, 128, 256, 512), slots=4):
+    """The serving workload on a short trace: closed-loop capacity of the
+    continuous-batching server (4 stream slots, same-L batching, HBM admission)
+    and of the plain path (one request at a time, one slot, no batching), then
+    `n` requests with Poisson arrivals (seed 1) at `rho` x the server's
+    capacity and band-limits uniform over `bandlimits` (seed 2), served by both:
+    throughput and p50 / p99 latency."""
+    import torch
+    from paper_1511_05578_amd import inputs, serving
+    out = {"requests": n, "load": rho, "bandlimits": list(bandlimits)}
+    _, Ls_cap = inputs.serving_trace(64, tuple(bandlimits), 1.0, seed_arrivals=1, seed_sizes=2)
+    res = {}
+    for name, nslots, mb in (("served", slots, 4), ("plain", 1, 1)):
+        srv = serving.CurveletServer(L_max=max(bandlimits), slots=nslots, max_batch=mb)
+        try:
+            srv.prepare(bandlimits)
+            cap = serving.measure_capacity(srv, Ls_cap, n=32 if nslots == 1 else 64)
+            res[name] = {"capacity_req_per_s": cap, "slots": nslots, "max_batch": mb}
+            if name == "served":
+                rate = rho * cap
+            arr, Ls = inputs.serving_trace(n, tuple(bandlimits), rate, seed_arrivals=1,
+                                           seed_sizes=2)
+            reqs = serving.make_requests(srv, n, Ls, arr)
+            t0 = time.perf_counter()
+            done = srv.run(reqs)
+            wall = time.perf_counter() - t0
+            st = serving.latency_stats(done)
+            st["served_req_per_s"] = len(done) / wall
+            res[name].update(st)
+            del reqs, done
+        finally:
+            srv.close()
+            torch.cuda.empty_cache()
+    out["offered_req_per_s"] = rate
+    out.update(res)
+    return out
+
+
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(L, lam=2.0, J0=2, unrot=False):
     """Oracle round-trip time at this workload, from a bounded sample: one beta
     row per scale of the analysis and one Gauss-Legendre node per scale of the
@@ -297,6 +447,15 @@ def cpu_baseline(L, lam=2.0, J0=2, unrot=False):
     from oracle import sht as osht
     from paper_1511_05578_amd import inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:  # the BLAS pool the oracle's matrix products actually use
+        import threadpoolctl
+        np.ones((64, 64)) @ np.ones((64, 64))
+        pools = [p["num_threads"] for p in threadpoolctl.threadpool_info()
+                 if p.get("user_api") == "blas"]
+        if pools:
+            threads = max(pools)
+    except ImportError:
+        pass
     plan = ocurv.Plan(L, lam, J0, rotated=not unrot)
     f = inputs.gaussian_real_flm(L, seed=0)
     t_an = 0.0
@@ -327,6 +486,7 @@ def cpu_baseline(L, lam=2.0, J0=2, unrot=False):
     wall = time.perf_counter() - t0
     t_total = t_an + t_sy + 2 * t_sht
     return {"value": 1.0 / t_total, "unit": "transforms/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "L=%d: 1 beta row per scale of the analysis and 1 Gauss-Legendre node per "
                       "scale of the synthesis (with its full alpha/gamma step), extrapolated by "
                       "rows/nodes per scale, plus one SHT pair; %.1f s sampled, estimated %.1f s "
@@ -353,6 +513,8 @@ def main():
                     help="also capture one step in a HIP graph and report its replay time "
                          "(graph_replay_ms_per_step; not the headline value)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the secondary workloads (L=1024 streamed FP32, serving trace)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after timing, copy BYTES of device memory once (a plain copy kernel "
                          "of known size, for scaling hardware byte counters)")
@@ -377,12 +539,11 @@ def main():
         sys.exit(2)
 
     def make_map(s):
-        m = ctx.sht_inverse(torch.from_numpy(inputs.gaussian_real_flm(L, seed=s)).cuda(), L)
+        f = inputs.gaussian_real_flm(L, seed=s)
         if args.point_sources:
-            raw = inputs.add_point_sources(m.cpu().numpy(),
-                                           inputs.point_sources(L, args.point_sources, seed=100 + s))
-            m = ctx.sht_inverse(ctx.sht_forward(torch.from_numpy(raw).cuda()), L)
-        return m
+            th, ph, a = inputs.point_sources(args.point_sources, seed=100 + s)
+            f = f + point_source_flm(L, th, ph, inputs.source_amplitudes(a, f, L))
+        return ctx.sht_inverse(torch.from_numpy(f).cuda(), L)
 
     maps = torch.stack([make_map(s) for s in range(NB)]).contiguous()
     rec = torch.empty((NB, L, 2 * L - 1), dtype=torch.float64, device="cuda")
@@ -483,15 +644,12 @@ def main():
     bytes_per_launch = nb / nscales  # one launch per scale per map
     flops_per_launch = nf / nscales
     peak_tf = stage_peak(top[0], prec)
-    ai = nf / max(nb, 1.0)
-    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if ai < ridge:
-        roof = {"bound": "hbm", "achieved": bytes_per_launch / t_top / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
-    else:
-        roof = {"bound": "mfma" if top[0].startswith(("contract", "beta")) else "alu",
-                "achieved": flops_per_launch / t_top / 1e12, "peak": peak_tf, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof = rule_roofline(top[0], top[1], GB, flops_per_launch, t_top, peak_tf)
+    # the same launch priced by its whole stage IO (input plane read once and
+    # output written once), which the measurement rule does not count
+    roof["stage_io"] = {"bytes": bytes_per_launch,
+                        "achieved_GBs": bytes_per_launch / t_top / 1e9,
+                        "frac_hbm": bytes_per_launch / t_top / 1e9 / HBM_PEAK_GBS}
     wkey = "L%d_b%d_%s%s%s%s%s" % (L, NB, prec, "_stream" if args.stream else "",
                                    "_ps%d" % args.point_sources if args.point_sources else "",
                                    "_rg" if RG else "", "_unrot" if UR else "")
@@ -565,6 +723,15 @@ def main():
                                         "grids_max_abs_rel": mx / mref,
                                         "rows": "beta row L_j/2 of every scale, map 0"}
     ctx.close()
+    del grids
+    torch.cuda.empty_cache()
+    if not args.no_legs and args.L == 256 and NB == 1 and prec == "fp64" and not UR \
+            and not args.stream:
+        # the other configurations of the metric, measured in the same run
+        print("large workload (L=1024 streamed FP32)", file=sys.stderr, flush=True)
+        out["large"] = large_leg()
+        print("serving trace", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg()
     print(json.dumps(out), flush=True)
 
 

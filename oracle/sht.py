@@ -88,3 +88,18 @@ def forward(fmap, L):
         for m in range(-l, l + 1):
             flm[lm_index(l, m)] = c * acc[l, m + L - 1]
     return flm
+
+
+def point_source_flm(L, theta, phi, amp):
+    """f_lm = sum_k amp_k conj(Y_lm(theta_k, phi_k)), l < L (flat, length L^2):
+    the band-limited point sources of amplitudes amp_k at the given positions
+    (the projection of amp_k delta(omega - omega_k) onto Y_lm, Sec. II-A), with
+    Y_lm = sqrt((2l+1)/(4pi)) d^l_{m0}(theta) e^{i m phi} from ``wigner.d_iter``."""
+    out = np.zeros(L * L, dtype=np.complex128)
+    ms = np.arange(-(L - 1), L)
+    for th, ph, a in zip(theta, phi, amp):
+        e = np.exp(-1j * ms * ph)
+        for l, D in wigner.d_iter(L, th, L, 1):
+            row = a * math.sqrt((2 * l + 1) / (4 * math.pi)) * D[:, 0] * e
+            out[l * l: (l + 1) * (l + 1)] += row[L - 1 - l: L + l]
+    return out

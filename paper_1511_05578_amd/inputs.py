@@ -57,29 +57,27 @@ def serving_trace(n_requests=1024, bandlimits=(64, 128, 256, 512), rate_hz=100.0
     return t, Ls
 
 
-def point_sources(L, n=64, seed=1):
-    """n point sources uniform on the sphere, snapped to MW samples of band-limit L.
+def point_sources(n=64, seed=1):
+    """n point sources uniform on the sphere with relative amplitudes.
 
     Draws cos(theta) ~ U[-1, 1], phi ~ U[0, 2 pi) and a relative amplitude
     a ~ U[1, 10] per source from ``numpy.random.default_rng(seed)`` (all
-    cos(theta), then all phi, then all a).  Returns (t, p, a): the nearest MW
-    sample indices (theta_t = pi(2t+1)/(2L-1), phi_p = 2 pi p/(2L-1)) and a."""
+    cos(theta), then all phi, then all a).  Returns (theta, phi, a)."""
     rng = np.random.default_rng(seed)
     ct = rng.uniform(-1.0, 1.0, size=n)
     ph = rng.uniform(0.0, 2.0 * np.pi, size=n)
     amp = rng.uniform(1.0, 10.0, size=n)
-    theta = np.arccos(ct)
-    t = np.clip(np.rint((theta * (2 * L - 1) / np.pi - 1.0) / 2.0), 0, L - 1).astype(np.int64)
-    p = np.rint(ph * (2 * L - 1) / (2.0 * np.pi)).astype(np.int64) % (2 * L - 1)
-    return t, p, amp
+    return np.arccos(ct), ph, amp
 
 
-def add_point_sources(fmap, sources):
-    """fmap (L x (2L-1) samples, modified in place) plus, at each source's
-    sample, a spike of height a * rms(fmap) (rms of the samples before any
-    source is added); returns fmap.  The result is not band-limited: consumers
-    project it onto band-limit L with their own SHT pair."""
-    t, p, amp = sources
-    rms = float(np.sqrt(np.mean(fmap * fmap)))
-    np.add.at(fmap, (t, p), amp * rms)
-    return fmap
+def source_amplitudes(a, field_flm, L):
+    """Harmonic amplitudes A_k of band-limited point sources whose peaks are
+    a_k times the rms of the field with coefficients ``field_flm``.
+
+    A source A conj(Y_lm(omega_k)) (l < L) peaks at omega_k with height
+    A L^2 / (4 pi) (the sum over l < L and |m| <= l of |Y_lm|^2), and the rms
+    of a field over the sphere is sqrt(sum |f_lm|^2 / (4 pi)) (Parseval), so
+    A_k = a_k rms 4 pi / L^2.  The coefficients themselves,
+    sum_k A_k conj(Y_lm(omega_k)), are formed by each consumer."""
+    rms = float(np.sqrt(np.sum(np.abs(field_flm) ** 2) / (4.0 * np.pi)))
+    return np.asarray(a, dtype=np.float64) * rms * 4.0 * np.pi / (L * L)

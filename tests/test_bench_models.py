@@ -2,6 +2,7 @@
 names, against brute-force enumeration of the unrotated cube."""
 import math
 
+import numpy as np
 import pytest
 
 import bench
@@ -72,3 +73,17 @@ def test_kernel_symbols():
     assert bench.kernel_symbol("beta_gemm_fwd", 256, "fp32") == "k_beta_mfma_f32"
     assert bench.bluestein_size(256) == 1024 and bench.bluestein_size(1024) == 4096
     assert math.isclose(bench.stage_peak("contract_inv", "bf16x3"), bench.BF16_MFMA_PEAK_TFLOPS)
+
+
+def test_bench_point_sources_match_library_ylm():
+    # the benchmark's own Legendre recurrence for its large workload's input
+    import scipy.special as sps
+    L = 20
+    th = np.array([0.05, 1.3, 3.1])
+    ph = np.array([0.2, 3.3, 6.0])
+    amp = np.array([2.0, 1.0, 0.5])
+    f = bench.point_source_flm(L, th, ph, amp)
+    for l in range(L):
+        for m in range(-l, l + 1):
+            ref = np.sum(amp * np.conj(sps.sph_harm_y(l, m, th, ph)))
+            assert abs(f[l * l + l + m] - ref) < 1e-13

@@ -107,18 +107,17 @@ def test_scale_workspace_is_enough_for_the_per_scale_calls(ctx):
 
 
 def test_point_sources_against_oracle(ctx):
-    # Gaussian field plus 64 point sources, projected onto band-limit L by each
-    # side's own SHT pair, then analysed by both.
+    # Gaussian field plus 64 band-limited point sources (harmonic form, built
+    # by the oracle), analysed by both sides.
     L, lam, J0 = 64, 2.0, 2
     say("point sources L=%d" % L)
-    base = osht.inverse(inputs.gaussian_real_flm(L, 21), L).real
-    raw = inputs.add_point_sources(base.copy(), inputs.point_sources(L, 64, seed=4))
-    f_or = osht.forward(raw, L)
+    f = inputs.gaussian_real_flm(L, 21)
+    th, ph, a = inputs.point_sources(64, seed=4)
+    f_or = f + osht.point_source_flm(L, th, ph, inputs.source_amplitudes(a, f, L))
     plan = ocurv.Plan(L, lam, J0)
     ref_scal, ref_grids = ocurv.analysis(plan, f_or)
-    flm = ctx.sht_forward(dev(raw))
-    assert rel_l2(host(flm), f_or) < 1e-10
-    gmap = ctx.sht_inverse(flm, L)
+    gmap = ctx.sht_inverse(dev(f_or), L)
+    assert rel_l2(host(ctx.sht_forward(gmap)), f_or) < 1e-10
     scal, grids = ctx.curvelet_analysis(gmap, lam, J0)
     for s, j in enumerate(plan.scales):
         e = rel_l2(host(grids[s]), ref_grids[j])
@@ -128,26 +127,34 @@ def test_point_sources_against_oracle(ctx):
     assert rel_l2(rec, host(gmap)) < 1e-10
 
 
+@pytest.mark.timeout(1200)
 def test_l1024_fp32_streamed_point_sources():
     # Band-limit 1024, Gaussian field plus 64 point sources, complex64 grids
     # one scale at a time (a single 34 GB grid buffer), FP32 MFMA contractions,
-    # FP64 Delta and final accumulation; then the same with real (float32)
-    # grids, which hold the same real parts in half the memory.
-    L, lam, J0 = 1024, 2.0, 2
+    # FP64 Delta and final accumulation: one beta row of a finest scale against
+    # the oracle, the round trip, the peak device memory; then the same with
+    # real (float32) grids, which hold the same real parts in half the memory.
+    import l1024_case as case
+    L, lam, J0 = case.L, case.LAM, case.J0
     free, total = torch.cuda.mem_get_info()
     if free < 120 * 2**30:
         pytest.skip("needs about 110 GB of free device memory")
+    say("L=1024 fp32 streamed: oracle row (background)")
+    case.start_oracle_row()
     c = api.Context(L, 0)
     try:
         say("L=1024 fp32 streamed: input")
-        f = inputs.gaussian_real_flm(L, seed=5)
-        base = c.sht_inverse(dev(f), L).cpu().numpy()
-        raw = inputs.add_point_sources(base, inputs.point_sources(L, 64, seed=9))
-        fmap = c.sht_inverse(c.sht_forward(dev(raw)), L)
+        fmap = c.sht_inverse(dev(case.flm()), L)
         torch.cuda.reset_peak_memory_stats()
         before = torch.cuda.memory_allocated()
         say("L=1024 fp32 streamed: round trip")
-        rec, scal = c.round_trip_streamed(fmap, lam, J0, precision="fp32")
+        rows = {}
+
+        def keep_row(j, g):
+            if j == case.SCALE:
+                rows[j] = g[:, case.ROW, :].cpu().numpy()
+
+        rec, scal = c.round_trip_streamed(fmap, lam, J0, precision="fp32", on_grid=keep_row)
         torch.cuda.synchronize()
         peak = (torch.cuda.max_memory_allocated() - before) / 2**30
         e = (torch.linalg.norm(rec - fmap) / torch.linalg.norm(fmap)).item()
@@ -156,6 +163,13 @@ def test_l1024_fp32_streamed_point_sources():
         # one grid (32 GiB) + the FP32 workspace (16 GiB), not all scales'
         # grids (68.5 GiB)
         assert peak < 56
+        say("L=1024 fp32 streamed: waiting for the oracle row")
+        ref = case.oracle_row()
+        g = rows[case.SCALE][:, None, :]
+        e = rel_l2(g, ref)
+        mx = np.abs(g - ref).max() / np.abs(ref).max()
+        say("  scale %d row %d vs oracle: rel L2 %.2e, max-abs rel %.2e" % (case.SCALE, case.ROW, e, mx))
+        assert e < 1e-5 and mx < 1e-5
         say("L=1024 fp32 streamed, real grids: round trip")
         torch.cuda.reset_peak_memory_stats()
         before = torch.cuda.memory_allocated()

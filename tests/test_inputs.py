@@ -5,23 +5,23 @@ from paper_1511_05578_amd import inputs
 
 
 def test_point_sources_seeded_and_uniform_on_sphere():
-    L = 64
-    t, p, a = inputs.point_sources(L, 4000, seed=3)
-    assert t.min() >= 0 and t.max() < L and p.min() >= 0 and p.max() < 2 * L - 1
+    th, ph, a = inputs.point_sources(4000, seed=3)
+    assert np.all((th >= 0) & (th <= np.pi)) and np.all((ph >= 0) & (ph < 2 * np.pi))
     assert np.all((a >= 1.0) & (a <= 10.0))
-    t2, p2, a2 = inputs.point_sources(L, 4000, seed=3)
-    assert np.array_equal(t, t2) and np.array_equal(p, p2) and np.array_equal(a, a2)
+    th2, ph2, a2 = inputs.point_sources(4000, seed=3)
+    assert np.array_equal(th, th2) and np.array_equal(ph, ph2) and np.array_equal(a, a2)
     # uniform on the sphere: about half the sources in the polar caps |cos theta| > 1/2
-    ct = np.cos(np.pi * (2 * t + 1) / (2 * L - 1))
-    assert 0.45 < np.mean(np.abs(ct) > 0.5) < 0.55
+    assert 0.45 < np.mean(np.abs(np.cos(th)) > 0.5) < 0.55
 
 
-def test_add_point_sources():
-    m = np.ones((8, 15))
-    src = (np.array([0, 3, 3]), np.array([1, 2, 2]), np.array([2.0, 3.0, 4.0]))
-    inputs.add_point_sources(m, src)
-    assert m[0, 1] == 3.0 and m[3, 2] == 8.0
-    assert np.isclose(m.sum(), 120 + 9.0)
+def test_source_amplitudes():
+    # a field with only f_00 = c is the constant c Y_00 = c / sqrt(4 pi): its rms
+    L = 16
+    f = np.zeros(L * L, dtype=np.complex128)
+    f[0] = 3.0
+    A = inputs.source_amplitudes(np.array([1.0, 2.0]), f, L)
+    rms = 3.0 / np.sqrt(4 * np.pi)
+    assert np.allclose(A, np.array([1.0, 2.0]) * rms * 4 * np.pi / L ** 2, rtol=1e-15)
 
 
 def test_gaussian_flm_reality_and_variance():

@@ -66,3 +66,22 @@ def test_real_input_generator_symmetry():
         assert abs(f[l * l + l].imag) == 0.0
         for m in range(1, l + 1):
             assert f[l * l + l - m] == (-1) ** m * np.conj(f[l * l + l + m])
+
+
+def test_point_source_flm_library_and_peak():
+    # sum_k A_k conj(Y_lm(omega_k)) against the library Y_lm, and the peak of
+    # the band-limited source: sum_lm |Y_lm(omega)|^2 = L^2 / (4 pi) (addition
+    # theorem), so a single source of amplitude A is A L^2 / (4 pi) at omega.
+    L = 12
+    th = np.array([0.4, 2.0])
+    ph = np.array([1.0, 5.5])
+    amp = np.array([1.5, -0.5])
+    f = sht.point_source_flm(L, th, ph, amp)
+    for l in range(L):
+        for m in range(-l, l + 1):
+            ref = np.sum(amp * np.conj(sps.sph_harm_y(l, m, th, ph)))
+            assert abs(f[sht.lm_index(l, m)] - ref) < 1e-14
+    one = sht.point_source_flm(L, th[:1], ph[:1], np.array([2.0]))
+    val = sum(one[sht.lm_index(l, m)] * sps.sph_harm_y(l, m, th[0], ph[0])
+              for l in range(L) for m in range(-l, l + 1))
+    assert abs(val - 2.0 * L * L / (4 * np.pi)) < 1e-12
