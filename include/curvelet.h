@@ -1,5 +1,5 @@
 /*
- * curvelet.h - C ABI of the MI355X (gfx950) spin-0 spherical curvelet transform.
+ * curvelet.h - C ABI of the MI355X (gfx950) spherical curvelet transform.
  *
  * Transform: second-generation scale-discretised curvelets on the sphere
  * (Chan, Leistedt, Kitching, McEwen, IEEE TSP 65(1), 2017).  Every numerical
@@ -68,7 +68,7 @@ enum {
 };
 
 /* Flags of cvl_params. */
-#define CVL_REAL 1u        /* real map (f_{l,-m} = (-1)^m conj f_lm); required */
+#define CVL_REAL 1u        /* real map (f_{l,-m} = (-1)^m conj f_lm); unset: complex map */
 #define CVL_REAL_GRIDS 2u  /* curvelet grids of real elements (see cvl_curvelet_analysis) */
 #define CVL_UNROTATED 4u   /* coefficients of the unrotated curvelets (see cvl_curvelet_analysis) */
 
@@ -85,11 +85,15 @@ typedef struct cvl_ctx cvl_ctx;
 /* Curvelet parameters (Sec. II-B).  L: band-limit of the map (>= 2).
  * N: azimuthal band-limit of the curvelets; curvelets have none, so N must be
  * 0 or L (each scale then uses N_j = L_j).  lambda > 1: dilation.  J0 >= 1:
- * lowest curvelet scale, J0 <= J where J = ceil(log_lambda L).  spin: must
- * be 0.  precision: CVL_FP64, CVL_FP32 or CVL_BF16X3 (curvelet calls only;
- * it selects the grid element type).  flags: CVL_REAL (required), optionally
- * CVL_REAL_GRIDS and CVL_UNROTATED; other bits are rejected.  The workspace
- * size depends on CVL_UNROTATED (cvl_workspace_bytes). */
+ * lowest curvelet scale, J0 <= J where J = ceil(log_lambda L).  spin: the
+ * spin s of the signal and of the curvelets (Sec. II-A, II-B), |s| < L; a
+ * real map (CVL_REAL) has spin 0.  precision: CVL_FP64, CVL_FP32 or
+ * CVL_BF16X3 (curvelet calls only; it selects the grid element type).
+ * flags: CVL_REAL for a real map [t][p] of doubles (unset: a complex map of
+ * cvl_c128, with complex grids), optionally CVL_REAL_GRIDS (real maps only)
+ * and CVL_UNROTATED; other bits are rejected.  Spin s != 0 needs
+ * CVL_UNROTATED (CVL_EUNSUPPORTED otherwise).  The workspace size depends on
+ * CVL_UNROTATED and CVL_REAL (cvl_workspace_bytes). */
 typedef struct {
     int L;
     int N;
@@ -132,7 +136,8 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes);
  * parameters or a NULL `bytes`. */
 int cvl_scale_workspace_bytes(const cvl_params *p, size_t *bytes);
 
-/* Workspace bytes needed by the SHT (L) and Wigner (L, N) entry points. */
+/* Workspace bytes needed by the SHT (L; real and complex maps) and Wigner
+ * (L, N) entry points. */
 int cvl_sht_workspace_bytes(int L, size_t *bytes);
 int cvl_wigner_workspace_bytes(int L, int N, size_t *bytes);
 
@@ -151,6 +156,19 @@ int cvl_sht_forward(cvl_ctx *ctx, int L, int spin, const double *map,
 int cvl_sht_inverse(cvl_ctx *ctx, int L, int spin, const cvl_c128 *flm,
                     double *map, void *ws, size_t ws_bytes, void *stream);
 
+/* Forward spin-s SHT of a complex map (L x (2L-1) cvl_c128, MW sampling) to
+ * the f_lm of every m (flat, L^2 entries; zero for l < |s|):
+ * f_lm = <f, sY_lm> with sY_lm = (-1)^s sqrt((2l+1)/4pi) d^l_{m,-s}(theta)
+ * e^{i m phi} (Sec. II-A), exact for band-limited maps (the MW sampling
+ * theorem; Sec. III-A-2's steps with n = -s).  -L < spin < L. */
+int cvl_sht_forward_complex(cvl_ctx *ctx, int L, int spin, const cvl_c128 *map,
+                            cvl_c128 *flm, void *ws, size_t ws_bytes, void *stream);
+
+/* Inverse spin-s SHT: the complex map sum_lm f_lm sY_lm (every m read;
+ * entries with l < |s| ignored). */
+int cvl_sht_inverse_complex(cvl_ctx *ctx, int L, int spin, const cvl_c128 *flm,
+                            cvl_c128 *map, void *ws, size_t ws_bytes, void *stream);
+
 /* Inverse Wigner transform (Sec. II-A, Sec. III-A-2): complex grid
  * W(rho) = sum_lmn (2l+1)/(8pi^2) F^l_mn D^{l*}_mn(rho), general complex F,
  * 1 <= N <= L <= L_max. */
@@ -164,14 +182,19 @@ int cvl_wigner_inverse(cvl_ctx *ctx, int L, int N, const cvl_c128 *flmn,
 int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid,
                        cvl_c128 *flmn, void *ws, size_t ws_bytes, void *stream);
 
-/* Curvelet analysis (Sec. II-D-1) of `batch` real maps (contiguous,
- * batch x L x (2L-1) doubles).  Outputs per map i:
- *   scal_maps + i * L_Phi * (2L_Phi-1): the scaling coefficients as a real MW
- *     map of band-limit L_Phi;
+/* Curvelet analysis (Sec. II-D-1) of `batch` maps (contiguous, batch x L x
+ * (2L-1) doubles with CVL_REAL, else cvl_c128 of spin p->spin).  Outputs per
+ * map i:
+ *   scal_maps + i * L_Phi * (2L_Phi-1): the scaling coefficients as a spin-0
+ *     MW map of band-limit L_Phi (doubles for a real map, else cvl_c128);
  *   grids[i * nJ + (j - J0)], nJ = J - J0 + 1: SO(3) grid W^(j)[a][b][g] of
  *     scale j, (2L_j-1) x L_j x (2L_j-1), of cvl_c128 (CVL_FP64) or cvl_c64
  *     (CVL_FP32, CVL_BF16X3) elements.  For a real map the curvelet
- *     coefficients are real: the imaginary parts are written as 0.  With
+ *     coefficients are real: the imaginary parts are written as 0.  For a
+ *     complex map f = f_a + i f_b they are W_a + i W_b (the curvelets'
+ *     coefficients obey the reality condition): the two parts' coefficients
+ *     run through the real-signal stages and meet in one complex gamma DFT
+ *     per grid line, so a complex map costs two real maps.  With
  *     CVL_REAL_GRIDS the elements are double (CVL_FP64) or float instead,
  *     holding the same real parts: the conjugate symmetry of real signals
  *     halves the grids' memory and traffic (Sec. III-A-3).
@@ -185,25 +208,29 @@ int cvl_wigner_forward(cvl_ctx *ctx, int L, int N, const cvl_c128 *grid,
  *     element types and synthesis (exact reconstruction) with the same flag.
  * `grids` is a HOST array of batch * nJ device pointers. */
 int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
-                          const double *maps, double *scal_maps,
+                          const void *maps, void *scal_maps,
                           void *const *grids, void *ws, size_t ws_bytes,
                           void *stream);
 
 /* Curvelet synthesis (Sec. II-D-2, exact reconstruction): the inverse of
- * cvl_curvelet_analysis on its range.  Synthesis is linear, and a grid's
- * imaginary part only feeds the imaginary part of the synthesised map, so the
- * real map returned is the synthesis of the grids' real parts (the imaginary
- * parts are not used).  Writes `batch` real maps.  Same layouts (and
- * CVL_REAL_GRIDS element types) as cvl_curvelet_analysis. */
+ * cvl_curvelet_analysis on its range.  With CVL_REAL: synthesis is linear,
+ * and a grid's imaginary part only feeds the imaginary part of the
+ * synthesised map, so the real map returned is the synthesis of the grids'
+ * real parts (the imaginary parts are not used).  Without CVL_REAL the
+ * complex grids and scaling maps give complex maps of spin p->spin.  Writes
+ * `batch` maps.  Same layouts (and CVL_REAL_GRIDS element types) as
+ * cvl_curvelet_analysis. */
 int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch,
-                           const double *scal_maps, const void *const *grids,
-                           double *maps, void *ws, size_t ws_bytes, void *stream);
+                           const void *scal_maps, const void *const *grids,
+                           void *maps, void *ws, size_t ws_bytes, void *stream);
 
 /* Streaming interface: the same transform one scale at a time, so that only
  * one scale's grid need be resident (Sec. II-D; the synthesis is a sum over
  * scales in harmonic space, Sec. II-D-2).  flm / flm_acc are L^2 complex128
- * harmonic coefficients in the layout of cvl_sht_forward (negative m by the
- * reality condition).  Workspace: cvl_scale_workspace_bytes(p).  A round trip is
+ * harmonic coefficients in the layout of cvl_sht_forward (with CVL_REAL:
+ * negative m by the reality condition; else every m, as from
+ * cvl_sht_forward_complex, and the scaling maps are cvl_c128).  Workspace:
+ * cvl_scale_workspace_bytes(p).  A round trip is
  *   cvl_sht_forward(map) -> flm;  cvl_curvelet_scaling_analysis(flm) -> scal;
  *   per scale j: cvl_curvelet_analysis_scale(flm, j) -> grid,
  *                cvl_curvelet_synthesis_scale(grid, j) adds into flm_acc;
@@ -217,19 +244,20 @@ int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j,
                                 const cvl_c128 *flm, void *grid, void *ws,
                                 size_t ws_bytes, void *stream);
 
-/* flm_acc += f^(j)_lm, the synthesis of the real part of scale j's grid. */
+/* flm_acc += f^(j)_lm, the synthesis of scale j's grid (with CVL_REAL: of
+ * its real part). */
 int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j,
                                  const void *grid, cvl_c128 *flm_acc, void *ws,
                                  size_t ws_bytes, void *stream);
 
-/* Scaling coefficients: real MW map of band-limit L_Phi (Sec. II-D-1). */
+/* Scaling coefficients: spin-0 MW map of band-limit L_Phi (Sec. II-D-1). */
 int cvl_curvelet_scaling_analysis(cvl_ctx *ctx, const cvl_params *p,
-                                  const cvl_c128 *flm, double *scal_map,
+                                  const cvl_c128 *flm, void *scal_map,
                                   void *ws, size_t ws_bytes, void *stream);
 
 /* flm_acc += the scaling part of the synthesis (Sec. II-D-2). */
 int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p,
-                                   const double *scal_map, cvl_c128 *flm_acc,
+                                   const void *scal_map, cvl_c128 *flm_acc,
                                    void *ws, size_t ws_bytes, void *stream);
 
 /* Host copy of the kernel tables of `p` (no device work; usable without a

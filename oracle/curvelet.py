@@ -29,26 +29,41 @@ from . import kernels, sampling, sht, so3, wigner
 
 
 class Plan:
-    """Kernel tables for one (L, lambda, J0), spin 0.
+    """Kernel tables for one (L, lambda, J0, spin).
 
     ``rotated`` (default): the curvelets rotated so that they are centred on
-    the North pole (Sec. II-B), Psi from zeta = d(pi/2) zeta~.  With
-    rotated=False the unrotated curvelets (zeta~ itself, |n| = l only), whose
-    coefficients the fast algorithm of Sec. III-A computes:
-    W~(rho) = W(rho rho*^-1) with rho* = (0, pi/2, 0)."""
+    the North pole (Sec. II-B), Psi from zeta = d(theta_j) zeta~ with
+    theta_j = arccos(-s / lambda^j) (pi/2 for spin 0; clamped to [0, pi] at
+    the scales with lambda^j < |s|).  With rotated=False the unrotated
+    curvelets (zeta~ itself, |n| = l only), whose coefficients the fast
+    algorithm of Sec. III-A computes: W~(rho) = W(rho rho*^-1) with
+    rho* = (0, theta_j, 0).  zeta~, kappa and Phi do not depend on the spin;
+    the spin enters through the signal's spin harmonic coefficients and, for
+    rotated curvelets, through theta_j."""
 
-    def __init__(self, L, lam=2.0, J0=2, rotated=True):
+    def __init__(self, L, lam=2.0, J0=2, rotated=True, spin=0):
         self.L, self.lam, self.J0 = L, float(lam), J0
         self.rotated = bool(rotated)
+        self.spin = int(spin)
         self.J = kernels.num_scales(L, lam)
         if J0 > self.J:
             raise ValueError("J0 must not exceed J = ceil(log_lambda L)")
         self.scales = list(range(J0, self.J + 1))
         self.Lj = {j: kernels.scale_bandlimit(j, L, lam) for j in self.scales}
         self.Lphi = kernels.scaling_bandlimit(L, lam, J0)
-        theta = math.pi / 2 if rotated else 0.0
-        self.psi = kernels.psi_table(L, lam, J0, self.J, theta)  # [j-J0, l, n+L-1]
+        if not rotated:
+            self.psi = kernels.psi_table(L, lam, J0, self.J, 0.0)   # [j-J0, l, n+L-1]
+        elif self.spin == 0:
+            self.psi = kernels.psi_table(L, lam, J0, self.J, math.pi / 2)
+        else:
+            self.psi = np.stack([kernels.psi_table(L, lam, j, j, self.theta_j(j))[0]
+                                 for j in self.scales])
         self.phi = kernels.phi_table(L, lam, J0)                  # [l]
+
+    def theta_j(self, j):
+        """Colatitude of the unrotated spin-s curvelet's centre, arccos(-s / lambda^j)."""
+        c = -self.spin / self.lam ** j
+        return math.acos(min(1.0, max(-1.0, c)))
 
     def psi_j(self, j, Lj):
         """Psi^(j)_ln restricted to l < Lj, |n| < Lj: [l, n + Lj - 1]."""

@@ -1,4 +1,4 @@
-"""Spin-0 spherical harmonic transforms on McEwen-Wiaux sampling.
+"""Spherical harmonic transforms on McEwen-Wiaux sampling (spin 0 and spin s).
 
 Test infrastructure (see ``oracle/__init__.py``).
 
@@ -14,6 +14,12 @@ stored flat with index l^2 + l + m.
   sampled at 2L-1 equispaced points, so plain trigonometric interpolation
   evaluates it exactly at Gauss-Legendre nodes, and L-point Gauss-Legendre in
   cos(theta) integrates the product exactly (polynomial degree <= 2L-2).
+* ``inverse_spin`` / ``forward_spin``: the same two routes for a spin-s signal,
+  with sY_lm = (-1)^s sqrt((2l+1)/(4 pi)) d^l_{m,-s}(theta) e^{i m phi}
+  (Sec. II-A) in place of Y_lm: the theta extension of F_m has the parity
+  (-1)^{m+s} (d^l_{m,-s}(-t) = (-1)^{m+s} d^l_{m,-s}(t)), and the product of
+  two d^l_{m,-s} is still a polynomial in cos(theta) of degree <= 2L-2, so
+  the Gauss-Legendre quadrature stays exact.  f_lm = 0 for l < |s|.
 """
 import math
 
@@ -103,3 +109,52 @@ def point_source_flm(L, theta, phi, amp):
             row = a * math.sqrt((2 * l + 1) / (4 * math.pi)) * D[:, 0] * e
             out[l * l: (l + 1) * (l + 1)] += row[L - 1 - l: L + l]
     return out
+
+
+def _spin_d_column(L, th, s):
+    """Yield (l, v) with v[m + L - 1] = d^l_{m,-s}(th), |m| < L (zero for |m| > l
+    or l < |s|), from ``wigner.d_iter`` with n = -s."""
+    N = abs(s) + 1
+    for l, D in wigner.d_iter(L, th, L, N):
+        yield l, D[:, N - 1 - s]
+
+
+def inverse_spin(flm, L, s):
+    """map[t, p] = sum_lm f_lm sY_lm(theta_t, phi_p), complex (L, 2L-1)."""
+    flm = np.asarray(flm, dtype=np.complex128)
+    thetas = sampling.mw_theta(L)
+    phis = sampling.mw_phi(L)
+    ms = np.arange(-(L - 1), L)
+    Ephi = sampling.dft_matrix(ms, phis, +1)          # [p, m]
+    F = np.zeros((L, 2 * L - 1), dtype=np.complex128)  # F[l, m + L - 1]
+    for l in range(abs(s), L):
+        for m in range(-l, l + 1):
+            F[l, m + L - 1] = flm[lm_index(l, m)] * (-1.0) ** s * math.sqrt((2 * l + 1) / (4 * math.pi))
+    out = np.zeros((L, 2 * L - 1), dtype=np.complex128)
+    for t, th in enumerate(thetas):
+        G = np.zeros(2 * L - 1, dtype=np.complex128)
+        for l, v in _spin_d_column(L, th, s):
+            if l >= abs(s):
+                G += v * F[l]
+        out[t] = Ephi @ G
+    return out
+
+
+def forward_spin(fmap, L, s):
+    """f_lm = <f, sY_lm> of a band-limited spin-s map on the MW grid (flat, L^2)."""
+    F = _phi_coeffs(fmap, L)                     # [t, m]
+    nodes, weights = sampling.gauss_legendre_beta(L)
+    E1, E2 = theta_interp_matrices(L, nodes)
+    ms = np.arange(-(L - 1), L)
+    sgn = (-1.0) ** np.abs(ms + s)
+    Fq = E1 @ F + (E2 @ F) * sgn[None, :]        # [q, m]
+    acc = np.zeros((L, 2 * L - 1), dtype=np.complex128)
+    for q, th in enumerate(nodes):
+        for l, v in _spin_d_column(L, th, s):
+            acc[l] += weights[q] * v * Fq[q]
+    flm = np.zeros(L * L, dtype=np.complex128)
+    for l in range(abs(s), L):
+        c = 2 * math.pi * (-1.0) ** s * math.sqrt((2 * l + 1) / (4 * math.pi))
+        for m in range(-l, l + 1):
+            flm[lm_index(l, m)] = c * acc[l, m + L - 1]
+    return flm

@@ -44,6 +44,12 @@ SIGNATURES = {
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "cvl_sht_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_sht_forward_complex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.c_void_p]),
+    "cvl_sht_inverse_complex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.c_void_p]),
     "cvl_wigner_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "cvl_wigner_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -109,8 +115,11 @@ def _prec(precision):
     return int(precision)
 
 
-def params(L, lam=2.0, J0=2, N=0, spin=0, flags=CVL_REAL, precision=CVL_FP64, real_grids=False,
-           unrotated=False):
+def params(L, lam=2.0, J0=2, N=0, spin=0, flags=None, precision=CVL_FP64, real_grids=False,
+           unrotated=False, complex_map=False):
+    """cvl_params; a complex map (complex_map) clears CVL_REAL."""
+    if flags is None:
+        flags = 0 if complex_map else CVL_REAL
     if real_grids:
         flags |= CVL_REAL_GRIDS
     if unrotated:
@@ -136,17 +145,21 @@ def scaling_bandlimit(L, lam=2.0, J0=2):
     return v.value
 
 
-def workspace_bytes(L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, unrotated=False):
+def workspace_bytes(L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, unrotated=False,
+                    complex_map=False, spin=0):
     v = ctypes.c_size_t()
-    p = params(L, lam, J0, precision=precision, unrotated=unrotated)
+    p = params(L, lam, J0, spin=spin, precision=precision, unrotated=unrotated,
+               complex_map=complex_map)
     _check(lib.cvl_workspace_bytes(ctypes.byref(p), batch, ctypes.byref(v)))
     return v.value
 
 
-def scale_workspace_bytes(L, lam=2.0, J0=2, precision=CVL_FP64, unrotated=False):
+def scale_workspace_bytes(L, lam=2.0, J0=2, precision=CVL_FP64, unrotated=False,
+                          complex_map=False, spin=0):
     """Workspace of the per-scale (streaming) calls."""
     v = ctypes.c_size_t()
-    p = params(L, lam, J0, precision=precision, unrotated=unrotated)
+    p = params(L, lam, J0, spin=spin, precision=precision, unrotated=unrotated,
+               complex_map=complex_map)
     _check(lib.cvl_scale_workspace_bytes(ctypes.byref(p), ctypes.byref(v)))
     return v.value
 
@@ -166,7 +179,14 @@ def _stream(torch):
 
 
 class Context:
-    """Resident Delta table (and kernel / DFT tables built on first use)."""
+    """Resident Delta table (and kernel / DFT tables built on first use).
+
+    The binding keeps one scratch workspace per HIP stream (the stream current
+    when a method is called), because calls that share a workspace must be
+    ordered on one stream.  A workspace grows (and is replaced) when a call
+    needs more: a HIP graph captured from these methods keeps pointing at the
+    workspace it was captured with, so prepare the largest call first (or
+    pass the raw C entry points a workspace of your own) before capturing."""
 
     def __init__(self, L_max, device=0):
         import torch
@@ -176,12 +196,13 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib.cvl_context_create(ctypes.byref(h), L_max, device))
         self.h = h
-        self._ws = None
+        self._ws = {}
 
     def close(self):
         if getattr(self, "h", None):
             lib.cvl_context_destroy(self.h)
             self.h = None
+        self._ws = {}
 
     def __del__(self):
         try:
@@ -190,36 +211,57 @@ class Context:
             pass
 
     def workspace(self, nbytes):
+        """The current stream's workspace, at least nbytes."""
         t = self.torch
-        if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = t.empty(max(nbytes, 256), dtype=t.uint8, device=self.device)
-        return self._ws
+        key = t.cuda.current_stream(self.device).cuda_stream
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = t.empty(max(nbytes, 256), dtype=t.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
 
-    def prepare(self, L, lam=2.0, J0=2):
-        _check(lib.cvl_prepare(self.h, ctypes.byref(params(L, lam, J0))))
+    def prepare(self, L, lam=2.0, J0=2, spin=0, complex_map=False, unrotated=False):
+        p = params(L, lam, J0, spin=spin, unrotated=unrotated, complex_map=complex_map or spin != 0)
+        _check(lib.cvl_prepare(self.h, ctypes.byref(p)))
 
     # ---- SHT ----
-    def sht_forward(self, fmap, out=None):
-        t = self.torch
-        L = fmap.shape[-2]
-        assert fmap.dtype == t.float64 and fmap.is_contiguous() and fmap.shape[-1] == 2 * L - 1
-        if out is None:
-            out = t.empty(L * L, dtype=t.complex128, device=self.device)
+    def _sht_ws(self, L):
         nb = ctypes.c_size_t()
         _check(lib.cvl_sht_workspace_bytes(L, ctypes.byref(nb)))
-        ws = self.workspace(nb.value)
+        return self.workspace(nb.value)
+
+    def sht_forward(self, fmap, out=None, spin=0):
+        """f_lm (L^2 complex128) of a real map (float64, spin 0) or of a
+        complex map (complex128) of spin `spin`."""
+        t = self.torch
+        L = fmap.shape[-2]
+        assert fmap.is_contiguous() and fmap.shape[-1] == 2 * L - 1
+        if out is None:
+            out = t.empty(L * L, dtype=t.complex128, device=self.device)
+        ws = self._sht_ws(L)
+        if fmap.dtype == t.complex128:
+            _check(lib.cvl_sht_forward_complex(self.h, L, spin, fmap.data_ptr(), out.data_ptr(),
+                                               ws.data_ptr(), ws.numel(), _stream(t)))
+            return out
+        assert fmap.dtype == t.float64 and spin == 0
         _check(lib.cvl_sht_forward(self.h, L, 0, fmap.data_ptr(), out.data_ptr(), ws.data_ptr(),
                                    ws.numel(), _stream(t)))
         return out
 
-    def sht_inverse(self, flm, L, out=None):
+    def sht_inverse(self, flm, L, out=None, spin=0, complex_map=False):
+        """Map of f_lm: real (float64; m >= 0 read) by default, complex
+        (complex128; every m read) with complex_map or spin != 0."""
         t = self.torch
         assert flm.dtype == t.complex128 and flm.is_contiguous() and flm.numel() == L * L
+        cplx = complex_map or spin != 0
         if out is None:
-            out = t.empty((L, 2 * L - 1), dtype=t.float64, device=self.device)
-        nb = ctypes.c_size_t()
-        _check(lib.cvl_sht_workspace_bytes(L, ctypes.byref(nb)))
-        ws = self.workspace(nb.value)
+            out = t.empty((L, 2 * L - 1), dtype=t.complex128 if cplx else t.float64,
+                          device=self.device)
+        ws = self._sht_ws(L)
+        if cplx:
+            _check(lib.cvl_sht_inverse_complex(self.h, L, spin, flm.data_ptr(), out.data_ptr(),
+                                               ws.data_ptr(), ws.numel(), _stream(t)))
+            return out
         _check(lib.cvl_sht_inverse(self.h, L, 0, flm.data_ptr(), out.data_ptr(), ws.data_ptr(),
                                    ws.numel(), _stream(t)))
         return out
@@ -260,43 +302,48 @@ class Context:
 
     def grid_dtype(self, precision=CVL_FP64, real_grids=False):
         """Element type of the curvelet grids: complex128 (precision "fp64") or
-        complex64 ("fp32", "bf16x3") with zero imaginary parts, or with
-        real_grids float64 / float32 holding the same (real) coefficients."""
+        complex64 ("fp32", "bf16x3") (zero imaginary parts for a real map), or
+        with real_grids float64 / float32 holding the same (real) coefficients."""
         t = self.torch
         if real_grids:
             return t.float64 if _prec(precision) == CVL_FP64 else t.float32
         return t.complex128 if _prec(precision) == CVL_FP64 else t.complex64
 
-    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, real_grids=False):
+    def alloc_outputs(self, L, lam=2.0, J0=2, batch=1, precision=CVL_FP64, real_grids=False,
+                      complex_map=False):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
-        scal = t.empty((batch, Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
+        scal = t.empty((batch, Lp, 2 * Lp - 1), dtype=t.complex128 if complex_map else t.float64,
+                       device=self.device)
         dt = self.grid_dtype(precision, real_grids)
         grids = [[t.empty(s, dtype=dt, device=self.device)
                   for s in self.grid_shapes(L, lam, J0)] for _ in range(batch)]
         return scal, grids
 
     def curvelet_analysis(self, maps, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                          real_grids=False, unrotated=False):
-        """maps: (batch, L, 2L-1) or (L, 2L-1) float64.  Returns (scal, grids);
+                          real_grids=False, unrotated=False, spin=0):
+        """maps: (batch, L, 2L-1) or (L, 2L-1), float64 (real maps) or
+        complex128 (complex maps of spin `spin`).  Returns (scal, grids);
         grids of grid_dtype(precision, real_grids).  unrotated: coefficients
         of the unrotated curvelets (CVL_UNROTATED)."""
         t = self.torch
         single = maps.dim() == 2
         if single:
             maps = maps.unsqueeze(0)
-        assert maps.dtype == t.float64 and maps.is_contiguous()
+        cplx = maps.dtype == t.complex128
+        assert (cplx or maps.dtype == t.float64) and maps.is_contiguous()
         batch, L = maps.shape[0], maps.shape[1]
         if out is None:
-            out = self.alloc_outputs(L, lam, J0, batch, precision, real_grids)
+            out = self.alloc_outputs(L, lam, J0, batch, precision, real_grids, cplx)
         scal, grids = out
         flat = [g for per in grids for g in per]
         dt = self.grid_dtype(precision, real_grids)
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
-        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision, unrotated))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision, unrotated, cplx, spin))
+        p = params(L, lam, J0, spin=spin, precision=precision, real_grids=real_grids,
+                   unrotated=unrotated, complex_map=cplx)
         _check(lib.cvl_curvelet_analysis(self.h, ctypes.byref(p), batch,
                                          maps.data_ptr(), scal.data_ptr(), arr, ws.data_ptr(),
                                          ws.numel(), _stream(t)))
@@ -305,30 +352,37 @@ class Context:
         return scal, grids
 
     def curvelet_synthesis(self, scal, grids, L, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                           real_grids=False, unrotated=False):
+                           real_grids=False, unrotated=False, spin=0):
+        """Maps from scaling maps and grids; complex maps when the scaling maps
+        are complex128 (the analysis of complex maps of spin `spin`)."""
         t = self.torch
         single = scal.dim() == 2
         if single:
             scal = scal.unsqueeze(0)
             grids = [grids]
+        cplx = scal.dtype == t.complex128
         batch = scal.shape[0]
         if out is None:
-            out = t.empty((batch, L, 2 * L - 1), dtype=t.float64, device=self.device)
+            out = t.empty((batch, L, 2 * L - 1), dtype=t.complex128 if cplx else t.float64,
+                          device=self.device)
         flat = [g for per in grids for g in per]
         dt = self.grid_dtype(precision, real_grids)
         for g in flat:
             assert g.dtype == dt and g.is_contiguous()
         arr = (ctypes.c_void_p * len(flat))(*[g.data_ptr() for g in flat])
-        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision, unrotated))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
+        ws = self.workspace(workspace_bytes(L, lam, J0, batch, precision, unrotated, cplx, spin))
+        p = params(L, lam, J0, spin=spin, precision=precision, real_grids=real_grids,
+                   unrotated=unrotated, complex_map=cplx)
         _check(lib.cvl_curvelet_synthesis(self.h, ctypes.byref(p), batch,
                                           scal.data_ptr(), arr, out.data_ptr(), ws.data_ptr(),
                                           ws.numel(), _stream(t)))
         return out[0] if single else out
 
     # ---- streaming (one scale at a time) ----
+    # complex_map: flm holds every m of a complex signal (spin `spin`) and the
+    # scaling maps are complex128; otherwise a real map's coefficients.
     def analysis_scale(self, flm, L, j, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                       real_grids=False, unrotated=False):
+                       real_grids=False, unrotated=False, complex_map=False, spin=0):
         """Grid of scale j from harmonic coefficients flm (L^2 complex128)."""
         t = self.torch
         assert flm.dtype == t.complex128 and flm.is_contiguous() and flm.numel() == L * L
@@ -337,20 +391,22 @@ class Context:
             Lj, _ = scale_shape(L, j, lam, J0)
             out = t.empty((2 * Lj - 1, Lj, 2 * Lj - 1), dtype=dt, device=self.device)
         assert out.dtype == dt and out.is_contiguous()
-        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated, complex_map, spin))
+        p = params(L, lam, J0, spin=spin, precision=precision, real_grids=real_grids,
+                   unrotated=unrotated, complex_map=complex_map)
         _check(lib.cvl_curvelet_analysis_scale(self.h, ctypes.byref(p), j, flm.data_ptr(),
                                                out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(t)))
         return out
 
     def synthesis_scale(self, grid, L, j, flm_acc, lam=2.0, J0=2, precision=CVL_FP64,
-                        real_grids=False, unrotated=False):
+                        real_grids=False, unrotated=False, complex_map=False, spin=0):
         """flm_acc += f^(j)_lm from scale j's grid."""
         t = self.torch
         assert grid.dtype == self.grid_dtype(precision, real_grids) and grid.is_contiguous()
         assert flm_acc.dtype == t.complex128 and flm_acc.numel() == L * L
-        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
-        p = params(L, lam, J0, precision=precision, real_grids=real_grids, unrotated=unrotated)
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated, complex_map, spin))
+        p = params(L, lam, J0, spin=spin, precision=precision, real_grids=real_grids,
+                   unrotated=unrotated, complex_map=complex_map)
         _check(lib.cvl_curvelet_synthesis_scale(self.h, ctypes.byref(p), j, grid.data_ptr(),
                                                 flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
                                                 _stream(t)))
@@ -359,37 +415,43 @@ class Context:
     # The scaling part is FP64 at every precision; `precision` only names the
     # streaming workspace (cvl_scale_workspace_bytes of the same parameters) to use.
     def scaling_analysis(self, flm, L, lam=2.0, J0=2, out=None, precision=CVL_FP64,
-                         unrotated=False):
+                         unrotated=False, complex_map=False, spin=0):
         t = self.torch
         Lp = scaling_bandlimit(L, lam, J0)
         if out is None:
-            out = t.empty((Lp, 2 * Lp - 1), dtype=t.float64, device=self.device)
-        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
-        p = params(L, lam, J0, precision=precision, unrotated=unrotated)
+            out = t.empty((Lp, 2 * Lp - 1), dtype=t.complex128 if complex_map else t.float64,
+                          device=self.device)
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated, complex_map, spin))
+        p = params(L, lam, J0, spin=spin, precision=precision, unrotated=unrotated,
+                   complex_map=complex_map)
         _check(lib.cvl_curvelet_scaling_analysis(self.h, ctypes.byref(p), flm.data_ptr(),
                                                  out.data_ptr(), ws.data_ptr(), ws.numel(),
                                                  _stream(t)))
         return out
 
     def scaling_synthesis(self, scal, L, flm_acc, lam=2.0, J0=2, precision=CVL_FP64,
-                          unrotated=False):
-        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated))
-        p = params(L, lam, J0, precision=precision, unrotated=unrotated)
+                          unrotated=False, complex_map=False, spin=0):
+        ws = self.workspace(scale_workspace_bytes(L, lam, J0, precision, unrotated, complex_map, spin))
+        p = params(L, lam, J0, spin=spin, precision=precision, unrotated=unrotated,
+                   complex_map=complex_map)
         _check(lib.cvl_curvelet_scaling_synthesis(self.h, ctypes.byref(p), scal.data_ptr(),
                                                   flm_acc.data_ptr(), ws.data_ptr(), ws.numel(),
                                                   _stream(self.torch)))
         return flm_acc
 
     def round_trip_streamed(self, fmap, lam=2.0, J0=2, precision=CVL_FP64, on_grid=None,
-                            real_grids=False, unrotated=False):
-        """Analysis + synthesis of one real map, one scale at a time (a single
-        grid buffer of the largest scale is reused).  on_grid(j, grid), if
-        given, sees each scale's grid between its analysis and synthesis."""
+                            real_grids=False, unrotated=False, spin=0):
+        """Analysis + synthesis of one map (real float64, or complex128 of spin
+        `spin`), one scale at a time (a single grid buffer of the largest
+        scale is reused).  on_grid(j, grid), if given, sees each scale's grid
+        between its analysis and synthesis."""
         t = self.torch
         L = fmap.shape[-2]
-        flm = self.sht_forward(fmap)
+        cplx = fmap.dtype == t.complex128
+        kw = dict(precision=precision, unrotated=unrotated, complex_map=cplx, spin=spin)
+        flm = self.sht_forward(fmap, spin=spin)
         acc = t.zeros(L * L, dtype=t.complex128, device=self.device)
-        scal = self.scaling_analysis(flm, L, lam, J0, precision=precision, unrotated=unrotated)
+        scal = self.scaling_analysis(flm, L, lam, J0, **kw)
         J = num_scales(L, lam, J0)
         Lt, _ = scale_shape(L, J, lam, J0)
         buf = t.empty((2 * Lt - 1) * Lt * (2 * Lt - 1),
@@ -397,14 +459,12 @@ class Context:
         for j in range(J0, J + 1):
             Lj, _ = scale_shape(L, j, lam, J0)
             g = buf[:(2 * Lj - 1) * Lj * (2 * Lj - 1)].view(2 * Lj - 1, Lj, 2 * Lj - 1)
-            self.analysis_scale(flm, L, j, lam, J0, out=g, precision=precision,
-                                real_grids=real_grids, unrotated=unrotated)
+            self.analysis_scale(flm, L, j, lam, J0, out=g, real_grids=real_grids, **kw)
             if on_grid is not None:
                 on_grid(j, g)
-            self.synthesis_scale(g, L, j, acc, lam, J0, precision=precision,
-                                 real_grids=real_grids, unrotated=unrotated)
-        self.scaling_synthesis(scal, L, acc, lam, J0, precision=precision, unrotated=unrotated)
-        return self.sht_inverse(acc, L), scal
+            self.synthesis_scale(g, L, j, acc, lam, J0, real_grids=real_grids, **kw)
+        self.scaling_synthesis(scal, L, acc, lam, J0, **kw)
+        return self.sht_inverse(acc, L, spin=spin, complex_map=cplx), scal
 
     def delta_block(self, l):
         out = np.zeros((l + 1, l + 1))

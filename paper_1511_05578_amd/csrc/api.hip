@@ -9,6 +9,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/curvelet.h"
@@ -121,6 +122,7 @@ struct ShtRt {
     int L;
     BetaTabs beta;  // factor 2 pi
     BluesteinDev inv, fwd;
+    BluesteinDev fwd_c;  // phi DFT of a complex map: every m
 };
 
 struct GenRt {
@@ -146,6 +148,9 @@ struct cvl_ctx {
     std::map<std::tuple<int, double, int>, std::unique_ptr<Plan>> plans;
     std::map<int, std::unique_ptr<ShtRt>> sht;
     std::map<std::pair<int, int>, std::unique_ptr<GenRt>> gen;
+    // Psi of the rotated spin-s curvelets per scale, [l][n + L_j - 1], keyed
+    // (L, lambda, J0, spin)
+    std::map<std::tuple<int, double, int, int>, std::vector<double *>> spin_psi;
     // side stream (and its fork / join events) per caller stream
     struct Side {
         hipStream_t s = nullptr;
@@ -343,14 +348,24 @@ int check_params(const cvl_params *p, int *J) {
     int JJ = num_scales(p->L, p->lambda);
     if (p->J0 < 1 || p->J0 > JJ)
         return fail(CVL_EINVAL, "J0=%d outside [1, J=%d]", p->J0, JJ);
-    if (p->spin != 0) return fail(CVL_EUNSUPPORTED, "spin=%d: only spin 0 is implemented", p->spin);
-    if (!(p->flags & CVL_REAL))
-        return fail(CVL_EUNSUPPORTED, "complex maps are not implemented: set CVL_REAL");
     if (p->precision != CVL_FP64 && p->precision != CVL_FP32 && p->precision != CVL_BF16X3)
         return fail(CVL_EINVAL, "precision=%d is not CVL_FP64, CVL_FP32 or CVL_BF16X3",
                     p->precision);
     if (p->flags & ~(CVL_REAL | CVL_REAL_GRIDS | CVL_UNROTATED))
         return fail(CVL_EINVAL, "flags=0x%x: unknown bits", p->flags);
+    if (p->flags & CVL_REAL) {
+        if (p->spin != 0)
+            return fail(CVL_EINVAL, "spin=%d: a spin signal is complex (clear CVL_REAL)", p->spin);
+    } else {
+        if (p->flags & CVL_REAL_GRIDS)
+            return fail(CVL_EINVAL, "CVL_REAL_GRIDS needs a real map (CVL_REAL): the "
+                                    "coefficients of a complex map are complex");
+        if (p->spin <= -p->L || p->spin >= p->L)
+            return fail(CVL_EINVAL, "spin=%d outside (-L, L)", p->spin);
+        if (p->spin != 0 && !(p->flags & CVL_UNROTATED) && p->precision != CVL_FP64)
+            return fail(CVL_EUNSUPPORTED, "spin=%d: the rotated spin curvelets run in FP64 only",
+                        p->spin);
+    }
     if (J) *J = JJ;
     return CVL_OK;
 }
@@ -398,18 +413,63 @@ void curvelet_buf_elems(int L, double lam, int J0, int J, bool unrot, size_t *b0
 // calls add two cube buffers and a plane for the side scales (cube elements
 // complex128, or complex64 in reduced precision).  The per-scale calls
 // (scale_call) need only the first part: they run on one stream.
+// Elements of the W2 / V1 plane buffer of a complex signal's second part:
+// the largest plane of the top scales (*top) and of the side scales (*side).
+void curvelet_plane_elems(int L, double lam, int J0, int J, bool unrot, size_t *top,
+                          size_t *side) {
+    *top = *side = 0;
+    const int T = scale_bandlimit(J, L, lam);
+    for (int j = J0; j <= J; ++j) {
+        ScaleGeom g = geom_of(scale_bandlimit(j, L, lam));
+        const size_t w2 = (size_t)g.L * g.Nm * (unrot ? g.L : g.h + 1);
+        size_t *x = g.L < T ? side : top;
+        *x = std::max(*x, w2);
+    }
+}
+
 size_t curvelet_ws_bytes(int L, double lam, int J0, int J, int precision, bool unrot,
-                         bool scale_call) {
-    size_t b0, b1, sb0, sb1;
+                         bool scale_call, bool cplx = false) {
+    size_t b0, b1, sb0, sb1, p2, sp2;
     curvelet_buf_elems(L, lam, J0, J, unrot, &b0, &b1, &sb0, &sb1);
+    curvelet_plane_elems(L, lam, J0, J, unrot, &p2, &sp2);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
     const int Lphi = scaling_bandlimit(L, lam, J0);
     size_t small = 4 * (size_t)L * L + 2 * (size_t)Lphi * Lphi;
-    const size_t base = align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) +
-                        8 * kAlign;
+    size_t base = align_up(b0 * esz) + align_up(b1 * esz) + align_up(small * 16) + 8 * kAlign;
+    // complex signals: the second part's plane, its padded coefficients and
+    // accumulator, the flat coefficients and the complex SHT's scratch at L
+    // and at L_Phi
+    const size_t L2 = align_up((size_t)L * L * 16);
+    const size_t sht = align_up((size_t)L * (2 * L - 1) * 16);
+    const size_t shtp = align_up((size_t)Lphi * (2 * Lphi - 1) * 16);
+    if (cplx) base += align_up(p2 * esz) + 3 * L2 + 2 * sht + 2 * shtp + 8 * kAlign;
     if (scale_call) return base;
     const size_t plane = align_up((size_t)L * L * 16);
-    return base + align_up(sb0 * esz) + align_up(sb1 * esz) + plane + 3 * kAlign;
+    size_t side = align_up(sb0 * esz) + align_up(sb1 * esz) + plane + 3 * kAlign;
+    if (cplx) side += align_up(sp2 * esz) + plane + 2 * kAlign;
+    return base + side;
+}
+
+// Rotated spin-s curvelets (kernel coefficients at every n, no reality
+// condition) run on the general Wigner layouts, every scale on the caller's
+// stream: two general cube buffers and the dense Wigner coefficients of the
+// top scale, the flat coefficients and accumulator, the complex SHT scratch.
+bool spin_rotated(const cvl_params *p) {
+    return !(p->flags & CVL_REAL) && !(p->flags & CVL_UNROTATED) && p->spin != 0;
+}
+size_t spin_ws_bytes(int L, double lam, int J0, int J) {
+    const int T = scale_bandlimit(J, L, lam), Lphi = scaling_bandlimit(L, lam, J0);
+    const size_t Nm = 2 * T - 1, Nnp = (Nm + 31) / 32 * 32;
+    const size_t gen = align_up((size_t)T * Nm * Nnp * 16), F = align_up((size_t)T * Nm * Nm * 16);
+    const size_t L2 = align_up((size_t)L * L * 16), sht = align_up((size_t)L * (2 * L - 1) * 16);
+    const size_t shtp = align_up((size_t)Lphi * (2 * Lphi - 1) * 16);
+    return 2 * gen + F + 2 * L2 + 2 * sht + 2 * shtp + align_up((size_t)Lphi * Lphi * 16) +
+           10 * kAlign;
+}
+size_t ws_bytes_of(const cvl_params *p, int J, bool scale_call) {
+    if (spin_rotated(p)) return spin_ws_bytes(p->L, p->lambda, p->J0, J);
+    return curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision,
+                             (p->flags & CVL_UNROTATED) != 0, scale_call, !(p->flags & CVL_REAL));
 }
 
 int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
@@ -503,6 +563,7 @@ int get_sht(cvl_ctx *c, int L, ShtRt **out) {
     const int Nm = 2 * L - 1;
     if ((rc = get_bluestein(c, Nm, Nm, -(L - 1), Nm, 0, +1, &S->inv))) return rc;
     if ((rc = get_bluestein(c, Nm, Nm, 0, L, 0, -1, &S->fwd))) return rc;
+    if ((rc = get_bluestein(c, Nm, Nm, 0, Nm, -(L - 1), -1, &S->fwd_c))) return rc;
     *out = S.get();
     c->sht[L] = std::move(S);
     return CVL_OK;
@@ -592,6 +653,30 @@ int sht_inverse_run(cvl_ctx *ctx, ShtRt *S, const cd *fpad, int Lf, double *map,
     return CVL_OK;
 }
 
+// Spin-s SHT of a complex map [t][p] (L x (2L-1) complex128) to the flat
+// f_lm of every m, and back (scratch: two L x (2L-1) complex buffers).
+int sht_forward_cplx_run(cvl_ctx *ctx, ShtRt *S, int spin, const cd *map, cd *flm, cd *F1,
+                         cd *Zs, hipStream_t st) {
+    const int L = S->L, Nm = 2 * L - 1;
+    TagScope tag(L);
+    LAUNCH(ST_SHT_PHI, launch_sht_fwd_phi_cplx(L, S->fwd_c, map, F1, st));
+    LAUNCH(ST_SHT_THETA, launch_sht_theta_cols(Nm, spin - L + 1, L, L, S->beta.Qp, S->beta.Qs,
+                                               F1, Zs, st));
+    LAUNCH(ST_SHT_DELTA, launch_sht_fwd_delta_spin(L, spin, ctx->delta, Zs, flm, st));
+    return CVL_OK;
+}
+
+int sht_inverse_cplx_run(cvl_ctx *ctx, ShtRt *S, int spin, const cd *flm, cd *map, cd *F,
+                         cd *G, hipStream_t st) {
+    const int L = S->L, Nm = 2 * L - 1;
+    TagScope tag(L);
+    LAUNCH(ST_SHT_DELTA, launch_sht_inv_delta_spin(L, spin, ctx->delta, flm, F, st));
+    LAUNCH(ST_SHT_THETA, launch_sht_theta_cols(Nm, spin - L + 1, L, L, S->beta.Cinv,
+                                               S->beta.Sinv, F, G, st));
+    LAUNCH(ST_SHT_PHI, launch_sht_inv_phi_cplx(L, S->inv, G, map, st));
+    return CVL_OK;
+}
+
 int check_ctx(cvl_ctx *ctx) {
     if (!ctx) return fail(CVL_EINVAL, "context is NULL");
     return CVL_OK;
@@ -606,6 +691,9 @@ int set_device(cvl_ctx *ctx) {
 }  // namespace
 
 extern "C" {
+
+static int get_spin_psi(cvl_ctx *ctx, const Plan *P, int spin, const std::vector<double *> **out);
+static int get_gen(cvl_ctx *ctx, int L, int N, GenRt **out);
 
 const char *cvl_last_error(void) { return g_err.c_str(); }
 
@@ -684,8 +772,7 @@ int cvl_workspace_bytes(const cvl_params *p, int batch, size_t *bytes) {
     if (rc) return rc;
     if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision,
-                               (p->flags & CVL_UNROTATED) != 0, false);
+    *bytes = ws_bytes_of(p, J, false);
     return CVL_OK;
 }
 
@@ -694,8 +781,7 @@ int cvl_scale_workspace_bytes(const cvl_params *p, size_t *bytes) {
     int J, rc = check_params(p, &J);
     if (rc) return rc;
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = curvelet_ws_bytes(p->L, p->lambda, p->J0, J, p->precision,
-                               (p->flags & CVL_UNROTATED) != 0, true);
+    *bytes = ws_bytes_of(p, J, true);
     return CVL_OK;
 }
 
@@ -703,7 +789,9 @@ int cvl_sht_workspace_bytes(int L, size_t *bytes) {
     g_err.clear();
     if (L < 2 || L > 2048) return fail(CVL_EINVAL, "L=%d outside [2, 2048]", L);
     if (!bytes) return fail(CVL_EINVAL, "bytes out-pointer is NULL");
-    *bytes = 3 * align_up((size_t)L * L * 16) + kAlign;
+    // real maps: three L x L complex buffers; complex maps: two L x (2L-1)
+    *bytes = std::max(3 * align_up((size_t)L * L * 16),
+                      2 * align_up((size_t)L * (2 * L - 1) * 16)) + kAlign;
     return CVL_OK;
 }
 
@@ -724,10 +812,20 @@ int cvl_prepare(cvl_ctx *ctx, const cvl_params *p) {
     if ((rc = set_device(ctx))) return rc;
     Plan *P;
     if ((rc = get_plan(ctx, p, &P))) return rc;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    ShtRt *S;
-    if ((rc = get_sht(ctx, P->L, &S))) return rc;
-    if ((rc = get_sht(ctx, P->Lphi, &S))) return rc;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ShtRt *S;
+        if ((rc = get_sht(ctx, P->L, &S))) return rc;
+        if ((rc = get_sht(ctx, P->Lphi, &S))) return rc;
+    }
+    if (spin_rotated(p)) {  // the kernel coefficients and general Wigner tables
+        const std::vector<double *> *psi;
+        if ((rc = get_spin_psi(ctx, P, p->spin, &psi))) return rc;
+        for (const ScaleRt &S : P->scales) {
+            GenRt *G;
+            if ((rc = get_gen(ctx, S.g.L, S.g.L, &G))) return rc;
+        }
+    }
     return CVL_OK;
 }
 
@@ -794,6 +892,47 @@ int cvl_sht_inverse(cvl_ctx *ctx, int L, int spin, const cvl_c128 *flm, double *
     cd *G = cv.take<cd>((size_t)L * L);
     LAUNCH(ST_MISC, launch_flm_pack(L, (const cd *)flm, fpad, st));
     return sht_inverse_run(ctx, S, fpad, L, map, F, G, st);
+}
+
+static int check_sht_call(cvl_ctx *ctx, int L, int spin, const void *a, const void *b, void *ws,
+                          size_t ws_bytes, ShtRt **S) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (L < 2 || L > ctx->Lmax) return fail(CVL_EINVAL, "L=%d outside [2, L_max=%d]", L, ctx->Lmax);
+    if (spin <= -L || spin >= L) return fail(CVL_EINVAL, "spin=%d outside (-L, L)", spin);
+    if (!a || !b || !ws) return fail(CVL_EINVAL, "NULL device pointer");
+    size_t need;
+    cvl_sht_workspace_bytes(L, &need);
+    if (ws_bytes < need) return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    if ((rc = set_device(ctx))) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return get_sht(ctx, L, S);
+}
+
+int cvl_sht_forward_complex(cvl_ctx *ctx, int L, int spin, const cvl_c128 *map, cvl_c128 *flm,
+                            void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    ShtRt *S;
+    int rc = check_sht_call(ctx, L, spin, map, flm, ws, ws_bytes, &S);
+    if (rc) return rc;
+    Carver cv{(char *)ws, ws_bytes};
+    cd *F1 = cv.take<cd>((size_t)L * (2 * L - 1));
+    cd *Zs = cv.take<cd>((size_t)L * (2 * L - 1));
+    return sht_forward_cplx_run(ctx, S, spin, (const cd *)map, (cd *)flm, F1, Zs,
+                                (hipStream_t)stream);
+}
+
+int cvl_sht_inverse_complex(cvl_ctx *ctx, int L, int spin, const cvl_c128 *flm, cvl_c128 *map,
+                            void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    ShtRt *S;
+    int rc = check_sht_call(ctx, L, spin, flm, map, ws, ws_bytes, &S);
+    if (rc) return rc;
+    Carver cv{(char *)ws, ws_bytes};
+    cd *F = cv.take<cd>((size_t)L * (2 * L - 1));
+    cd *G = cv.take<cd>((size_t)L * (2 * L - 1));
+    return sht_inverse_cplx_run(ctx, S, spin, (const cd *)flm, (cd *)map, F, G,
+                                (hipStream_t)stream);
 }
 
 static int get_gen(cvl_ctx *ctx, int L, int N, GenRt **out) {
@@ -887,8 +1026,7 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
     if (!a || !b || !grids || !ws) return fail(CVL_EINVAL, "NULL pointer argument");
     if ((rc = set_device(ctx))) return rc;
     if ((rc = get_plan(ctx, p, P))) return rc;
-    const size_t need = curvelet_ws_bytes((*P)->L, (*P)->lambda, (*P)->J0, (*P)->J, p->precision,
-                                          (p->flags & CVL_UNROTATED) != 0, scale_call);
+    const size_t need = ws_bytes_of(p, (*P)->J, scale_call);
     if (ws_bytes < need)
         return fail(CVL_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -901,19 +1039,27 @@ static int check_curvelet_call(cvl_ctx *ctx, const cvl_params *p, int batch, con
 struct CurveletBufs {
     void *b0, *b1;
     cd *fpad, *facc, *s0, *s1, *fphi;
+    // complex signals: the second (imaginary) part's W2 / V1 plane, padded
+    // coefficients and accumulator; the flat coefficients of every m; the
+    // complex SHT's scratch at L (c0, c1) and at L_Phi (cp0, cp1)
+    void *b2;
+    cd *fpadb, *faccb, *flat, *c0, *c1, *cp0, *cp1;
     void *sb0, *sb1;  // cube buffers of the side scales
     cd *sfacc;        // harmonic accumulator of the side scales' synthesis
+    void *sb2;        // complex signals: the side scales' second plane and
+    cd *sfaccb;       // second accumulator
 };
 
-static CurveletBufs carve_curvelet(const Plan *P, int precision, bool unrot, void *ws,
-                                   size_t ws_bytes) {
-    size_t b0, b1, sb0, sb1;
+static CurveletBufs carve_curvelet(const Plan *P, int precision, bool unrot, bool cplx,
+                                   void *ws, size_t ws_bytes) {
+    size_t b0, b1, sb0, sb1, p2, sp2;
     curvelet_buf_elems(P->L, P->lambda, P->J0, P->J, unrot, &b0, &b1, &sb0, &sb1);
+    curvelet_plane_elems(P->L, P->lambda, P->J0, P->J, unrot, &p2, &sp2);
     const size_t esz = precision == CVL_FP64 ? 16 : 8;
-    // the per-scale calls may pass the first part only (through fphi): the
-    // side-stream buffers then come out null, and those calls do not use them
+    // the per-scale calls may pass the first part only: the side-stream
+    // buffers then come out null, and those calls do not use them
     Carver cv{(char *)ws, ws_bytes};
-    CurveletBufs B;
+    CurveletBufs B{};
     B.b0 = cv.take<char>(b0 * esz);
     B.b1 = cv.take<char>(b1 * esz);
     const size_t L2 = (size_t)P->L * P->L;
@@ -922,23 +1068,40 @@ static CurveletBufs carve_curvelet(const Plan *P, int precision, bool unrot, voi
     B.s0 = cv.take<cd>(L2);
     B.s1 = cv.take<cd>(L2);
     B.fphi = cv.take<cd>((size_t)P->Lphi * P->Lphi);
+    if (cplx) {
+        B.b2 = cv.take<char>(p2 * esz);
+        B.fpadb = cv.take<cd>(L2);
+        B.faccb = cv.take<cd>(L2);
+        B.flat = cv.take<cd>(L2);
+        B.c0 = cv.take<cd>((size_t)P->L * (2 * P->L - 1));
+        B.c1 = cv.take<cd>((size_t)P->L * (2 * P->L - 1));
+        B.cp0 = cv.take<cd>((size_t)P->Lphi * (2 * P->Lphi - 1));
+        B.cp1 = cv.take<cd>((size_t)P->Lphi * (2 * P->Lphi - 1));
+    }
     B.sb0 = cv.take<char>(sb0 * esz);
     B.sb1 = cv.take<char>(sb1 * esz);
     B.sfacc = cv.take<cd>(L2);
+    if (cplx) {
+        B.sb2 = cv.take<char>(sp2 * esz);
+        B.sfaccb = cv.take<cd>(L2);
+    }
     return B;
 }
 
-// The buffers a side-scale run uses: its own cubes and accumulator, the
+// The buffers a side-scale run uses: its own cubes and accumulators, the
 // shared (read-only) padded harmonic coefficients.
 static CurveletBufs side_bufs(const CurveletBufs &B) {
     CurveletBufs S = B;
     S.b0 = B.sb0;
     S.b1 = B.sb1;
     S.facc = B.sfacc;
+    S.b2 = B.sb2;
+    S.faccb = B.sfaccb;
     return S;
 }
 
 static bool real_grids(const cvl_params *p) { return (p->flags & CVL_REAL_GRIDS) != 0; }
+static bool complex_map(const cvl_params *p) { return (p->flags & CVL_REAL) == 0; }
 static bool unrotated(const cvl_params *p) { return (p->flags & CVL_UNROTATED) != 0; }
 
 // Analysis of one scale of the unrotated curvelets (same buffers and stages
@@ -1084,6 +1247,150 @@ static int synthesis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, in
     return CVL_OK;
 }
 
+// ---- complex signals: each scale runs the real-signal stages twice, on the
+// coefficients of the signal's real part (B.fpad) and imaginary part
+// (B.fpadb), up to their W2 planes, and one complex gamma DFT combines the
+// two into the complex grid W = W_a + i W_b (the curvelets' harmonic
+// coefficients obey the reality condition, so each part's coefficients are
+// real and the analysis is linear).  The synthesis splits each complex grid
+// line into its two real parts' coefficients and accumulates them into
+// B.facc and B.faccb. ----
+extern "C++" {
+template <class C> struct FullTabs;
+template <> struct FullTabs<cd> {
+    static const BluesteinDev &inv(const ScaleRt &S) { return S.inv_full; }
+    static const BluesteinDev &fwd(const ScaleRt &S) { return S.fwd_full; }
+    static const BluesteinDev &beta(const ScaleRt &S) { return S.beta_inv; }
+};
+template <> struct FullTabs<cf> {
+    static const BluesteinF &inv(const ScaleRt &S) { return S.inv_full_f; }
+    static const BluesteinF &fwd(const ScaleRt &S) { return S.fwd_full_f; }
+    static const BluesteinF &beta(const ScaleRt &S) { return S.beta_inv_f; }
+};
+
+static hipError_t beta_gemm_any(int precision, int M, int K, int ncols, int Nep,
+                                const BetaTabs &T64, const BetaTabsF &T32, bool inverse,
+                                const void *in, void *out, hipStream_t st) {
+    if (precision == CVL_FP64)
+        return launch_beta_gemm(M, K, ncols, Nep, 0, 0, inverse ? T64.Cinv : T64.Qp,
+                                inverse ? T64.Sinv : T64.Qs, (const cd *)in, (cd *)out, st);
+    return launch_beta_gemm_f32(precision, M, K, ncols, Nep, inverse ? T32.Cinv : T32.Qp,
+                                inverse ? T32.Sinv : T32.Qs, (const cf *)in, (cf *)out, st);
+}
+
+// Analysis stages of one part (padded coefficients fp) up to its W2 plane w2
+// (cube scratch b0, b1).
+template <class C>
+static int analysis_to_w2(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                          bool unrot, const cd *fp, C *b0, C *b1, C *w2, hipStream_t st) {
+    const ScaleGeom &g = S.g;
+    const int L = P->L;
+    if (unrot) {
+        LAUNCH(ST_CONTRACT_INV,
+               launch_unrot_contract_inv(g, L, ctx->delta, fp, S.pd, b0, !S.beta_fft, st));
+        if (S.beta_fft)
+            LAUNCH(ST_BETA_INV, launch_unrot_inv_beta_dft(g, FullTabs<C>::beta(S), b0, b1, st));
+        else
+            LAUNCH(ST_BETA_INV, beta_gemm_any(precision, g.L, g.L, 2 * g.L * g.Nep, g.Nep,
+                                              S.beta, S.betaf, true, b0, b1, st));
+        LAUNCH(ST_ALPHA_INV, launch_unrot_inv_alpha(g, FullTabs<C>::inv(S), b1, w2, st));
+        return CVL_OK;
+    }
+    if constexpr (std::is_same<C, cd>::value)
+        LAUNCH(ST_CONTRACT_INV, launch_contract_inv(g, L, ctx->delta, fp, S.psi, b0, st));
+    else
+        LAUNCH(ST_CONTRACT_INV,
+               launch_contract_inv_mx(precision, g, L, ctx->delta, fp, S.psi, b0, st));
+    if (S.beta_fft)
+        LAUNCH(ST_BETA_INV, launch_inv_beta_dft(g, FullTabs<C>::beta(S), b0, b1, st));
+    else
+        LAUNCH(ST_BETA_INV, beta_gemm_any(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.beta,
+                                          S.betaf, true, b0, b1, st));
+    LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, FullTabs<C>::inv(S), b1, w2, st));
+    return CVL_OK;
+}
+
+// Synthesis stages of one part from its V1 plane v1 (which may be b0) into
+// the padded accumulator acc (cube scratch b0, b1).
+template <class C>
+static int synthesis_from_v1(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                             bool unrot, C *v1, C *b0, C *b1, cd *acc, hipStream_t st) {
+    const ScaleGeom &g = S.g;
+    const int L = P->L;
+    if (unrot) {
+        LAUNCH(ST_ALPHA_FWD, launch_unrot_fwd_alpha(g, FullTabs<C>::fwd(S), v1, b1, st));
+        if (precision == CVL_FP64)
+            LAUNCH(ST_BETA_FWD, launch_beta_gemm_unrot_fwd(g, S.beta.Qp, S.beta.Qs,
+                                                           (const cd *)b1, (cd *)b0, st));
+        else
+            LAUNCH(ST_BETA_FWD, beta_gemm_any(precision, g.L, g.L, 2 * g.L * g.Nep, g.Nep,
+                                              S.beta, S.betaf, false, b1, b0, st));
+        LAUNCH(ST_CONTRACT_FWD,
+               launch_unrot_contract_fwd(g, L, ctx->delta, (const C *)b0, S.pd, acc, st));
+        return CVL_OK;
+    }
+    LAUNCH(ST_ALPHA_FWD, launch_fwd_alpha(g, FullTabs<C>::fwd(S), v1, b1, st));
+    LAUNCH(ST_BETA_FWD, beta_gemm_any(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.beta, S.betaf,
+                                      false, b1, b0, st));
+    if constexpr (std::is_same<C, cd>::value) {
+        LAUNCH(ST_CONTRACT_FWD, launch_contract_fwd(g, ctx->delta, b0, S.psi, b1, st));
+        LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd(g, L, b1, S.ngroups, acc, st));
+    } else {
+        LAUNCH(ST_CONTRACT_FWD,
+               launch_contract_fwd_mx(precision, g, ctx->delta, b0, S.psi, b1, st));
+        LAUNCH(ST_REDUCE_FWD, launch_reduce_fwd_mx(g, L, b1, S.ngroups, acc, st));
+    }
+    return CVL_OK;
+}
+
+template <class C>
+static int analysis_scale_cplx_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                                 bool unrot, const CurveletBufs &B, C *grid, hipStream_t st) {
+    C *b0 = (C *)B.b0, *b1 = (C *)B.b1, *b2 = (C *)B.b2;
+    int rc = analysis_to_w2<C>(ctx, P, S, precision, unrot, B.fpad, b0, b1, b2, st);
+    if (!rc) rc = analysis_to_w2<C>(ctx, P, S, precision, unrot, B.fpadb, b0, b1, b0, st);
+    if (rc) return rc;
+    if (unrot)
+        LAUNCH(ST_GAMMA_INV, launch_unrot_inv_gamma_cplx(S.g, FullTabs<C>::inv(S), b2, b0, grid, st));
+    else
+        LAUNCH(ST_GAMMA_INV, launch_inv_gamma_cplx(S.g, FullTabs<C>::inv(S), b2, b0, grid, st));
+    return CVL_OK;
+}
+
+template <class C>
+static int synthesis_scale_cplx_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                                  bool unrot, const CurveletBufs &B, const C *grid,
+                                  hipStream_t st) {
+    C *b0 = (C *)B.b0, *b1 = (C *)B.b1, *b2 = (C *)B.b2;
+    if (unrot)
+        LAUNCH(ST_GAMMA_FWD, launch_unrot_fwd_gamma_cplx(S.g, FullTabs<C>::fwd(S), grid, b2, b0, st));
+    else
+        LAUNCH(ST_GAMMA_FWD, launch_fwd_gamma_cplx(S.g, FullTabs<C>::fwd(S), grid, b2, b0, st));
+    // the imaginary part first: its V1 plane sits in b0, which the stages reuse
+    int rc = synthesis_from_v1<C>(ctx, P, S, precision, unrot, b0, b0, b1, B.faccb, st);
+    if (!rc) rc = synthesis_from_v1<C>(ctx, P, S, precision, unrot, b2, b0, b1, B.facc, st);
+    return rc;
+}
+
+static int analysis_scale_cplx(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                               bool unrot, const CurveletBufs &B, void *grid, hipStream_t st) {
+    TagScope tag(S.g.L);
+    if (precision == CVL_FP64)
+        return analysis_scale_cplx_t<cd>(ctx, P, S, precision, unrot, B, (cd *)grid, st);
+    return analysis_scale_cplx_t<cf>(ctx, P, S, precision, unrot, B, (cf *)grid, st);
+}
+
+static int synthesis_scale_cplx(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
+                                bool unrot, const CurveletBufs &B, const void *grid,
+                                hipStream_t st) {
+    TagScope tag(S.g.L);
+    if (precision == CVL_FP64)
+        return synthesis_scale_cplx_t<cd>(ctx, P, S, precision, unrot, B, (const cd *)grid, st);
+    return synthesis_scale_cplx_t<cf>(ctx, P, S, precision, unrot, B, (const cf *)grid, st);
+}
+
+}  // extern "C++"
+
 // ---- side stream: the scales below the top band-limit run concurrently with
 // the top ones (they only meet in the sum over scales); every call forks and
 // joins it with events, so callers see plain stream order. ----
@@ -1161,6 +1468,47 @@ static int scaling_synthesis_run(cvl_ctx *ctx, const Plan *P, ShtRt *SP, const C
     return CVL_OK;
 }
 
+// Scaling part of the analysis of a complex signal: (W^Phi)_lm = phifac_l
+// f_lm on the flat coefficients of every m (X.flat), then the complex spin-0
+// inverse SHT at L_Phi (the scaling coefficients are a spin-0 map).
+static int scaling_analysis_cplx_run(cvl_ctx *ctx, const Plan *P, ShtRt *SP,
+                                     const CurveletBufs &X, cd *smap, hipStream_t st) {
+    LAUNCH(ST_MISC, launch_scale_flat(P->Lphi, P->phifac, X.flat, X.fphi, 0, st));
+    return sht_inverse_cplx_run(ctx, SP, 0, X.fphi, smap, X.cp0, X.cp1, st);
+}
+
+// Forward complex spin-0 SHT of the scaling map into X.fphi (flat); the
+// caller adds phifac_l times it into the synthesised coefficients.
+static int scaling_synthesis_cplx_run(cvl_ctx *ctx, ShtRt *SP, const CurveletBufs &X,
+                                      const cd *smap, hipStream_t st) {
+    return sht_forward_cplx_run(ctx, SP, 0, smap, X.fphi, X.cp0, X.cp1, st);
+}
+
+static int analysis_scales_cplx(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
+                                const CurveletBufs &B, void *const *grids, int s0, int s1,
+                                hipStream_t st) {
+    for (int s = s0; s < s1; ++s) {
+        int rc = analysis_scale_cplx(ctx, P, P->scales[s], p->precision, unrotated(p), B,
+                                     grids[s], st);
+        if (rc) return rc;
+    }
+    return CVL_OK;
+}
+
+// Zeroes B.facc and B.faccb, then adds the synthesis of scales [s0, s1).
+static int synthesis_scales_cplx(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
+                                 const CurveletBufs &B, const void *const *grids, int s0,
+                                 int s1, hipStream_t st) {
+    LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)P->L * P->L, st));
+    LAUNCH(ST_MISC, launch_zero(B.faccb, (size_t)P->L * P->L, st));
+    for (int s = s0; s < s1; ++s) {
+        int rc = synthesis_scale_cplx(ctx, P, P->scales[s], p->precision, unrotated(p), B,
+                                      grids[s], st);
+        if (rc) return rc;
+    }
+    return CVL_OK;
+}
+
 // Zeroes B.facc, then adds the synthesis of scales [s0, s1) into it.
 static int synthesis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
                             const CurveletBufs &B, const void *const *grids, int s0, int s1,
@@ -1175,21 +1523,222 @@ static int synthesis_scales(cvl_ctx *ctx, const Plan *P, const cvl_params *p,
     return CVL_OK;
 }
 
-int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *maps,
-                          double *scal_maps, void *const *grids, void *ws, size_t ws_bytes,
-                          void *stream) {
-    g_err.clear();
-    Plan *P;
-    int rc = check_curvelet_call(ctx, p, batch, maps, scal_maps, grids, ws, ws_bytes, &P);
-    if (rc) return rc;
-    const int nJ = P->J - P->J0 + 1;
-    for (int i = 0; i < batch * nJ; ++i)
-        if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
-    ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
-    hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
+static int curvelet_analysis_cplx(cvl_ctx *ctx, const cvl_params *p, const Plan *P, int batch,
+                                  const cd *maps, cd *scal_maps, void *const *grids,
+                                  const CurveletBufs &B, hipStream_t st, bool side_ok) {
     const CurveletBufs BS = side_bufs(B);
-    const int L = P->L, Lp = P->Lphi, nside = side_count(P);
+    const int L = P->L, Lp = P->Lphi, nJ = P->J - P->J0 + 1;
+    const int nside = side_ok ? side_count(P) : 0;
+    ShtRt *SL = ctx->sht[L].get(), *SP = ctx->sht[Lp].get();
+    cvl_ctx::Side *sd = nullptr;
+    int rc;
+    if (nside > 0 && (rc = get_side(ctx, st, &sd))) return rc;
+    for (int bi = 0; bi < batch; ++bi) {
+        const cd *map = maps + (size_t)bi * L * (2 * L - 1);
+        cd *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        void *const *g = grids + (size_t)bi * nJ;
+        if ((rc = sht_forward_cplx_run(ctx, SL, p->spin, map, B.flat, B.c0, B.c1, st))) return rc;
+        LAUNCH(ST_MISC, launch_flm_split(L, B.flat, B.fpad, B.fpadb, st));
+        if (!sd && (rc = scaling_analysis_cplx_run(ctx, P, SP, B, smap, st))) return rc;
+        if (sd && (rc = side_fork(sd, st))) return rc;
+        rc = analysis_scales_cplx(ctx, P, p, B, g, nside, nJ, st);
+        if (!rc && sd) rc = scaling_analysis_cplx_run(ctx, P, SP, BS, smap, sd->s);
+        if (!rc && sd) rc = analysis_scales_cplx(ctx, P, p, BS, g, 0, nside, sd->s);
+        const int rj = sd ? side_join(sd, st) : CVL_OK;
+        if (rc || (rc = rj)) return rc;
+    }
+    return CVL_OK;
+}
+
+static int curvelet_synthesis_cplx(cvl_ctx *ctx, const cvl_params *p, const Plan *P, int batch,
+                                   const cd *scal_maps, const void *const *grids, cd *maps,
+                                   const CurveletBufs &B, hipStream_t st) {
+    const CurveletBufs BS = side_bufs(B);
+    const int L = P->L, Lp = P->Lphi, nside = side_count(P), nJ = P->J - P->J0 + 1;
+    ShtRt *SL = ctx->sht[L].get(), *SP = ctx->sht[Lp].get();
+    cvl_ctx::Side *sd = nullptr;
+    int rc;
+    if (nside > 0 && (rc = get_side(ctx, st, &sd))) return rc;
+    for (int bi = 0; bi < batch; ++bi) {
+        const cd *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        cd *map = maps + (size_t)bi * L * (2 * L - 1);
+        const void *const *g = grids + (size_t)bi * nJ;
+        if (sd && (rc = side_fork(sd, st))) return rc;
+        rc = synthesis_scales_cplx(ctx, P, p, B, g, nside, nJ, st);
+        if (!rc && sd) rc = synthesis_scales_cplx(ctx, P, p, BS, g, 0, nside, sd->s);
+        if (!rc && sd) rc = scaling_synthesis_cplx_run(ctx, SP, BS, smap, sd->s);
+        const int rj = sd ? side_join(sd, st) : CVL_OK;
+        if (rc || (rc = rj)) return rc;
+        if (sd) {
+            LAUNCH(ST_MISC, launch_add(B.facc, BS.facc, (size_t)L * L, st));
+            LAUNCH(ST_MISC, launch_add(B.faccb, BS.faccb, (size_t)L * L, st));
+        } else if ((rc = scaling_synthesis_cplx_run(ctx, SP, B, smap, st))) {
+            return rc;
+        }
+        LAUNCH(ST_MISC, launch_flm_combine(L, B.facc, B.faccb, B.flat, 0, st));
+        LAUNCH(ST_MISC, launch_scale_flat(Lp, P->phifac, B.fphi, B.flat, 1, st));
+        if ((rc = sht_inverse_cplx_run(ctx, SL, p->spin, B.flat, map, B.c0, B.c1, st))) return rc;
+    }
+    return CVL_OK;
+}
+
+// ---- rotated spin-s curvelets (general Wigner layouts, caller's stream) ----
+static int get_spin_psi(cvl_ctx *ctx, const Plan *P, int spin, const std::vector<double *> **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto key = std::make_tuple(P->L, P->lambda, P->J0, spin);
+    auto it = ctx->spin_psi.find(key);
+    if (it == ctx->spin_psi.end()) {
+        const int L = P->L;
+        std::vector<double> kap = host::kappa_table(L, P->lambda, P->J0, P->J);
+        std::vector<double *> tabs;
+        for (const ScaleRt &S : P->scales) {
+            const int Lj = S.g.L, Nm = 2 * Lj - 1;
+            // theta_j = arccos(-s / lambda^j), clamped to [0, pi] where lambda^j < |s|
+            const double c = std::max(-1.0, std::min(1.0, -spin / std::pow(P->lambda, S.j)));
+            std::vector<double> z = host::zeta_rotated(Lj, std::acos(c));
+            const double *kj = &kap[(size_t)(S.j - P->J0) * L];
+            for (int l = 0; l < Lj; ++l) {
+                const double f = std::sqrt((2.0 * l + 1.0) / (8.0 * M_PI * M_PI)) * kj[l];
+                for (int n = 0; n < Nm; ++n) z[(size_t)l * Nm + n] *= f;
+            }
+            double *d;
+            int rc = ctx->arena.upload(z, &d);
+            if (rc) return rc;
+            tabs.push_back(d);
+        }
+        it = ctx->spin_psi.emplace(key, std::move(tabs)).first;
+    }
+    *out = &it->second;
+    return CVL_OK;
+}
+
+struct SpinBufs {
+    cd *g0, *g1, *F, *flat, *acc, *c0, *c1, *cp0, *cp1, *fphi;
+};
+
+static SpinBufs carve_spin(const Plan *P, void *ws, size_t ws_bytes) {
+    const int T = P->scales.back().g.L, L = P->L, Lp = P->Lphi;
+    const size_t Nm = 2 * T - 1, Nnp = (Nm + 31) / 32 * 32;
+    Carver cv{(char *)ws, ws_bytes};
+    SpinBufs B{};
+    B.g0 = cv.take<cd>((size_t)T * Nm * Nnp);
+    B.g1 = cv.take<cd>((size_t)T * Nm * Nnp);
+    B.F = cv.take<cd>((size_t)T * Nm * Nm);
+    B.flat = cv.take<cd>((size_t)L * L);
+    B.acc = cv.take<cd>((size_t)L * L);
+    B.c0 = cv.take<cd>((size_t)L * (2 * L - 1));
+    B.c1 = cv.take<cd>((size_t)L * (2 * L - 1));
+    B.cp0 = cv.take<cd>((size_t)Lp * (2 * Lp - 1));
+    B.cp1 = cv.take<cd>((size_t)Lp * (2 * Lp - 1));
+    B.fphi = cv.take<cd>((size_t)Lp * Lp);
+    return B;
+}
+
+// Grid of scale s from the flat coefficients B.flat.
+static int spin_analysis_scale(cvl_ctx *ctx, const Plan *P, int s, const double *psi,
+                               const SpinBufs &B, cd *grid, hipStream_t st) {
+    const ScaleGeom &g = P->scales[s].g;
+    const int Lj = g.L;
+    TagScope tag(Lj);
+    GenRt *G;
+    int rc = get_gen(ctx, Lj, Lj, &G);
+    if (rc) return rc;
+    const int Nnp = ((2 * Lj - 1) + 31) / 32 * 32, ncols = (2 * Lj - 1) * Nnp;
+    LAUNCH(ST_CONTRACT_INV,
+           launch_spin_contract_inv(Lj, g.llo, g.lhi, ctx->delta, B.flat, psi, B.g0, st));
+    LAUNCH(ST_BETA_INV, launch_beta_gemm(Lj, Lj, ncols, Nnp, 1, 0, G->beta.Cinv, G->beta.Sinv,
+                                         B.g0, B.g1, st));
+    LAUNCH(ST_ALPHA_INV, launch_gen_inv_alpha(Lj, Lj, G->a_inv, B.g1, B.g0, st));
+    LAUNCH(ST_GAMMA_INV, launch_gen_inv_gamma(Lj, Lj, G->g_inv, B.g0, grid, st));
+    return CVL_OK;
+}
+
+// acc (flat) += the synthesis of scale s's grid.
+static int spin_synthesis_scale(cvl_ctx *ctx, const Plan *P, int s, const double *psi,
+                                const SpinBufs &B, const cd *grid, cd *acc, hipStream_t st) {
+    const int Lj = P->scales[s].g.L;
+    TagScope tag(Lj);
+    GenRt *G;
+    int rc = get_gen(ctx, Lj, Lj, &G);
+    if (rc) return rc;
+    const int Nnp = ((2 * Lj - 1) + 31) / 32 * 32, ncols = (2 * Lj - 1) * Nnp;
+    LAUNCH(ST_GAMMA_FWD, launch_gen_fwd_gamma(Lj, Lj, G->g_fwd, grid, B.g0, st));
+    LAUNCH(ST_ALPHA_FWD, launch_gen_fwd_alpha(Lj, Lj, G->a_fwd, B.g0, B.g1, st));
+    LAUNCH(ST_BETA_FWD, launch_beta_gemm(Lj, Lj, ncols, Nnp, 1, 0, G->beta.Qp, G->beta.Qs, B.g1,
+                                         B.g0, st));
+    LAUNCH(ST_CONTRACT_FWD, launch_gen_contract_fwd(Lj, Lj, ctx->delta, B.g0, B.F, st));
+    LAUNCH(ST_REDUCE_FWD, launch_spin_reduce_fwd(Lj, B.F, psi, acc, st));
+    return CVL_OK;
+}
+
+static int spin_analysis_run(cvl_ctx *ctx, const cvl_params *p, const Plan *P, int batch,
+                             const cd *maps, cd *scal_maps, void *const *grids, void *ws,
+                             size_t ws_bytes, hipStream_t st) {
+    const std::vector<double *> *psi;
+    int rc = get_spin_psi(ctx, P, p->spin, &psi);
+    if (rc) return rc;
+    const SpinBufs B = carve_spin(P, ws, ws_bytes);
+    const int L = P->L, Lp = P->Lphi, nJ = P->J - P->J0 + 1;
+    ShtRt *SL = ctx->sht[L].get(), *SP = ctx->sht[Lp].get();
+    for (int bi = 0; bi < batch; ++bi) {
+        const cd *map = maps + (size_t)bi * L * (2 * L - 1);
+        cd *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        if ((rc = sht_forward_cplx_run(ctx, SL, p->spin, map, B.flat, B.c0, B.c1, st))) return rc;
+        LAUNCH(ST_MISC, launch_scale_flat(Lp, P->phifac, B.flat, B.fphi, 0, st));
+        if ((rc = sht_inverse_cplx_run(ctx, SP, 0, B.fphi, smap, B.cp0, B.cp1, st))) return rc;
+        for (int s = 0; s < nJ; ++s)
+            if ((rc = spin_analysis_scale(ctx, P, s, (*psi)[s], B,
+                                          (cd *)grids[(size_t)bi * nJ + s], st)))
+                return rc;
+    }
+    return CVL_OK;
+}
+
+static int spin_synthesis_run(cvl_ctx *ctx, const cvl_params *p, const Plan *P, int batch,
+                              const cd *scal_maps, const void *const *grids, cd *maps, void *ws,
+                              size_t ws_bytes, hipStream_t st) {
+    const std::vector<double *> *psi;
+    int rc = get_spin_psi(ctx, P, p->spin, &psi);
+    if (rc) return rc;
+    const SpinBufs B = carve_spin(P, ws, ws_bytes);
+    const int L = P->L, Lp = P->Lphi, nJ = P->J - P->J0 + 1;
+    ShtRt *SL = ctx->sht[L].get(), *SP = ctx->sht[Lp].get();
+    for (int bi = 0; bi < batch; ++bi) {
+        const cd *smap = scal_maps + (size_t)bi * Lp * (2 * Lp - 1);
+        cd *map = maps + (size_t)bi * L * (2 * L - 1);
+        LAUNCH(ST_MISC, launch_zero(B.acc, (size_t)L * L, st));
+        for (int s = 0; s < nJ; ++s)
+            if ((rc = spin_synthesis_scale(ctx, P, s, (*psi)[s], B,
+                                           (const cd *)grids[(size_t)bi * nJ + s], B.acc, st)))
+                return rc;
+        if ((rc = sht_forward_cplx_run(ctx, SP, 0, smap, B.fphi, B.cp0, B.cp1, st))) return rc;
+        LAUNCH(ST_MISC, launch_scale_flat(Lp, P->phifac, B.fphi, B.acc, 1, st));
+        if ((rc = sht_inverse_cplx_run(ctx, SL, p->spin, B.acc, map, B.c0, B.c1, st))) return rc;
+    }
+    return CVL_OK;
+}
+
+// The analysis launches of a validated call.  side_ok: the scales below the
+// top band-limit may run on the caller stream's side stream (the workspace
+// then holds their buffers too); otherwise every stage runs on the caller's
+// stream, in the first part of the workspace.
+static int curvelet_analysis_run(cvl_ctx *ctx, const cvl_params *p, const Plan *P, int batch,
+                                 const void *maps_v, void *scal_maps_v, void *const *grids,
+                                 void *ws, size_t ws_bytes, hipStream_t st, bool side_ok) {
+    int rc;
+    const int nJ = P->J - P->J0 + 1;
+    ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
+    if (spin_rotated(p))
+        return spin_analysis_run(ctx, p, P, batch, (const cd *)maps_v, (cd *)scal_maps_v, grids,
+                                 ws, ws_bytes, st);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), complex_map(p), ws, ws_bytes);
+    if (complex_map(p))
+        return curvelet_analysis_cplx(ctx, p, P, batch, (const cd *)maps_v, (cd *)scal_maps_v,
+                                      grids, B, st, side_ok);
+    const double *maps = (const double *)maps_v;
+    double *scal_maps = (double *)scal_maps_v;
+    const CurveletBufs BS = side_bufs(B);
+    const int L = P->L, Lp = P->Lphi, nside = side_ok ? side_count(P) : 0;
     cvl_ctx::Side *sd = nullptr;
     if (nside > 0 && (rc = get_side(ctx, st, &sd))) return rc;
     for (int bi = 0; bi < batch; ++bi) {
@@ -1213,19 +1762,41 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const do
     return CVL_OK;
 }
 
-int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const double *scal_maps,
-                           const void *const *grids, double *maps, void *ws, size_t ws_bytes,
+int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const void *maps_v,
+                          void *scal_maps_v, void *const *grids, void *ws, size_t ws_bytes,
+                          void *stream) {
+    g_err.clear();
+    Plan *P;
+    int rc = check_curvelet_call(ctx, p, batch, maps_v, scal_maps_v, grids, ws, ws_bytes, &P);
+    if (rc) return rc;
+    const int nJ = P->J - P->J0 + 1;
+    for (int i = 0; i < batch * nJ; ++i)
+        if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
+    return curvelet_analysis_run(ctx, p, P, batch, maps_v, scal_maps_v, grids, ws, ws_bytes,
+                                 (hipStream_t)stream, true);
+}
+
+int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const void *scal_maps_v,
+                           const void *const *grids, void *maps_v, void *ws, size_t ws_bytes,
                            void *stream) {
     g_err.clear();
     Plan *P;
-    int rc = check_curvelet_call(ctx, p, batch, scal_maps, maps, grids, ws, ws_bytes, &P);
+    int rc = check_curvelet_call(ctx, p, batch, scal_maps_v, maps_v, grids, ws, ws_bytes, &P);
     if (rc) return rc;
     const int nJ = P->J - P->J0 + 1;
     for (int i = 0; i < batch * nJ; ++i)
         if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
     ShtRt *SL = ctx->sht[P->L].get(), *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
+    if (spin_rotated(p))
+        return spin_synthesis_run(ctx, p, P, batch, (const cd *)scal_maps_v, grids, (cd *)maps_v,
+                                  ws, ws_bytes, st);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), complex_map(p), ws, ws_bytes);
+    if (complex_map(p))
+        return curvelet_synthesis_cplx(ctx, p, P, batch, (const cd *)scal_maps_v, grids,
+                                       (cd *)maps_v, B, st);
+    const double *scal_maps = (const double *)scal_maps_v;
+    double *maps = (double *)maps_v;
     const CurveletBufs BS = side_bufs(B);
     const int L = P->L, Lp = P->Lphi, nside = side_count(P);
     cvl_ctx::Side *sd = nullptr;
@@ -1268,7 +1839,18 @@ int cvl_curvelet_analysis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const 
     int s, rc = check_scale_call(ctx, p, j, flm, grid, ws, ws_bytes, &P, &s);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
+    if (spin_rotated(p)) {
+        const std::vector<double *> *psi;
+        if ((rc = get_spin_psi(ctx, P, p->spin, &psi))) return rc;
+        SpinBufs SB = carve_spin(P, ws, ws_bytes);
+        SB.flat = (cd *)flm;  // read only
+        return spin_analysis_scale(ctx, P, s, (*psi)[s], SB, (cd *)grid, st);
+    }
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), complex_map(p), ws, ws_bytes);
+    if (complex_map(p)) {
+        LAUNCH(ST_MISC, launch_flm_split(P->L, (const cd *)flm, B.fpad, B.fpadb, st));
+        return analysis_scale_cplx(ctx, P, P->scales[s], p->precision, unrotated(p), B, grid, st);
+    }
     LAUNCH(ST_MISC, launch_flm_pack(P->L, (const cd *)flm, B.fpad, st));
     return analysis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), unrotated(p), B,
                               grid, st);
@@ -1281,8 +1863,23 @@ int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const
     int s, rc = check_scale_call(ctx, p, j, grid, flm_acc, ws, ws_bytes, &P, &s);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
+    if (spin_rotated(p)) {
+        const std::vector<double *> *psi;
+        if ((rc = get_spin_psi(ctx, P, p->spin, &psi))) return rc;
+        const SpinBufs SB = carve_spin(P, ws, ws_bytes);
+        return spin_synthesis_scale(ctx, P, s, (*psi)[s], SB, (const cd *)grid, (cd *)flm_acc, st);
+    }
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), complex_map(p), ws, ws_bytes);
     const int L = P->L;
+    if (complex_map(p)) {
+        LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
+        LAUNCH(ST_MISC, launch_zero(B.faccb, (size_t)L * L, st));
+        if ((rc = synthesis_scale_cplx(ctx, P, P->scales[s], p->precision, unrotated(p), B, grid,
+                                       st)))
+            return rc;
+        LAUNCH(ST_MISC, launch_flm_combine(L, B.facc, B.faccb, (cd *)flm_acc, 1, st));
+        return CVL_OK;
+    }
     LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
     if ((rc = synthesis_scale_run(ctx, P, P->scales[s], p->precision, real_grids(p), unrotated(p),
                                   B, grid, st)))
@@ -1292,30 +1889,55 @@ int cvl_curvelet_synthesis_scale(cvl_ctx *ctx, const cvl_params *p, int j, const
 }
 
 int cvl_curvelet_scaling_analysis(cvl_ctx *ctx, const cvl_params *p, const cvl_c128 *flm,
-                                  double *scal_map, void *ws, size_t ws_bytes, void *stream) {
+                                  void *scal_map_v, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
     Plan *P;
-    int rc = check_curvelet_call(ctx, p, 1, flm, scal_map, flm, ws, ws_bytes, &P, true);
+    int rc = check_curvelet_call(ctx, p, 1, flm, scal_map_v, flm, ws, ws_bytes, &P, true);
     if (rc) return rc;
     ShtRt *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), complex_map(p), ws, ws_bytes);
     const int L = P->L, Lp = P->Lphi;
+    if (spin_rotated(p)) {  // the same steps in the buffers of that layout
+        const SpinBufs SB = carve_spin(P, ws, ws_bytes);
+        LAUNCH(ST_MISC, launch_scale_flat(Lp, P->phifac, (const cd *)flm, SB.fphi, 0, st));
+        return sht_inverse_cplx_run(ctx, SP, 0, SB.fphi, (cd *)scal_map_v, SB.cp0, SB.cp1, st);
+    }
+    if (complex_map(p)) {
+        LAUNCH(ST_MISC, launch_scale_flat(Lp, P->phifac, (const cd *)flm, B.fphi, 0, st));
+        return sht_inverse_cplx_run(ctx, SP, 0, B.fphi, (cd *)scal_map_v, B.cp0, B.cp1, st);
+    }
+    double *scal_map = (double *)scal_map_v;
     LAUNCH(ST_MISC, launch_flm_pack(L, (const cd *)flm, B.fpad, st));
     LAUNCH(ST_MISC, launch_scale_flm(Lp, L, Lp, P->phifac, B.fpad, B.fphi, 0, st));
     return sht_inverse_run(ctx, SP, B.fphi, Lp, scal_map, B.s0, B.s1, st);
 }
 
-int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p, const double *scal_map,
+int cvl_curvelet_scaling_synthesis(cvl_ctx *ctx, const cvl_params *p, const void *scal_map_v,
                                    cvl_c128 *flm_acc, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
     Plan *P;
-    int rc = check_curvelet_call(ctx, p, 1, scal_map, flm_acc, scal_map, ws, ws_bytes, &P, true);
+    int rc = check_curvelet_call(ctx, p, 1, scal_map_v, flm_acc, scal_map_v, ws, ws_bytes, &P, true);
     if (rc) return rc;
     ShtRt *SP = ctx->sht[P->Lphi].get();
     hipStream_t st = (hipStream_t)stream;
-    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), ws, ws_bytes);
+    CurveletBufs B = carve_curvelet(P, p->precision, unrotated(p), complex_map(p), ws, ws_bytes);
     const int L = P->L, Lp = P->Lphi;
+    if (complex_map(p)) {
+        CurveletBufs X = B;
+        if (spin_rotated(p)) {  // the same steps in the buffers of that layout
+            const SpinBufs SB = carve_spin(P, ws, ws_bytes);
+            X.fphi = SB.fphi;
+            X.cp0 = SB.cp0;
+            X.cp1 = SB.cp1;
+        }
+        if ((rc = sht_forward_cplx_run(ctx, SP, 0, (const cd *)scal_map_v, X.fphi, X.cp0, X.cp1,
+                                       st)))
+            return rc;
+        LAUNCH(ST_MISC, launch_scale_flat(Lp, P->phifac, X.fphi, (cd *)flm_acc, 1, st));
+        return CVL_OK;
+    }
+    const double *scal_map = (const double *)scal_map_v;
     if ((rc = sht_forward_run(ctx, SP, scal_map, B.fphi, Lp, B.s0, B.s1, st))) return rc;
     LAUNCH(ST_MISC, launch_zero(B.facc, (size_t)L * L, st));
     LAUNCH(ST_MISC, launch_scale_flm(Lp, Lp, L, P->phifac, B.fphi, B.facc, 1, st));

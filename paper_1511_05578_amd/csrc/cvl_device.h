@@ -260,6 +260,11 @@ hipError_t launch_gen_contract_inv(int L, int N, const double *delta, const cd *
 hipError_t launch_gen_contract_fwd(int L, int N, const double *delta, const cd *Z,
                                    cd *F, hipStream_t st);
 
+// Rotated spin-s curvelets on the general layouts (see kernels_linalg.hip).
+hipError_t launch_spin_contract_inv(int L, int llo, int lhi, const double *delta, const cd *flm,
+                                    const double *psi, cd *X, hipStream_t st);
+hipError_t launch_spin_reduce_fwd(int L, const cd *F, const double *psi, cd *acc, hipStream_t st);
+
 // SHT helpers.
 hipError_t launch_sht_inv_delta(int L, int Lf, const double *delta, const cd *fpad,
                                 cd *F, hipStream_t st);
@@ -271,6 +276,42 @@ hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, int accumulate, hip
 hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st);
 hipError_t launch_scale_flm(int Lphi, int Lsrc, int Ldst, const double *fac, const cd *src,
                             cd *dst, int accumulate, hipStream_t st);
+// Spin-s SHT of complex maps (every m, columns m + L - 1 of rows of 2L - 1).
+hipError_t launch_sht_inv_delta_spin(int L, int s, const double *delta, const cd *flm, cd *F,
+                                     hipStream_t st);
+hipError_t launch_sht_fwd_delta_spin(int L, int s, const double *delta, const cd *Z, cd *flm,
+                                     hipStream_t st);
+hipError_t launch_sht_theta_cols(int ncols, int par0, int Mrows, int Kdim, const double *Aeven,
+                                 const double *Aodd, const cd *in, cd *out, hipStream_t st);
+hipError_t launch_sht_inv_phi_cplx(int L, const BluesteinDev &B, const cd *G, cd *map,
+                                   hipStream_t st);
+hipError_t launch_sht_fwd_phi_cplx(int L, const BluesteinDev &B, const cd *map, cd *F1,
+                                   hipStream_t st);
+// Complex signals as two real parts (coefficient sets a, b with the reality
+// condition, padded [l][m >= 0]); flat coefficients of every m.
+hipError_t launch_flm_split(int L, const cd *flm, cd *fa, cd *fb, hipStream_t st);
+hipError_t launch_flm_combine(int L, const cd *fa, const cd *fb, cd *flm, int accumulate,
+                              hipStream_t st);
+hipError_t launch_scale_flat(int Lphi, const double *fac, const cd *src, cd *dst, int accumulate,
+                             hipStream_t st);
+// gamma stages of complex grids: W2a / V1a carry the real part's
+// coefficients, W2b / V1b the imaginary part's.
+hipError_t launch_inv_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B, const cd *W2a,
+                                 const cd *W2b, cd *grid, hipStream_t st);
+hipError_t launch_inv_gamma_cplx(const ScaleGeom &g, const BluesteinF &B, const cf *W2a,
+                                 const cf *W2b, cf *grid, hipStream_t st);
+hipError_t launch_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                                 cd *V1a, cd *V1b, hipStream_t st);
+hipError_t launch_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinF &B, const cf *grid,
+                                 cf *V1a, cf *V1b, hipStream_t st);
+hipError_t launch_unrot_inv_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B,
+                                       const cd *W2a, const cd *W2b, cd *grid, hipStream_t st);
+hipError_t launch_unrot_inv_gamma_cplx(const ScaleGeom &g, const BluesteinF &B,
+                                       const cf *W2a, const cf *W2b, cf *grid, hipStream_t st);
+hipError_t launch_unrot_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B,
+                                       const cd *grid, cd *V1a, cd *V1b, hipStream_t st);
+hipError_t launch_unrot_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinF &B,
+                                       const cf *grid, cf *V1a, cf *V1b, hipStream_t st);
 hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
 hipError_t launch_add(cd *dst, const cd *src, size_t n, hipStream_t st);  // dst += src
 

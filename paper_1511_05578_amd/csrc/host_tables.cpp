@@ -128,6 +128,34 @@ std::vector<double> delta_col_l(int L) {
     return out;
 }
 
+std::vector<double> zeta_rotated(int L, double theta) {
+    const int Nm = 2 * L - 1;
+    std::vector<double> z((size_t)L * Nm, 0.0);
+    const ld sh = std::sin((ld)theta / 2), ch = std::cos((ld)theta / 2);
+    // b^e in log space (0^0 = 1, 0^e = 0 for e > 0)
+    auto lpow = [](ld b, int e, bool *zero) -> ld {
+        if (e == 0) return 0.0L;
+        if (b <= 0.0L) {
+            *zero = true;
+            return 0.0L;
+        }
+        return (ld)e * std::log(b);
+    };
+    for (int l = 0; l < L; ++l) {
+        for (int n = -l; n <= l; ++n) {
+            const ld lb = 0.5L * (std::lgamma((ld)(2 * l + 1)) - std::lgamma((ld)(l + n + 1)) -
+                                  std::lgamma((ld)(l - n + 1)));
+            bool z1 = false, z2 = false;
+            const ld e1 = lb + lpow(sh, l - n, &z1) + lpow(ch, l + n, &z1);
+            const ld e2 = lb + lpow(sh, l + n, &z2) + lpow(ch, l - n, &z2);
+            const ld t1 = z1 ? 0.0L : std::exp(e1);
+            const ld t2 = z2 ? 0.0L : std::exp(e2) * ((n & 1) ? -1.0L : 1.0L);
+            z[(size_t)l * Nm + n + L - 1] = (double)((t1 + t2) / std::sqrt(2.0L));
+        }
+    }
+    return z;
+}
+
 void beta_inverse_mats(int L, std::vector<double> &C, std::vector<double> &S) {
     const long Nm = 2L * L - 1;
     C.assign((size_t)L * L, 0.0);

@@ -23,6 +23,14 @@ std::vector<double> phi_table(int L, double lam, int J0);
 // out[l * L + n] (zero for n > l).
 std::vector<double> delta_col_l(int L);
 
+// Directional component of spin-s curvelets rotated by rho* = (0, theta, 0)
+// (Sec. II-B): z[l * (2L - 1) + n + L - 1] = zeta_ln for 0 <= l < L, |n| <= l,
+// zeta_ln = (d^l_{n,l}(theta) + (-1)^l d^l_{n,-l}(theta)) / sqrt 2 from the
+// one-term edge cases of the factorial sum of d^l (Sec. II-A):
+// d^l_{n,l} = sqrt(C(2l, l+n)) sin(t/2)^(l-n) cos(t/2)^(l+n) and
+// d^l_{n,-l} = (-1)^(l-n) sqrt(C(2l, l+n)) sin(t/2)^(l+n) cos(t/2)^(l-n).
+std::vector<double> zeta_rotated(int L, double theta);
+
 // MW beta nodes of band-limit L: angles pi(2b+1)/(2L-1), as exact phases.
 // Inverse beta matrices (rows b, columns m' >= 0), parity-folded:
 //   C[b][m'] = (m' ? 2 : 1) cos(m' beta_b),  S[b][m'] = 2 sin(m' beta_b).

@@ -1130,6 +1130,164 @@ struct UnrotFwdAlphaIO {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Complex signals.  A complex map f = f_a + i f_b is analysed as its two real
+// parts' coefficient sets a_lm, b_lm (each with the reality condition), run
+// through the real-signal stages up to the gamma DFT, where the two enter one
+// complex transform per grid line: W(a, b, g) = W_a + i W_b, whose gamma
+// coefficients are z_n = A_n + i B_n with A_-n = conj A_n, B_-n = conj B_n.
+// The synthesis splits a complex grid line the same way:
+// A_n = (Z_n + conj Z_-n)/2, B_n = (Z_n - conj Z_-n)/(2i).
+// ---------------------------------------------------------------------------
+
+// gamma DFT of the analysis: line (a, b); even n of W2a (A) and W2b (B).
+template <class C_>
+struct InvGammaCplxIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 8;  // two loads per element
+    const C *W2a, *W2b;
+    C *grid;
+    int L, h, Nm;
+    struct Ctx {
+        const C *sa, *sb;
+        C *d;
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        const size_t o = ((size_t)b * Nm + a) * (h + 1);
+        return Ctx{W2a + o, W2b + o, grid + (size_t)line * Nm};
+    }
+    __device__ C load(const Ctx &c, int n) const {
+        const int k = (n < 0 ? -n : n) >> 1;
+        const C A = c.sa[k], B = c.sb[k];
+        const real_t<C> keep = (n & 1) ? 0 : 1;   // odd n: zero
+        const real_t<C> sg = n < 0 ? -1 : 1;      // conjugate both for n < 0
+        return C{keep * (A.x - sg * B.y), keep * (sg * A.y + B.x)};
+    }
+    __device__ void store(const Ctx &c, int g, C v) const { c.d[g] = v; }
+};
+
+// gamma DFT of the synthesis: line (a, b) of a complex grid split into the
+// even n >= 0 coefficients of its two real parts, V1a and V1b [b][a][n/2].
+template <class C_>
+struct FwdGammaCplxIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const C *grid;
+    C *V1a, *V1b;
+    int L, h, Nm;
+    struct Ctx {
+        const C *src;
+        C *da, *db;
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        const size_t o = ((size_t)b * Nm + a) * (h + 1);
+        return Ctx{grid + (size_t)line * Nm, V1a + o, V1b + o};
+    }
+    __device__ C load(const Ctx &c, int g) const { return c.src[g]; }
+    __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
+        if (n & 1) return;
+        const C czm = cconj(zmn);
+        const C s = cadd(zn, czm), d = csub(zn, czm);
+        c.da[n / 2] = C{s.x * (real_t<C>)0.5, s.y * (real_t<C>)0.5};
+        c.db[n / 2] = C{d.y * (real_t<C>)0.5, d.x * (real_t<C>)-0.5};
+    }
+};
+
+// The same two stages for the unrotated curvelets (every n; W2 / V1 rows of
+// L entries, n in [0, L)).
+template <class C_>
+struct UnrotInvGammaCplxIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 8;  // two loads per element
+    const C *W2a, *W2b;
+    C *grid;
+    int L, Nm;
+    struct Ctx {
+        const C *sa, *sb;
+        C *d;
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        const size_t o = ((size_t)b * Nm + a) * L;
+        return Ctx{W2a + o, W2b + o, grid + (size_t)line * Nm};
+    }
+    __device__ C load(const Ctx &c, int n) const {
+        const int k = n < 0 ? -n : n;
+        const C A = c.sa[k], B = c.sb[k];
+        const real_t<C> sg = n < 0 ? -1 : 1;
+        return C{A.x - sg * B.y, sg * A.y + B.x};
+    }
+    __device__ void store(const Ctx &c, int g, C v) const { c.d[g] = v; }
+};
+
+template <class C_>
+struct UnrotFwdGammaCplxIO {
+    using C = C_;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const C *grid;
+    C *V1a, *V1b;
+    int L, Nm;
+    struct Ctx {
+        const C *src;
+        C *da, *db;
+    };
+    __device__ Ctx at(int line) const {
+        const int a = line / L, b = line % L;
+        const size_t o = ((size_t)b * Nm + a) * L;
+        return Ctx{grid + (size_t)line * Nm, V1a + o, V1b + o};
+    }
+    __device__ C load(const Ctx &c, int g) const { return c.src[g]; }
+    __device__ void store_pair(const Ctx &c, int n, C zn, C zmn) const {
+        const C czm = cconj(zmn);
+        const C s = cadd(zn, czm), d = csub(zn, czm);
+        c.da[n] = C{s.x * (real_t<C>)0.5, s.y * (real_t<C>)0.5};
+        c.db[n] = C{d.y * (real_t<C>)0.5, d.x * (real_t<C>)-0.5};
+    }
+};
+
+// phi DFTs of the SHT of a complex map (every m, column m + L - 1).
+struct ShtInvPhiCplxIO {
+    using C = cd;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const cd *G;
+    cd *map;
+    int L, Nm;
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int t) const {
+        return Ctx{G + (size_t)t * Nm + (L - 1), map + (size_t)t * Nm};
+    }
+    __device__ cd load(const Ctx &c, int m) const { return c.src[m]; }
+    __device__ void store(const Ctx &c, int p, cd v) const { c.dst[p] = v; }
+};
+
+struct ShtFwdPhiCplxIO {
+    using C = cd;
+    static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
+    static constexpr int kBatch = 16;  // loads in flight per thread
+    const cd *map;
+    cd *F1;
+    int L, Nm;
+    struct Ctx {
+        const cd *src;
+        cd *dst;
+    };
+    __device__ Ctx at(int t) const {
+        return Ctx{map + (size_t)t * Nm, F1 + (size_t)t * Nm + (L - 1)};
+    }
+    __device__ cd load(const Ctx &c, int p) const { return c.src[p]; }
+    __device__ void store(const Ctx &c, int m, cd v) const { c.dst[m] = v; }
+};
+
 struct ShtInvPhiIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
@@ -1360,6 +1518,74 @@ hipError_t launch_unrot_fwd_alpha(const ScaleGeom &g, const BluesteinDev &B, con
 hipError_t launch_unrot_fwd_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *V1,
                                   cf *V2, hipStream_t st) {
     return unrot_fwd_alpha_t(g, B, V1, V2, st);
+}
+
+// ---- complex signals ----
+template <class C>
+static hipError_t inv_gamma_cplx_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2a,
+                                   const C *W2b, C *grid, hipStream_t st) {
+    InvGammaCplxIO<C> io{W2a, W2b, grid, g.L, g.h, g.Nm};
+    return run_bluestein(io, g.Nm * g.L, B, st);
+}
+template <class C>
+static hipError_t fwd_gamma_cplx_t(const ScaleGeom &g, const BlueT<C> &B, const C *grid, C *V1a,
+                                   C *V1b, hipStream_t st) {
+    FwdGammaCplxIO<C> io{grid, V1a, V1b, g.L, g.h, g.Nm};
+    return run_bluestein(io, g.Nm * g.L, B, st);
+}
+template <class C>
+static hipError_t unrot_inv_gamma_cplx_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2a,
+                                         const C *W2b, C *grid, hipStream_t st) {
+    UnrotInvGammaCplxIO<C> io{W2a, W2b, grid, g.L, g.Nm};
+    return run_bluestein(io, g.Nm * g.L, B, st);
+}
+template <class C>
+static hipError_t unrot_fwd_gamma_cplx_t(const ScaleGeom &g, const BlueT<C> &B, const C *grid,
+                                         C *V1a, C *V1b, hipStream_t st) {
+    UnrotFwdGammaCplxIO<C> io{grid, V1a, V1b, g.L, g.Nm};
+    return run_bluestein(io, g.Nm * g.L, B, st);
+}
+hipError_t launch_inv_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B, const cd *W2a,
+                                 const cd *W2b, cd *grid, hipStream_t st) {
+    return inv_gamma_cplx_t(g, B, W2a, W2b, grid, st);
+}
+hipError_t launch_inv_gamma_cplx(const ScaleGeom &g, const BluesteinF &B, const cf *W2a,
+                                 const cf *W2b, cf *grid, hipStream_t st) {
+    return inv_gamma_cplx_t(g, B, W2a, W2b, grid, st);
+}
+hipError_t launch_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B, const cd *grid,
+                                 cd *V1a, cd *V1b, hipStream_t st) {
+    return fwd_gamma_cplx_t(g, B, grid, V1a, V1b, st);
+}
+hipError_t launch_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinF &B, const cf *grid,
+                                 cf *V1a, cf *V1b, hipStream_t st) {
+    return fwd_gamma_cplx_t(g, B, grid, V1a, V1b, st);
+}
+hipError_t launch_unrot_inv_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B,
+                                       const cd *W2a, const cd *W2b, cd *grid, hipStream_t st) {
+    return unrot_inv_gamma_cplx_t(g, B, W2a, W2b, grid, st);
+}
+hipError_t launch_unrot_inv_gamma_cplx(const ScaleGeom &g, const BluesteinF &B,
+                                       const cf *W2a, const cf *W2b, cf *grid, hipStream_t st) {
+    return unrot_inv_gamma_cplx_t(g, B, W2a, W2b, grid, st);
+}
+hipError_t launch_unrot_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinDev &B,
+                                       const cd *grid, cd *V1a, cd *V1b, hipStream_t st) {
+    return unrot_fwd_gamma_cplx_t(g, B, grid, V1a, V1b, st);
+}
+hipError_t launch_unrot_fwd_gamma_cplx(const ScaleGeom &g, const BluesteinF &B,
+                                       const cf *grid, cf *V1a, cf *V1b, hipStream_t st) {
+    return unrot_fwd_gamma_cplx_t(g, B, grid, V1a, V1b, st);
+}
+hipError_t launch_sht_inv_phi_cplx(int L, const BluesteinDev &B, const cd *G, cd *map,
+                                   hipStream_t st) {
+    ShtInvPhiCplxIO io{G, map, L, 2 * L - 1};
+    return run_bluestein(io, L, B, st);
+}
+hipError_t launch_sht_fwd_phi_cplx(int L, const BluesteinDev &B, const cd *map, cd *F1,
+                                   hipStream_t st) {
+    ShtFwdPhiCplxIO io{map, F1, L, 2 * L - 1};
+    return run_bluestein(io, L, B, st);
 }
 
 hipError_t launch_sht_inv_phi(int L, const BluesteinDev &B, const cd *G, double *map,

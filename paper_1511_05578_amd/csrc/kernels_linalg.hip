@@ -907,6 +907,83 @@ __global__ void k_gen_contract_fwd(int L, int N, int Nnp, const double *__restri
     *o = ipow(s, m - n);
 }
 
+// Spin-s curvelets rotated to the North pole (Sec. II-B; rho* = (0, theta_j, 0)
+// with theta_j = arccos(-s / lambda^j)): the kernel coefficients Psi_ln are
+// real but non-zero at every n, and the signal has no reality condition, so
+// each scale runs on the general Wigner layouts with the harmonic product
+// folded into the contraction:
+//   X[m'][m][n] = i^{n-m} sum_l Delta^l_{m'm} Delta^l_{m'n} f_lm Psi_ln,
+// l over the kernel support [llo, lhi] and l >= max(|m|, |n|, m'); f flat
+// (band-limit Lf), psi [l][n + L - 1] (rows of 2L - 1).  The synthesis
+// contracts the forward Wigner coefficients with Psi:
+//   acc[l^2 + l + m] += sum_n F^l_mn Psi_ln.
+__global__ void k_spin_contract_inv(int L, int Nnp, int llo, int lhi,
+                                    const double *__restrict__ delta, const cd *__restrict__ flm,
+                                    const double *__restrict__ psi, cd *__restrict__ X) {
+    const int Nm = 2 * L - 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mp = blockIdx.y;
+    if (idx >= Nm * Nnp) return;
+    const int mi = idx / Nnp, ni = idx % Nnp;
+    cd *o = X + ((size_t)mp * Nm + mi) * Nnp + ni;
+    if (ni >= Nm) {
+        *o = cd{0.0, 0.0};
+        return;
+    }
+    const int m = mi - (L - 1), n = ni - (L - 1);
+    const int am = m < 0 ? -m : m, an = n < 0 ? -n : n;
+    int l0 = am > an ? am : an;
+    if (mp > l0) l0 = mp;
+    if (llo > l0) l0 = llo;
+    const int l1 = lhi < L - 1 ? lhi : L - 1;
+    cd s = cd{0.0, 0.0};
+    for (int l = l0; l <= l1; ++l) {
+        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        double w = row[am] * row[an] * psi[(size_t)l * Nm + ni];
+        const int flip = ((m < 0) + (n < 0)) * ((l + mp) & 1);
+        if (flip & 1) w = -w;
+        const cd f = flm[(size_t)l * l + l + m];
+        s.x += w * f.x;
+        s.y += w * f.y;
+    }
+    *o = ipow(s, n - m);
+}
+
+// One thread per (l, m) of l < L: a fixed-order sum over n.
+__global__ void k_spin_reduce_fwd(int L, const cd *__restrict__ F, const double *__restrict__ psi,
+                                  cd *__restrict__ acc) {
+    const int Nm = 2 * L - 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    int l = (int)sqrt((double)idx);
+    while (l * l > idx) --l;
+    while ((l + 1) * (l + 1) <= idx) ++l;
+    const int m = idx - l * l - l;
+    const cd *row = F + ((size_t)l * Nm + m + L - 1) * Nm;
+    const double *ps = psi + (size_t)l * Nm;
+    cd s = cd{0.0, 0.0};
+    for (int ni = L - 1 - l; ni <= L - 1 + l; ++ni) {
+        const double w = ps[ni];
+        s.x += w * row[ni].x;
+        s.y += w * row[ni].y;
+    }
+    acc[idx] = cadd(acc[idx], s);
+}
+
+hipError_t launch_spin_contract_inv(int L, int llo, int lhi, const double *delta, const cd *flm,
+                                    const double *psi, cd *X, hipStream_t st) {
+    const int Nnp = ((2 * L - 1) + 31) / 32 * 32;
+    const int n = (2 * L - 1) * Nnp;
+    hipLaunchKernelGGL(k_spin_contract_inv, dim3((n + 255) / 256, L), dim3(256), 0, st, L, Nnp,
+                       llo, lhi, delta, flm, psi, X);
+    return hipGetLastError();
+}
+hipError_t launch_spin_reduce_fwd(int L, const cd *F, const double *psi, cd *acc, hipStream_t st) {
+    hipLaunchKernelGGL(k_spin_reduce_fwd, dim3((L * L + 255) / 256), dim3(256), 0, st, L, F, psi,
+                       acc);
+    return hipGetLastError();
+}
+
 hipError_t launch_gen_contract_inv(int L, int N, const double *delta, const cd *F, cd *X,
                                    hipStream_t st) {
     const int Nnp = ((2 * N - 1) + 31) / 32 * 32;
@@ -1013,12 +1090,122 @@ hipError_t launch_sht_fwd_delta(int L, int Lf, const double *delta, const cd *Z,
                        Z, fpad);
     return hipGetLastError();
 }
-// theta stage of the SHT: out[r][m] = (i^(m&1)) sum_k A^{m&1}[r][k] in[k][m],
-// r < Mrows, k < Kdim, m < L.  Work-group: an 8 x 8 output tile, K in chunks
+// ---------------------------------------------------------------------------
+// Spin-s SHT of complex maps (Sec. II-A: sY_lm = (-1)^s c_l d^l_{m,-s}(theta)
+// e^{i m phi}, c_l = sqrt((2l+1)/(4 pi))), every m in (-L, L), column
+// c = m + L - 1.  Through the Fourier factorisation of d with Delta = d(pi/2):
+//   inverse: F[m'][c] = (-1)^s i^{-(m+s)} sum_{l >= max(|m|,|s|,m')}
+//                         c_l Delta^l_{m'm} Delta^l_{m',-s} f_lm,   m' >= 0
+//   forward: f_lm = (-1)^s i^{m+s} c_l sum_{m'<=l} Delta^l_{m'm} Delta^l_{m',-s} Z[m'][c]
+// (the theta stage folds -m' onto m' with the parity (-1)^{m+s} of the
+// product in m').  Quarter-table entries for negative indices:
+// Delta^l_{m',-k} = (-1)^{l+m'} Delta^l_{m'k}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double spin_sign(int l, int mp, int m, int s) {
+    // sign of Delta^l_{m'm} Delta^l_{m',-s} relative to row[|m|] row[|s|]
+    int q = 0;
+    if (m < 0) q += l + mp;
+    if (s > 0) q += l + mp;
+    return (q & 1) ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_sht_inv_delta_spin(int L, int s,
+                                                            const double *__restrict__ delta,
+                                                            const cd *__restrict__ flm,
+                                                            cd *__restrict__ F) {
+    __shared__ double red[4][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Nm = 2 * L - 1;
+    const int mp = blockIdx.y, c = blockIdx.x * 64 + lane, m = c - (L - 1);
+    const int am = m < 0 ? -m : m, as = s < 0 ? -s : s;
+    double sx = 0.0, sy = 0.0;
+    if (c < Nm) {
+        int l0 = am > mp ? am : mp;
+        if (as > l0) l0 = as;
+        for (int l = l0 + w; l < L; l += 4) {
+            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double v = sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * row[am] * row[as] *
+                             spin_sign(l, mp, m, s);
+            const cd f = flm[(size_t)l * l + l + m];
+            sx += v * f.x;
+            sy += v * f.y;
+        }
+    }
+    red[w][lane][0] = sx;
+    red[w][lane][1] = sy;
+    __syncthreads();
+    if (w == 0 && c < Nm) {
+        double tx = red[0][lane][0], ty = red[0][lane][1];
+        for (int q = 1; q < 4; ++q) {
+            tx += red[q][lane][0];
+            ty += red[q][lane][1];
+        }
+        cd v = ipow(cd{tx, ty}, -(m + s));
+        if (s & 1) v = cd{-v.x, -v.y};
+        F[(size_t)mp * Nm + c] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sht_fwd_delta_spin(int L, int s,
+                                                            const double *__restrict__ delta,
+                                                            const cd *__restrict__ Z,
+                                                            cd *__restrict__ flm) {
+    __shared__ double red[4][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Nm = 2 * L - 1;
+    const int l = blockIdx.y, k = blockIdx.x * 64 + lane, m = k - l;  // m in [-l, l]
+    const int am = m < 0 ? -m : m, as = s < 0 ? -s : s;
+    const bool live = k <= 2 * l && as <= l;
+    double sx = 0.0, sy = 0.0;
+    if (live) {
+        for (int mp = w; mp <= l; mp += 4) {
+            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double v = row[am] * row[as] * spin_sign(l, mp, m, s);
+            const cd z = Z[(size_t)mp * Nm + m + L - 1];
+            sx += v * z.x;
+            sy += v * z.y;
+        }
+    }
+    red[w][lane][0] = sx;
+    red[w][lane][1] = sy;
+    __syncthreads();
+    if (w == 0 && k <= 2 * l) {
+        cd v{0.0, 0.0};
+        if (live) {
+            double tx = red[0][lane][0], ty = red[0][lane][1];
+            for (int q = 1; q < 4; ++q) {
+                tx += red[q][lane][0];
+                ty += red[q][lane][1];
+            }
+            v = ipow(cscale(cd{tx, ty}, sqrt((2.0 * l + 1.0) / (4.0 * M_PI))), m + s);
+            if (s & 1) v = cd{-v.x, -v.y};
+        }
+        flm[(size_t)l * l + k] = v;
+    }
+}
+
+hipError_t launch_sht_inv_delta_spin(int L, int s, const double *delta, const cd *flm, cd *F,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(k_sht_inv_delta_spin, dim3((2 * L - 1 + 63) / 64, L), dim3(256), 0, st,
+                       L, s, delta, flm, F);
+    return hipGetLastError();
+}
+hipError_t launch_sht_fwd_delta_spin(int L, int s, const double *delta, const cd *Z, cd *flm,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(k_sht_fwd_delta_spin, dim3((2 * L - 1 + 63) / 64, L), dim3(256), 0, st,
+                       L, s, delta, Z, flm);
+    return hipGetLastError();
+}
+
+// theta stage of the SHT: out[r][m] = (i^(p)) sum_k A^{p}[r][k] in[k][m],
+// p = (m + par0) & 1, r < Mrows, k < Kdim, m < ncols (columns: m >= 0 of a
+// real spin-0 map with par0 = 0; or every m of a spin-s map, column
+// m + L - 1, with par0 the parity offset that makes p the parity of m + s).
+// Work-group: an 8 x 8 output tile, K in chunks
 // of 32 through LDS, each chunk's 32 terms split over the four waves (8 each)
 // and the wave sums added in LDS in wave order; small tiles so that there are
 // enough work-groups to fill the device at the band-limits of the SHT.
-__global__ __launch_bounds__(256) void k_sht_theta(int L, int Mrows, int Kdim,
+__global__ __launch_bounds__(256) void k_sht_theta(int L, int par0, int Mrows, int Kdim,
                                                    const double *__restrict__ Ae,
                                                    const double *__restrict__ Ao,
                                                    const cd *__restrict__ in,
@@ -1029,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_sht_theta(int L, int Mrows, int Kdim,
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tx = lane & 7, ty = lane >> 3;
     const int m = blockIdx.x * 8 + tx, r = blockIdx.y * 8 + ty;
-    const int par = m & 1;
+    const int par = (m + par0) & 1;
     double re = 0.0, im = 0.0;
     for (int k0 = 0; k0 < Kdim; k0 += 32) {
         {
@@ -1070,7 +1257,15 @@ __global__ __launch_bounds__(256) void k_sht_theta(int L, int Mrows, int Kdim,
 hipError_t launch_sht_theta(int L, int Mrows, int Kdim, int, const double *Aeven,
                             const double *Aodd, const cd *in, cd *out, hipStream_t st) {
     dim3 grid((L + 7) / 8, (Mrows + 7) / 8);
-    hipLaunchKernelGGL(k_sht_theta, grid, dim3(256), 0, st, L, Mrows, Kdim, Aeven, Aodd, in, out);
+    hipLaunchKernelGGL(k_sht_theta, grid, dim3(256), 0, st, L, 0, Mrows, Kdim, Aeven, Aodd, in,
+                       out);
+    return hipGetLastError();
+}
+hipError_t launch_sht_theta_cols(int ncols, int par0, int Mrows, int Kdim, const double *Aeven,
+                                 const double *Aodd, const cd *in, cd *out, hipStream_t st) {
+    dim3 grid((ncols + 7) / 8, (Mrows + 7) / 8);
+    hipLaunchKernelGGL(k_sht_theta, grid, dim3(256), 0, st, ncols, par0 & 1, Mrows, Kdim, Aeven,
+                       Aodd, in, out);
     return hipGetLastError();
 }
 
@@ -1101,6 +1296,76 @@ hipError_t launch_flm_unpack(int L, const cd *fpad, cd *flm, int accumulate, hip
 }
 hipError_t launch_flm_pack(int L, const cd *flm, cd *fpad, hipStream_t st) {
     hipLaunchKernelGGL(k_flm_pack, dim3((L * L + 255) / 256), dim3(256), 0, st, L, flm, fpad);
+    return hipGetLastError();
+}
+
+// Complex signals as two real parts: every f_lm (flat) <-> the coefficients
+// a, b (padded [l][m], m >= 0) of the real and imaginary parts of the signal,
+// each obeying the reality condition (x_{l,-m} = (-1)^m conj x_lm):
+//   a_lm = (f_lm + (-1)^m conj f_{l,-m}) / 2,  b_lm = (f_lm - (-1)^m conj f_{l,-m}) / (2i),
+//   f_lm = a_lm + i b_lm (every m, negative m of a and b by their reality).
+__global__ void k_flm_split(int L, const cd *__restrict__ flm, cd *__restrict__ fa,
+                            cd *__restrict__ fb) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    const int l = idx / L, m = idx % L;
+    cd a{0.0, 0.0}, b{0.0, 0.0};
+    if (m <= l) {
+        const cd p = flm[(size_t)l * l + l + m];
+        cd q = cconj(flm[(size_t)l * l + l - m]);
+        if (m & 1) q = cd{-q.x, -q.y};
+        a = cd{0.5 * (p.x + q.x), 0.5 * (p.y + q.y)};
+        // (p - q) / (2i) = -i (p - q) / 2
+        b = cd{0.5 * (p.y - q.y), -0.5 * (p.x - q.x)};
+    }
+    fa[idx] = a;
+    fb[idx] = b;
+}
+__global__ void k_flm_combine(int L, const cd *__restrict__ fa, const cd *__restrict__ fb,
+                              cd *__restrict__ flm, int accumulate) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * L) return;
+    int l = (int)sqrt((double)idx);
+    while (l * l > idx) --l;
+    while ((l + 1) * (l + 1) <= idx) ++l;
+    const int m = idx - l * l - l, am = m < 0 ? -m : m;
+    cd a = fa[(size_t)l * L + am], b = fb[(size_t)l * L + am];
+    if (m < 0) {
+        const double sg = (am & 1) ? -1.0 : 1.0;
+        a = cd{sg * a.x, -sg * a.y};
+        b = cd{sg * b.x, -sg * b.y};
+    }
+    const cd v{a.x - b.y, a.y + b.x};
+    flm[idx] = accumulate ? cadd(flm[idx], v) : v;
+}
+hipError_t launch_flm_split(int L, const cd *flm, cd *fa, cd *fb, hipStream_t st) {
+    hipLaunchKernelGGL(k_flm_split, dim3((L * L + 255) / 256), dim3(256), 0, st, L, flm, fa, fb);
+    return hipGetLastError();
+}
+hipError_t launch_flm_combine(int L, const cd *fa, const cd *fb, cd *flm, int accumulate,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_flm_combine, dim3((L * L + 255) / 256), dim3(256), 0, st, L, fa, fb,
+                       flm, accumulate);
+    return hipGetLastError();
+}
+
+// Flat coefficients (index l^2 + l + m, the same for every band-limit):
+// dst (=|+=) fac[l] src for l < Lphi, every m.
+__global__ void k_scale_flat(int Lphi, const double *__restrict__ fac, const cd *__restrict__ src,
+                             cd *__restrict__ dst, int accumulate) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Lphi * Lphi) return;
+    int l = (int)sqrt((double)idx);
+    while (l * l > idx) --l;
+    while ((l + 1) * (l + 1) <= idx) ++l;
+    const cd v = cscale(src[idx], fac[l]);
+    dst[idx] = accumulate ? cadd(dst[idx], v) : v;
+}
+hipError_t launch_scale_flat(int Lphi, const double *fac, const cd *src, cd *dst, int accumulate,
+                             hipStream_t st) {
+    const int n = Lphi * Lphi;
+    hipLaunchKernelGGL(k_scale_flat, dim3((n + 255) / 256), dim3(256), 0, st, Lphi, fac, src, dst,
+                       accumulate);
     return hipGetLastError();
 }
 

@@ -60,8 +60,11 @@ def test_workspace_grows_with_L():
     (dict(L=32, lam=float("nan")), api.CVL_EINVAL),
     (dict(L=32, J0=0), api.CVL_EINVAL),
     (dict(L=32, J0=6), api.CVL_EINVAL),
-    (dict(L=32, spin=2), api.CVL_EUNSUPPORTED),
-    (dict(L=32, flags=0), api.CVL_EUNSUPPORTED),
+    (dict(L=32, spin=2), api.CVL_EINVAL),             # a spin signal is complex
+    (dict(L=32, flags=0, spin=2, precision=api.CVL_FP32), api.CVL_EUNSUPPORTED),  # rotated spin: FP64
+    (dict(L=32, flags=0, spin=32), api.CVL_EINVAL),
+    (dict(L=32, flags=0, spin=-32), api.CVL_EINVAL),
+    (dict(L=32, flags=api.CVL_REAL_GRIDS), api.CVL_EINVAL),  # complex map, real grids
     (dict(L=32, flags=api.CVL_REAL | 8), api.CVL_EINVAL),
 ])
 def test_parameter_validation(kw, code):
@@ -72,6 +75,26 @@ def test_parameter_validation(kw, code):
     assert rc == code
     assert J.value == -7                       # nothing written on failure
     assert len(api.lib.cvl_last_error()) > 0
+
+
+@pytest.mark.parametrize("kw", [dict(flags=0), dict(flags=api.CVL_UNROTATED, spin=2),
+                                dict(flags=0, spin=2), dict(flags=0, spin=-5),
+                                dict(flags=api.CVL_UNROTATED, spin=-31),
+                                dict(flags=0, precision=api.CVL_FP32)])
+def test_complex_and_spin_params_accepted(kw):
+    p = api.params(32, **kw)
+    J = ctypes.c_int(-7)
+    assert api.lib.cvl_num_scales(ctypes.byref(p), ctypes.byref(J)) == api.CVL_OK
+    assert J.value == 5
+
+
+def test_complex_workspace_larger():
+    # a complex map carries a second W2 plane, coefficient sets and SHT scratch
+    for unrot in (False, True):
+        r = api.workspace_bytes(64, unrotated=unrot)
+        c = api.workspace_bytes(64, unrotated=unrot, complex_map=True)
+        assert c > r
+        assert api.scale_workspace_bytes(64, unrotated=unrot, complex_map=True) <= c
 
 
 def test_real_grids_flag_accepted():

@@ -1,0 +1,235 @@
+"""GPU: complex maps and spin-s signals through the C ABI, against the oracle.
+
+* Spin-s SHT of complex maps (Sec. II-A spin harmonics) against the oracle's
+  spin transforms.
+* Curvelet analysis / synthesis of complex maps: every grid element-wise
+  against the oracle, for the paper's accuracy experiment's signals
+  (Re, Im of f_lm ~ U[-1, 1], three repeats, L = 4 ... 128; Sec. III-C);
+  the round-trip max-abs f_lm error is printed per L, as that experiment
+  reports it.
+* Spin-s signals with the unrotated curvelets (their directional component
+  does not depend on s, Sec. II-B) and with the curvelets rotated to the
+  North pole by rho* = (0, arccos(-s / lambda^j), 0), whose kernel
+  coefficients are non-zero at every n.
+
+Bars: FP64 1e-10 relative L2 and max-abs relative; FP32 1e-5; BF16x3 1e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU, skipped
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import curvelet as ocurv  # noqa: E402
+from oracle import sht as osht  # noqa: E402
+from paper_1511_05578_amd import api, inputs  # noqa: E402
+
+TOL = 1e-10
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+def close(a, b, tol=TOL):
+    e = rel_l2(a, b)
+    mx = np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+    assert e < tol and mx < tol, (e, mx)
+    return e, mx
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def spin_flm(L, s, seed):
+    """Re, Im ~ U[-1, 1], zero for l < |s| (no spin-s harmonics there)."""
+    f = inputs.uniform_complex_flm(L, seed)
+    f[:s * s] = 0
+    return f
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(128, 0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.mark.parametrize("L,s", [(2, 0), (5, 0), (16, 0), (33, 0), (64, 0), (5, 1), (16, -2),
+                                 (33, 3), (64, 2), (17, -16)])
+def test_complex_sht(ctx, L, s):
+    say("complex SHT L=%d spin=%d" % (L, s))
+    f = spin_flm(L, abs(s), seed=100 + L)
+    ref = osht.inverse_spin(f, L, s)
+    m = host(ctx.sht_inverse(dev(f), L, spin=s, complex_map=True))
+    close(m, ref)
+    f2 = host(ctx.sht_forward(dev(ref), spin=s))
+    close(f2, f)
+
+
+def _analysis_check(ctx, plan, f, fmap, L, lam, J0, spin=0, unrotated=False, rows=None):
+    ref_scal = osht.inverse(ocurv.scaling_flm(plan, f), plan.Lphi)
+    scal, grids = ctx.curvelet_analysis(dev(fmap), lam, J0, spin=spin, unrotated=unrotated)
+    close(host(scal), ref_scal)
+    for s_, j in enumerate(plan.scales):
+        Lj = plan.Lj[j]
+        rr = list(range(Lj)) if rows is None else [r for r in rows if r < Lj]
+        ref = ocurv.analysis_scale(plan, f, j, rows=rr)
+        g = host(grids[s_])[:, rr, :]
+        e, mx = close(g, ref)
+        say("  scale %d (L_j=%d): rel L2 %.2e, max-abs rel %.2e" % (j, Lj, e, mx))
+    return scal, grids
+
+
+@pytest.mark.parametrize("L", [4, 8, 16, 32, 64, 128])
+def test_complex_curvelets_accuracy_experiment(ctx, L):
+    # the paper's accuracy experiment on complex signals, GPU against the oracle
+    lam, J0 = 2.0, 2 if L > 4 else 1
+    plan = ocurv.Plan(L, lam, J0)
+    for seed in range(3):
+        say("complex curvelets L=%d seed %d" % (L, seed))
+        f = inputs.uniform_complex_flm(L, seed)
+        fmap = osht.inverse(f, L)
+        rows = None if L <= 64 else [0, 1, 63, 126, 127]
+        scal, grids = _analysis_check(ctx, plan, f, fmap, L, lam, J0, rows=rows)
+        rec = ctx.curvelet_synthesis(scal, grids, L, lam, J0)
+        close(host(rec), fmap)
+        f_rec = host(ctx.sht_forward(rec))
+        err = np.abs(f_rec - f).max()
+        say("  round trip max |f_lm - f_lm'| = %.2e" % err)
+        assert err < 1e-10
+
+
+def test_complex_batch_streams_and_determinism(ctx):
+    L, lam, J0 = 32, 2.0, 2
+    say("complex batch / streamed / deterministic")
+    maps = np.stack([osht.inverse(inputs.uniform_complex_flm(L, 10 + i), L) for i in range(3)])
+    scal_b, grids_b = ctx.curvelet_analysis(dev(maps), lam, J0)
+    rec_b = host(ctx.curvelet_synthesis(scal_b, grids_b, L, lam, J0))
+    close(rec_b, maps)
+    for i in range(3):
+        scal_1, grids_1 = ctx.curvelet_analysis(dev(maps[i]), lam, J0)
+        assert np.array_equal(host(scal_b[i]), host(scal_1))
+        for a, b in zip(grids_b[i], grids_1):
+            assert np.array_equal(host(a), host(b))
+    scal_2, grids_2 = ctx.curvelet_analysis(dev(maps[0]), lam, J0)
+    for a, b in zip(grids_2, grids_b[0]):
+        assert np.array_equal(host(a), host(b))
+    # streaming interface: same grids, same map up to rounding order
+    keep = {}
+    rec_s, scal_s = ctx.round_trip_streamed(dev(maps[0]), lam, J0,
+                                            on_grid=lambda j, g: keep.__setitem__(j, host(g)))
+    assert np.array_equal(host(scal_s), host(scal_b[0]))
+    for s_, j in enumerate(range(J0, api.num_scales(L) + 1)):
+        assert np.array_equal(keep[j], host(grids_b[0][s_]))
+    assert rel_l2(host(rec_s), rec_b[0]) < 1e-14
+
+
+def test_complex_unrotated(ctx):
+    for L, lam, J0 in [(32, 2.0, 2), (20, 1.5, 2)]:
+        say("complex unrotated L=%d lambda=%g" % (L, lam))
+        plan = ocurv.Plan(L, lam, J0, rotated=False)
+        f = inputs.uniform_complex_flm(L, 5)
+        fmap = osht.inverse(f, L)
+        scal, grids = _analysis_check(ctx, plan, f, fmap, L, lam, J0, unrotated=True)
+        rec = ctx.curvelet_synthesis(scal, grids, L, lam, J0, unrotated=True)
+        close(host(rec), fmap)
+
+
+@pytest.mark.parametrize("L,s", [(16, 1), (32, 2), (32, -2), (33, 5)])
+def test_spin_unrotated_curvelets(ctx, L, s):
+    # spin-s signal, unrotated curvelets (zeta~ does not depend on s): the
+    # Wigner coefficients are f_lm Psi~*_ln as for spin 0, with f_lm the
+    # spin-s harmonic coefficients
+    lam, J0 = 2.0, 2
+    say("spin %d unrotated L=%d" % (s, L))
+    plan = ocurv.Plan(L, lam, J0, rotated=False)
+    f = spin_flm(L, abs(s), seed=200 + L + s)
+    fmap = osht.inverse_spin(f, L, s)
+    scal, grids = _analysis_check(ctx, plan, f, fmap, L, lam, J0, spin=s, unrotated=True)
+    rec = ctx.curvelet_synthesis(scal, grids, L, lam, J0, unrotated=True, spin=s)
+    close(host(rec), fmap)
+    # streamed
+    rec_s, _ = ctx.round_trip_streamed(dev(fmap), lam, J0, unrotated=True, spin=s)
+    close(host(rec_s), fmap)
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-5), ("bf16x3", 1e-3)])
+def test_complex_reduced_precision(ctx, prec, bound):
+    for L, unrot in [(32, False), (64, False), (32, True)]:
+        say("complex %s L=%d unrotated=%s" % (prec, L, unrot))
+        lam, J0 = 2.0, 2
+        plan = ocurv.Plan(L, lam, J0, rotated=not unrot)
+        f = inputs.uniform_complex_flm(L, 7)
+        fmap = osht.inverse(f, L)
+        ref_scal, ref_grids = ocurv.analysis(plan, f)
+        scal, grids = ctx.curvelet_analysis(dev(fmap), lam, J0, precision=prec, unrotated=unrot)
+        close(host(scal), ref_scal)
+        for s_, j in enumerate(plan.scales):
+            e, mx = close(host(grids[s_]), ref_grids[j], bound)
+            say("  scale %d rel L2 %.2e max-abs rel %.2e" % (j, e, mx))
+        rec = ctx.curvelet_synthesis(scal, grids, L, lam, J0, precision=prec, unrotated=unrot)
+        e, mx = close(host(rec), fmap, bound)
+        say("  round trip rel L2 %.2e" % e)
+
+
+def test_complex_l256_rows(ctx):
+    # L = 256 (the benchmark band-limit, FFT beta path at L_j = 256), one
+    # complex map: sampled oracle rows of the finest scales, round trip
+    L, lam, J0 = 256, 2.0, 2
+    c = api.Context(L, 0)
+    try:
+        plan = ocurv.Plan(L, lam, J0)
+        f = inputs.uniform_complex_flm(L, 1)
+        fmap = c.sht_inverse(dev(f), L, complex_map=True)
+        scal, grids = c.curvelet_analysis(fmap, lam, J0)
+        for s_, j in enumerate(plan.scales):
+            if plan.Lj[j] < 256:
+                continue
+            say("complex L=256: oracle rows of scale %d" % j)
+            ref = ocurv.analysis_scale(plan, f, j, rows=[0, 200, 255])
+            e, mx = close(host(grids[s_])[:, [0, 200, 255], :], ref)
+            say("  rel L2 %.2e max-abs rel %.2e" % (e, mx))
+        rec = c.curvelet_synthesis(scal, grids, L, lam, J0)
+        e, mx = close(host(rec), host(fmap))
+        say("  round trip rel L2 %.2e" % e)
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+@pytest.mark.parametrize("L,s", [(16, 1), (32, 2), (32, -2), (20, 3)])
+def test_spin_rotated_curvelets(ctx, L, s):
+    lam, J0 = 2.0, 2
+    say("spin %d rotated L=%d" % (s, L))
+    plan = ocurv.Plan(L, lam, J0, spin=s)
+    f = spin_flm(L, abs(s), seed=300 + L + s)
+    fmap = osht.inverse_spin(f, L, s)
+    scal, grids = _analysis_check(ctx, plan, f, fmap, L, lam, J0, spin=s)
+    rec = ctx.curvelet_synthesis(scal, grids, L, lam, J0, spin=s)
+    close(host(rec), fmap)
+    keep = {}
+    rec_s, scal_s = ctx.round_trip_streamed(dev(fmap), lam, J0, spin=s,
+                                            on_grid=lambda j, g: keep.__setitem__(j, host(g)))
+    for s_, j in enumerate(plan.scales):
+        assert np.array_equal(keep[j], host(grids[s_]))
+    close(host(rec_s), fmap)

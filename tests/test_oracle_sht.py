@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 import scipy.special as sps
 
 from oracle import sampling, sht
@@ -85,3 +86,74 @@ def test_point_source_flm_library_and_peak():
     val = sum(one[sht.lm_index(l, m)] * sps.sph_harm_y(l, m, th[0], ph[0])
               for l in range(L) for m in range(-l, l + 1))
     assert abs(val - 2.0 * L * L / (4 * np.pi)) < 1e-12
+
+
+# ---- spin-s transforms (Sec. II-A) ----
+
+def _sY_sum(l, m, s, th, ph):
+    # sY_lm from the explicit factorial sum of d (exact, mpmath)
+    from oracle import wigner
+    return ((-1.0) ** s * math.sqrt((2 * l + 1) / (4 * math.pi))
+            * float(wigner.d_sum(l, m, -s, th)) * np.exp(1j * m * ph))
+
+
+@pytest.mark.parametrize("s", [0, 1, -2, 3])
+def test_inverse_spin_against_explicit_sum(s):
+    L = 6
+    rng = np.random.default_rng(40 + s)
+    f = rng.standard_normal(L * L) + 1j * rng.standard_normal(L * L)
+    for l in range(abs(s)):
+        f[l * l:(l + 1) * (l + 1)] = 0
+    m_ = sht.inverse_spin(f, L, s)
+    th = sampling.mw_theta(L)
+    ph = sampling.mw_phi(L)
+    for t in (0, 2, L - 1):
+        for p in (0, 3, 2 * L - 2):
+            ref = sum(f[sht.lm_index(l, m)] * _sY_sum(l, m, s, th[t], ph[p])
+                      for l in range(abs(s), L) for m in range(-l, l + 1))
+            assert abs(m_[t, p] - ref) < 1e-13
+
+
+def test_spin_one_textbook_value():
+    # 1Y_10 = sqrt(3/(8 pi)) sin(theta) in the convention of Sec. II-A
+    L = 3
+    f = np.zeros(L * L, dtype=np.complex128)
+    f[sht.lm_index(1, 0)] = 1.0
+    m_ = sht.inverse_spin(f, L, 1)
+    th = sampling.mw_theta(L)
+    assert np.allclose(m_, (math.sqrt(3 / (8 * math.pi)) * np.sin(th))[:, None], atol=1e-15)
+
+
+def test_spin_ll_closed_form():
+    # the closed form of d^l_{l,-s}(theta) the paper writes in its FWHM analysis
+    # (Sec. II-B): (-1)^(l+s) sqrt((2l)!/((l-s)!(l+s)!)) sin(theta/2)^(l+s) cos(theta/2)^(l-s)
+    L, s, l = 9, 2, 7
+    f = np.zeros(L * L, dtype=np.complex128)
+    f[sht.lm_index(l, l)] = 1.0
+    m_ = sht.inverse_spin(f, L, s)
+    th = sampling.mw_theta(L)
+    ph = sampling.mw_phi(L)
+    d = ((-1.0) ** (l + s) * math.sqrt(math.factorial(2 * l) / (math.factorial(l + s) * math.factorial(l - s)))
+         * np.cos(th / 2) ** (l - s) * np.sin(th / 2) ** (l + s))
+    ref = (-1.0) ** s * math.sqrt((2 * l + 1) / (4 * math.pi)) * d[:, None] * np.exp(1j * l * ph)[None, :]
+    assert np.abs(m_ - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("s", [0, 2, -1])
+def test_spin_round_trip_and_conjugate_symmetry(s):
+    L = 10
+    rng = np.random.default_rng(7)
+    f = rng.uniform(-1, 1, L * L) + 1j * rng.uniform(-1, 1, L * L)
+    for l in range(abs(s)):
+        f[l * l:(l + 1) * (l + 1)] = 0
+    m_ = sht.inverse_spin(f, L, s)
+    assert np.abs(sht.forward_spin(m_, L, s) - f).max() < 1e-12
+    # conj(sY_lm) = (-1)^(s+m) (-s)Y_{l,-m}: conj of the spin-s map is the
+    # spin -s map of g_lm = (-1)^(s+m) conj(f_{l,-m})
+    g = np.zeros_like(f)
+    for l in range(L):
+        for m in range(-l, l + 1):
+            g[sht.lm_index(l, m)] = (-1.0) ** (s + m) * np.conj(f[sht.lm_index(l, -m)])
+    assert np.abs(np.conj(m_) - sht.inverse_spin(g, L, -s)).max() < 1e-12
+    if s == 0:  # spin 0 agrees with the spin-0 transforms (pinned to library Y_lm)
+        assert np.abs(m_ - sht.inverse(f, L)).max() < 1e-13
