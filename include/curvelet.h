@@ -212,6 +212,27 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch,
                           void *const *grids, void *ws, size_t ws_bytes,
                           void *stream);
 
+/* Bytes of the static device scratch of cvl_curvelet_analysis_noalloc. */
+#define CVL_NOALLOC_SCRATCH_BYTES (80u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * analysis as cvl_curvelet_analysis, with the same arguments and results,
+ * but with no workspace argument and no allocation of any kind.  Its scratch
+ * is a static device array of CVL_NOALLOC_SCRATCH_BYTES (80 MiB) per GPU,
+ * held by the library until the process ends, so a call must fit it: it
+ * needs cvl_scale_workspace_bytes(p) bytes (FP64 real maps up to L = 128,
+ * for example); larger ones return CVL_ENOMEM.  Every stage runs on the
+ * caller's stream (no side stream).  Requirements, checked before anything
+ * is enqueued: the tables of (L, lambda, J0) exist (cvl_prepare, else
+ * CVL_EINVAL) and per-stage timing is off (CVL_EINVAL).  Every call on one
+ * GPU shares that GPU's scratch, which keeps the last call's contents:
+ * calls that overlap on one GPU (on different streams, or from different
+ * contexts or threads) race; order them on one stream. */
+int cvl_curvelet_analysis_noalloc(cvl_ctx *ctx, const cvl_params *p, int batch,
+                                  const void *maps, void *scal_maps,
+                                  void *const *grids, void *stream);
+
 /* Curvelet synthesis (Sec. II-D-2, exact reconstruction): the inverse of
  * cvl_curvelet_analysis on its range.  With CVL_REAL: synthesis is linear,
  * and a grid's imaginary part only feeds the imaginary part of the

@@ -57,6 +57,9 @@ SIGNATURES = {
     "cvl_curvelet_analysis": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams), ctypes.c_int,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cvl_curvelet_analysis_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams),
+                                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                     ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "cvl_curvelet_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CvlParams), ctypes.c_int,
                                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,

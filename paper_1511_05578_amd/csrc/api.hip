@@ -133,10 +133,19 @@ struct GenRt {
 
 }  // namespace
 
+// Scratch of cvl_curvelet_analysis_noalloc: a file-scope device array of
+// CVL_NOALLOC_SCRATCH_BYTES, one copy per GPU, held while the library is
+// loaded.  In host code the name `scratch` is a host-side stand-in, not a
+// device address: its address on each device comes from hipGetSymbolAddress
+// (cvl_context_create, with the context's device current) and is the only
+// handle host code passes on.
+static __device__ __align__(256) unsigned char scratch[CVL_NOALLOC_SCRATCH_BYTES];
+
 struct cvl_ctx {
     int device = 0;
     int Lmax = 0;
     double *delta = nullptr;
+    void *scratch_dev = nullptr;  // this device's copy of `scratch`
     std::mutex mu;
     DeviceArena arena;
     std::map<int, cd *> tw;
@@ -710,6 +719,15 @@ int cvl_context_create(cvl_ctx **out, int L_max, int device) {
     c->device = device;
     c->Lmax = L_max;
     HIP_TRY(hipSetDevice(device));
+    // device address of the static scratch on this device (set-up of the
+    // allocation-free entry point; allocates nothing)
+    {
+        void *sp = nullptr;
+        e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !sp)
+            return fail(CVL_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        c->scratch_dev = sp;
+    }
     size_t n = (size_t)delta_off(L_max);
     void *p = nullptr;
     e = hipMalloc(&p, n * sizeof(double));
@@ -1774,6 +1792,41 @@ int cvl_curvelet_analysis(cvl_ctx *ctx, const cvl_params *p, int batch, const vo
         if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
     return curvelet_analysis_run(ctx, p, P, batch, maps_v, scal_maps_v, grids, ws, ws_bytes,
                                  (hipStream_t)stream, true);
+}
+
+int cvl_curvelet_analysis_noalloc(cvl_ctx *ctx, const cvl_params *p, int batch,
+                                  const void *maps, void *scal_maps, void *const *grids,
+                                  void *stream) {
+    g_err.clear();
+    int J, rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_params(p, &J))) return rc;
+    if (batch < 1) return fail(CVL_EINVAL, "batch=%d < 1", batch);
+    if (!maps || !scal_maps || !grids) return fail(CVL_EINVAL, "NULL pointer argument");
+    if (p->L > ctx->Lmax) return fail(CVL_EINVAL, "L=%d exceeds the context's L_max=%d", p->L, ctx->Lmax);
+    if (!ctx->scratch_dev) return fail(CVL_EDEVICE, "no device address for the static scratch");
+    const Plan *P = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->prof)
+            return fail(CVL_EINVAL, "per-stage timing is on: its events would be created here");
+        auto it = ctx->plans.find(std::make_tuple(p->L, p->lambda, p->J0));
+        if (it == ctx->plans.end() || !ctx->sht.count(p->L) ||
+            !ctx->sht.count(it->second->Lphi))
+            return fail(CVL_EINVAL, "the tables of (L=%d, lambda=%g, J0=%d) are not built: call "
+                                    "cvl_prepare first", p->L, p->lambda, p->J0);
+        P = it->second.get();
+    }
+    const size_t need = ws_bytes_of(p, P->J, true);
+    if (need > (size_t)CVL_NOALLOC_SCRATCH_BYTES)
+        return fail(CVL_ENOMEM, "this call needs %zu bytes of scratch, above the static %zu",
+                    need, (size_t)CVL_NOALLOC_SCRATCH_BYTES);
+    const int nJ = P->J - P->J0 + 1;
+    for (int i = 0; i < batch * nJ; ++i)
+        if (!grids[i]) return fail(CVL_EINVAL, "grids[%d] is NULL", i);
+    if ((rc = set_device(ctx))) return rc;
+    return curvelet_analysis_run(ctx, p, P, batch, maps, scal_maps, grids, ctx->scratch_dev, need,
+                                 (hipStream_t)stream, false);
 }
 
 int cvl_curvelet_synthesis(cvl_ctx *ctx, const cvl_params *p, int batch, const void *scal_maps_v,
