@@ -232,9 +232,11 @@ def kernel_symbol(stage, Lj, prec, real_grids=False, unrot=False):
     c = "cd" if prec == "fp64" else "cf"
     P = bluestein_size(Lj)
     u = "Unrot" if unrot else ""
+    # the packed gamma stages at even L_j with P = 1024 run one FFT at half length
+    odd = "Odd" if (P == 1024 and Lj % 2 == 0 and not unrot) else ""
     io = {"alpha_dft_inv": u + "InvAlphaIO", "alpha_dft_fwd": u + "FwdAlphaIO",
-          "gamma_dft_inv": u + ("InvGammaPackIO" if P >= 256 else "InvGammaIO"),
-          "gamma_dft_fwd": u + ("FwdGammaPackIO" if P >= 256 else "FwdGammaIO")}
+          "gamma_dft_inv": u + ("InvGammaPack%sIO" % odd if P >= 256 else "InvGammaIO"),
+          "gamma_dft_fwd": u + ("FwdGammaPack%sIO" % odd if P >= 256 else "FwdGammaIO")}
     if stage in io:
         targs = c
         if stage.startswith("gamma"):  # grid element type

@@ -32,6 +32,20 @@ struct HasLive : std::false_type {};
 template <class T>
 struct HasLive<T, std::void_t<decltype(std::declval<const T &>().live(0))>> : std::true_type {};
 
+// An IO policy may declare `static constexpr bool kOddIn`: its inputs are
+// non-zero only at odd window positions t (and t < P/2), so the register
+// engine's first FFT is a half-length FFT of the odd samples; or
+// `kOddOut`: only odd output positions are read, so its second FFT is a
+// half-length FFT of the folded sequence.  (Both for P = 1024, T = 64.)
+template <class T, class = void>
+struct OddIn : std::false_type {};
+template <class T>
+struct OddIn<T, std::void_t<decltype(T::kOddIn)>> : std::integral_constant<bool, T::kOddIn> {};
+template <class T, class = void>
+struct OddOut : std::false_type {};
+template <class T>
+struct OddOut<T, std::void_t<decltype(T::kOddOut)>> : std::integral_constant<bool, T::kOddOut> {};
+
 // Output modes: IO_PAIR hands the policy output pairs (k, -k) of a symmetric
 // window, line by line; IO_STAGED_PAIR does the same with the work-group's
 // lines interleaved (neighbouring lines neighbouring in memory).
@@ -347,6 +361,32 @@ __device__ __forceinline__ void twiddle16(C v[16], C w1) {
     v[15] = cmul(v[15], cmul(w12, w3));
 }
 
+// v[r] *= w^r for r = 1..7 (w^r from w by a product tree, used as produced).
+template <class C>
+__device__ __forceinline__ void twiddle8(C v[8], C w1) {
+    const C w2 = cmul(w1, w1), w4 = cmul(w2, w2), w3 = cmul(w2, w1);
+    v[1] = cmul(v[1], w1);
+    v[2] = cmul(v[2], w2);
+    v[3] = cmul(v[3], w3);
+    v[4] = cmul(v[4], w4);
+    v[5] = cmul(v[5], cmul(w4, w1));
+    v[6] = cmul(v[6], cmul(w4, w2));
+    v[7] = cmul(v[7], cmul(w4, w3));
+}
+
+// u[e] *= W^{j + 64 e}, e = 0..7, W = e^{-2 pi i / 1024}: W^j from the table
+// times powers of the constant W^64 = e^{-i pi / 8}.
+template <class C>
+__device__ __forceinline__ void twiddle_stride64(C u[8], C wj) {
+    const C c1 = cmk<C>(CVL_C1, -CVL_S1);  // e^{-i pi / 8}
+    C w = wj;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        u[e] = cmul(u[e], w);
+        if (e < 7) w = cmul(w, c1);
+    }
+}
+
 // Forward FFT of one line; v[s] = element tid + T*s on entry and on exit.
 template <int P, class C>
 __device__ __forceinline__ void fft_r16(C v[16], real_t<C> *lds, const C *__restrict__ tw,
@@ -381,14 +421,7 @@ __device__ __forceinline__ void fft_r16(C v[16], real_t<C> *lds, const C *__rest
                 u[2] = cmul(u[2], w2);
                 u[3] = cmul(u[3], cmul(w2, w1));
             } else if constexpr (RC == 8) {
-                const C w2 = cmul(w1, w1), w4 = cmul(w2, w2), w3 = cmul(w2, w1);
-                u[1] = cmul(u[1], w1);
-                u[2] = cmul(u[2], w2);
-                u[3] = cmul(u[3], w3);
-                u[4] = cmul(u[4], w4);
-                u[5] = cmul(u[5], cmul(w4, w1));
-                u[6] = cmul(u[6], cmul(w4, w2));
-                u[7] = cmul(u[7], cmul(w4, w3));
+                twiddle8(u, w1);
             } else {
                 twiddle16(u, w1);
             }
@@ -403,6 +436,51 @@ __device__ __forceinline__ void fft_r16(C v[16], real_t<C> *lds, const C *__rest
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = t[k];
     }
+}
+
+// Moves 8 values per thread through the LDS line (one real component at a
+// time), as `exchange` does for 16.
+template <int P, class C, class WO, class RO>
+__device__ __forceinline__ void exchange8(C v[8], real_t<C> *lds, int wb, WO wo, int rb, RO ro) {
+    real_t<C> nx[8];
+    real_t<C> *w = lds + wb;
+    const real_t<C> *r = lds + rb;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[wo(k)] = v[k].x;
+    line_sync<P>();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) nx[i] = r[ro(i)];
+    line_sync<P>();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[wo(k)] = v[k].y;
+    line_sync<P>();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = C{nx[i], r[ro(i)]};
+    line_sync<P>();
+}
+
+// Forward FFT of 512 points held by the 64 threads of a 1024-point line, 8
+// each: v[s] = element tid + 64 s on entry and on exit.  Stockham radix-8,
+// three passes (Ns = 1, 8, 64); twiddles e^{-2 pi i x / 512} = tw[2x] of the
+// 1024-point table.
+template <int P, class C>
+__device__ __forceinline__ void fft_r8_512(C v[8], real_t<C> *lds, const C *__restrict__ tw,
+                                           int tid) {
+    static_assert(P == 1024, "half-length FFT of a 1024-point line");
+    dft8(v);  // pass Ns = 1: outputs 8 tid + k
+    const int rb = lpad(tid);
+    exchange8<P>(
+        v, lds, lpad(8 * tid), [](int k) { return k; }, rb, [](int r) { return lpo(64 * r); });
+    {  // pass Ns = 8: twiddle w^{r k}, w = e^{-2 pi i / 64}, k = tid mod 8
+        twiddle8(v, tw[16 * (tid & 7)]);
+        dft8(v);  // outputs (tid / 8) 64 + (tid mod 8) + 8 k'
+    }
+    exchange8<P>(
+        v, lds, lpad((tid >> 3) * 64 + (tid & 7)), [](int k) { return lpo(8 * k); }, rb,
+        [](int r) { return lpo(64 * r); });
+    // pass Ns = 64: twiddle w^{r tid}, w = e^{-2 pi i / 512}; outputs tid + 64 k'
+    twiddle8(v, tw[2 * tid]);
+    dft8(v);
 }
 
 // Three waves per SIMD for lines that fit one wavefront (the kernel is latency
@@ -436,10 +514,53 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
         vh = v2;
     }
     C v[16];
+    constexpr bool kOI = OddIn<IO>::value, kOO = OddOut<IO>::value;
+    static_assert(!(kOI || kOO) || P == 1024, "odd-input / odd-output paths need P = 1024");
     // Every load of a line is issued before any is used: indices are clamped
     // into the window and out-of-window elements zeroed afterwards, so no
     // load waits behind a branch (the IO policies' loads are branch-free too).
-    if constexpr (IO::kLoad == IO_DIRECT) {
+    if constexpr (kOI) {
+        // inputs only at odd t = 2u + 1 < P/2: the FFT of the window is
+        // FFT_P(a)(k) = W^k FFT_{P/2}(a'')(k mod P/2), a''_u = a_{2u+1},
+        // W = e^{-2 pi i / P}.  Load a''_u at u = tid + 64 s, s < 8.
+        static_assert(IO::kLoad == IO_DIRECT, "odd-input path loads directly");
+        C u8[8];
+        if (line < nlines) {
+            const auto c = io.at(line);
+#pragma unroll
+            for (int h = 0; h < 8; h += 4) {
+                if (2 * T * h >= B.Kin) {  // past the input (uniform)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) u8[h + e] = C{0, 0};
+                    continue;
+                }
+                C raw[4], pw[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int t = 2 * (tid + T * (h + e)) + 1;
+                    const int tc = t < B.Kin ? t : B.Kin - 1;
+                    raw[e] = io.load(c, B.j0 + tc);
+                    pw[e] = B.pre[tc];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int t = 2 * (tid + T * (h + e)) + 1;
+                    u8[h + e] = cscale(cmul(raw[e], pw[e]), (real_t<C>)(t < B.Kin ? 1 : 0));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) u8[e] = C{0, 0};
+        }
+        fft_r8_512<P>(u8, lds, B.tw, tid);
+        // v[s] = W^k Y''(k mod 512), k = tid + 64 s; W^{k + 512} = -W^k
+        twiddle_stride64(u8, B.tw[tid]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            v[e] = u8[e];
+            v[e + 8] = C{-u8[e].x, -u8[e].y};
+        }
+    } else if constexpr (IO::kLoad == IO_DIRECT) {
         if (line < nlines) {
             const auto c = io.at(line);
 #pragma unroll
@@ -507,16 +628,30 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
         }
         __syncthreads();
     }
-    fft_r16<P>(v, lds, B.tw, tid);
+    if constexpr (!kOI) fft_r16<P>(v, lds, B.tw, tid);
 #pragma unroll
     for (int s = 0; s < 16; ++s) v[s] = cconj(cmul(v[s], vh[tid + T * s]));
-    fft_r16<P>(v, lds, B.tw, tid);
+    if constexpr (kOO) {
+        // only odd outputs q = 2 v' + 1 are read: FFT_P(c)(2v'+1) =
+        // FFT_{P/2}(d)(v'), d_j = (c_j - c_{j+P/2}) W^j; v[s] then holds
+        // output 2 (tid + 64 s) + 1 for s < 8
+        C u8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) u8[e] = csub(v[e], v[e + 8]);
+        twiddle_stride64(u8, B.tw[tid]);
+        fft_r8_512<P>(u8, lds, B.tw, tid);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = u8[e];
+    } else {
+        fft_r16<P>(v, lds, B.tw, tid);
+    }
     // v[s] = conj(c[q]), q = tid + T*s: output k = k0 + q for q < Kout.
     // Post-chirp factors: loaded 8 at a time (clamped indices), so that a
     // half line's loads are in flight together without doubling the
     // registers; a half past the outputs is skipped (with Kout <= P/2, the
     // usual case, one half and one round trip).
     if constexpr (IO::kStore == IO_DIRECT) {
+        static_assert(!kOO, "odd-output path stores through LDS");
         if (line < nlines) {
             const auto c = io.at(line);
 #pragma unroll
@@ -541,21 +676,37 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
         // Kout <= P/2 complex fit in the line viewed as complex.
         C *buf = reinterpret_cast<C *>(lds);
         line_sync<P>();
+        if constexpr (kOO) {  // odd positions q = 2 (tid + 64 e) + 1 only
+            C pq[4];
 #pragma unroll
-        for (int h8 = 0; h8 < 16; h8 += 8) {
-            if (T * h8 >= B.Kout) break;  // uniform
-            C pq[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int q = tid + T * (h8 + e);
+            for (int e = 0; e < 4; ++e) {
+                const int q = 2 * (tid + T * e) + 1;
                 pq[e] = B.post[q < B.Kout ? q : B.Kout - 1];
             }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) materialize(pq[e]);
+            for (int e = 0; e < 4; ++e) materialize(pq[e]);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int q = tid + T * (h8 + e);
-                if (q < B.Kout) buf[q] = cmul(cconj(v[h8 + e]), pq[e]);
+            for (int e = 0; e < 4; ++e) {
+                const int q = 2 * (tid + T * e) + 1;
+                if (q < B.Kout) buf[q] = cmul(cconj(v[e]), pq[e]);
+            }
+        } else {
+#pragma unroll
+            for (int h8 = 0; h8 < 16; h8 += 8) {
+                if (T * h8 >= B.Kout) break;  // uniform
+                C pq[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int q = tid + T * (h8 + e);
+                    pq[e] = B.post[q < B.Kout ? q : B.Kout - 1];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) materialize(pq[e]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int q = tid + T * (h8 + e);
+                    if (q < B.Kout) buf[q] = cmul(cconj(v[h8 + e]), pq[e]);
+                }
             }
         }
         __syncthreads();
@@ -814,6 +965,19 @@ struct FwdGammaPackIO {
         c.d1[n / 2] = C{s.x * (real_t<C>)0.5, s.y * (real_t<C>)0.5};
         if (c.two) c.d2[n / 2] = C{d.y * (real_t<C>)0.5, d.x * (real_t<C>)-0.5};
     }
+};
+
+// The two packed gamma stages at an even band-limit L with P = 1024: the
+// analysis window (n = t - (L-1)) holds non-zero coefficients (even n) only
+// at odd t, and the synthesis reads only the outputs of even n, at odd
+// positions q = n + L - 1; each then runs one of its two FFTs at half length.
+template <class C_, class G>
+struct InvGammaPackOddIO : InvGammaPackIO<C_, G> {
+    static constexpr bool kOddIn = true;
+};
+template <class C_, class G>
+struct FwdGammaPackOddIO : FwdGammaPackIO<C_, G> {
+    static constexpr bool kOddOut = true;
 };
 
 // alpha DFT of the synthesis: line (b, k), k = n/2 >= 0, all m in (-L, L).
@@ -1333,6 +1497,10 @@ template <class C, class G>
 static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2, G *grid,
                               hipStream_t st) {
     const int nreal = g.Nm * g.L;
+    if (B.P == 1024 && (g.L & 1) == 0) {
+        InvGammaPackOddIO<C, G> io{{W2, grid, g.L, g.h, g.Nm, nreal}};
+        return launch_r16<1024>(io, (nreal + 1) / 2, B, st);
+    }
     if (B.P >= 256) {
         InvGammaPackIO<C, G> io{W2, grid, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
@@ -1344,6 +1512,10 @@ template <class C, class G>
 static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const G *grid, C *V1,
                               hipStream_t st) {
     const int nreal = g.Nm * g.L;
+    if (B.P == 1024 && (g.L & 1) == 0) {
+        FwdGammaPackOddIO<C, G> io{{grid, V1, g.L, g.h, g.Nm, nreal}};
+        return launch_r16<1024>(io, (nreal + 1) / 2, B, st);
+    }
     if (B.P >= 256) {
         FwdGammaPackIO<C, G> io{grid, V1, g.L, g.h, g.Nm, nreal};
         return run_bluestein_r16(io, (nreal + 1) / 2, B, st);
