@@ -404,7 +404,7 @@ def serving_leg(n=128, rho=0.7, bandlimits=(64, 128, 256, 512), slots=4):
         srv = serving.CurveletServer(L_max=max(bandlimits), slots=nslots, max_batch=mb)
         try:
             srv.prepare(bandlimits)
-            cap = serving.measure_capacity(srv, Ls_cap, n=32 if nslots == 1 else 64)
+            cap = serving.measure_capacity(srv, Ls_cap, n=64)  # the same 64 requests for both
             res[name] = {"capacity_req_per_s": cap, "slots": nslots, "max_batch": mb}
             if name == "served":
                 rate = rho * cap

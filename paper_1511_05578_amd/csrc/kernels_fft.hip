@@ -484,9 +484,22 @@ __device__ __forceinline__ void fft_r8_512(C v[8], real_t<C> *lds, const C *__re
 }
 
 // Three waves per SIMD for lines that fit one wavefront (the kernel is latency
-// bound; the register cap costs at most a few spilled dwords).
+// bound; the register cap costs at most a few spilled dwords); four for an IO
+// policy that declares `kFourWaves` (its instance fits 128 registers without
+// spills, and it reads the chirp spectrum from global memory so that four
+// work-groups fit a CU's LDS).
+template <class T, class = void>
+struct FourWaves : std::false_type {};
+template <class T>
+struct FourWaves<T, std::void_t<decltype(T::kFourWaves)>>
+    : std::integral_constant<bool, T::kFourWaves> {};
 template <int P, class IO>
-__global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
+struct WavesFor {
+    static constexpr int v = P <= 1024 ? (FourWaves<IO>::value ? 4 : 3) : 2;
+};
+
+template <int P, class IO>
+__global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
     IO io, int nlines, BlueT<typename IO::C> B) {
     using C = typename IO::C;
     using R = real_t<C>;
@@ -505,7 +518,7 @@ __global__ __launch_bounds__(R16<P>::WG, (P <= 1024 ? 3 : 2)) void k_blue_r16(
     // The chirp spectrum is read by every line between the two FFTs: one copy
     // in LDS per work-group instead of a cache-missing global read per line.
     // (Up to P = 2048; at P = 4096 the copy would cost occupancy.)
-    constexpr bool kVhLds = P <= 2048;
+    constexpr bool kVhLds = P <= 2048 && !FourWaves<IO>::value;
     const C *vh = B.vhat;
     if constexpr (kVhLds) {
         C *v2 = reinterpret_cast<C *>(smem_d + LINES * LW);
@@ -742,7 +755,7 @@ static hipError_t launch_r16(const IO &io, int nlines, const BlueT<typename IO::
                              hipStream_t st) {
     using G = R16<P>;
     const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>) +
-                       (P <= 2048 ? (size_t)P * sizeof(typename IO::C) : 0);
+                       (P <= 2048 && !FourWaves<IO>::value ? (size_t)P * sizeof(typename IO::C) : 0);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -978,6 +991,7 @@ struct InvGammaPackOddIO : InvGammaPackIO<C_, G> {
 template <class C_, class G>
 struct FwdGammaPackOddIO : FwdGammaPackIO<C_, G> {
     static constexpr bool kOddOut = true;
+    static constexpr bool kFourWaves = true;
 };
 
 // alpha DFT of the synthesis: line (b, k), k = n/2 >= 0, all m in (-L, L).
