@@ -79,3 +79,36 @@ def test_unrotated_server_alone_equals_in_mix():
             assert err < 1e-10
     finally:
         srv.close()
+
+
+def test_alone_equals_in_mix_configured_bandlimits():
+    # The configured mix {64, 128, 256, 512}, including two L = 512 requests
+    # and a batched pair of L = 128: every result (map, scaling map and every
+    # grid) bitwise the one-call result.
+    Ls = [512, 128, 64, 128, 256, 512, 64, 256]
+    arrivals = np.cumsum([0.0, 1e-4, 0, 0, 2e-3, 0, 1e-3, 0])
+    srv = serving.CurveletServer(L_max=512, slots=4, max_batch=4, keep_grids=True)
+    try:
+        srv.prepare(set(Ls))
+        reqs = serving.make_requests(srv, len(Ls), Ls, arrivals, seed_base=500)
+        done = srv.run(reqs)
+        assert len(done) == len(Ls)
+        ctx = srv.ctx
+        for r in sorted(done, key=lambda r: r.rid):
+            print("request %d L=%d admitted %.1f ms after arrival, latency %.1f ms"
+                  % (r.rid, r.L, 1e3 * (r.admitted - r.arrival), 1e3 * (r.done - r.arrival)),
+                  flush=True)
+            scal, grids = ctx.curvelet_analysis(r.fmap)
+            rec = ctx.curvelet_synthesis(scal, grids, r.L)
+            torch.cuda.synchronize()
+            assert torch.equal(rec, r.out), r.rid
+            assert torch.equal(scal, r.scal)
+            for a, b in zip(grids, r.grids):
+                assert torch.equal(a, b)
+            err = (torch.linalg.norm(rec - r.fmap) / torch.linalg.norm(r.fmap)).item()
+            assert err < 1e-10
+            del scal, grids, rec
+            r.grids = None
+            torch.cuda.empty_cache()
+    finally:
+        srv.close()
