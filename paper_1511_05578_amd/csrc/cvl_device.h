@@ -83,6 +83,18 @@ __device__ __forceinline__ int xcd_group_runs(int b, int n, int G) {
 __host__ __device__ __forceinline__ int64_t delta_off(int l) {
     return (int64_t)l * (l + 1) * (2 * l + 1) / 6;
 }
+// The same offset in 32-bit arithmetic, exact for l <= 2048 (the table of
+// L = 2048 has 2.86e9 < 2^32 entries): l (l + 1) / 2 is exact, its product with
+// 2l + 1 is a multiple of 3, and a multiple of 3 below 2^32 divided by 3 is its
+// product with the inverse of 3 modulo 2^32.  Row m' of block l starts at
+// delta_off32(l) + m' (l + 1), also below 2^32.
+__host__ __device__ __forceinline__ uint32_t delta_off32(int l) {
+    const uint32_t t = (uint32_t)l * (uint32_t)(l + 1) / 2u;
+    return t * (uint32_t)(2 * l + 1) * 0xAAAAAAABu;
+}
+__host__ __device__ __forceinline__ uint32_t delta_row32(int l, int mp) {
+    return delta_off32(l) + (uint32_t)mp * (uint32_t)(l + 1);
+}
 
 // Device tables of one Bluestein DFT configuration (see host::Bluestein), in
 // the working precision of the transform.

@@ -323,7 +323,9 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
     const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nkt * nmt);
     const int mp = lg / (nkt * nmt);
     const int m0 = ((lg / nkt) % nmt) * 64, k0 = (lg % nkt) * 32;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // w is the same across a wave: readfirstlane lets the compiler keep it,
+    // the l of each staged row and that row's offsets in scalar registers.
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int p = w & 1, c = w >> 1;
     const int li = lane & 15, lq = lane >> 4;
     cvl_d4 acc[4][2];
@@ -337,28 +339,43 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
     if (2 * k0 > lstart) lstart = 2 * k0;
     const int lend = g.lhi;
     // The next chunk's raw operands, prefetched while the current one is
-    // multiplied: A element q: mm = idx & 63, i = (idx >> 6) & 15, pp = idx >> 10;
-    // B element q: kk = idx & 31, i = (idx >> 5) & 15, pp = idx >> 9.
+    // multiplied.  A element q of a thread: parity pp = q >> 2, i = w + 4 (q & 3),
+    // mm = lane, so l = lb + pp + 2 i is uniform over the wave.  B element q:
+    // parity = lane >> 5, i = w + 4 q, kk = lane & 31 (two l per wave, both
+    // offsets scalar).  Loads out of range read element 0 and are replaced by 0.
     double ra[8], rb2[4], rp[4];
     cd rf[8];
     auto fetch = [&](int lb) {
+        const int m = m0 + lane;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int idx = tid + 256 * q;
-            const int mm = idx & 63, i = (idx >> 6) & 15, pp = idx >> 10;
-            const int l = lb + pp + 2 * i, m = m0 + mm;
-            const bool ok = l >= lstart && l <= lend && m <= l && m < L;
-            ra[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + m] : 0.0;
-            rf[q] = ok ? fpad[(size_t)l * Lf + m] : cd{0.0, 0.0};
+            const int l = lb + (q >> 2) + 2 * (w + 4 * (q & 3));
+            const bool lok = l >= lstart && l <= lend;
+            const bool ok = lok && m <= l && m < L;
+            const uint32_t dro = lok ? delta_off32(l) + (uint32_t)(mp * (l + 1)) : 0u;
+            const uint32_t fro = lok ? (uint32_t)(l * Lf) : 0u;
+            const uint32_t mi = ok ? (uint32_t)m : 0u;
+            const double dv = delta[(size_t)(dro + mi)];
+            const cd fv = fpad[(size_t)(fro + mi)];
+            ra[q] = ok ? dv : 0.0;
+            rf[q] = ok ? fv : cd{0.0, 0.0};
         }
+        const int hi = lane >> 5, k = k0 + (lane & 31);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int idx = tid + 256 * q;
-            const int kk = idx & 31, i = (idx >> 5) & 15, pp = idx >> 9;
-            const int l = lb + pp + 2 * i, k = k0 + kk;
-            const bool ok = l >= lstart && l <= lend && k <= h && 2 * k <= l;
-            rb2[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] : 0.0;
-            rp[q] = ok ? psi[(size_t)l * (h + 1) + k] : 0.0;
+            const int la = lb + 2 * (w + 4 * q);
+            const bool ok0 = la >= lstart && la <= lend, ok1 = la + 1 >= lstart && la + 1 <= lend;
+            const uint32_t d0 = ok0 ? delta_off32(la) + (uint32_t)(mp * (la + 1)) : 0u;
+            const uint32_t d1 = ok1 ? delta_off32(la + 1) + (uint32_t)(mp * (la + 2)) : 0u;
+            const uint32_t p0 = ok0 ? (uint32_t)(la * (h + 1)) : 0u;
+            const uint32_t p1 = ok1 ? (uint32_t)((la + 1) * (h + 1)) : 0u;
+            const int l = la + hi;
+            const bool ok = (hi ? ok1 : ok0) && k <= h && 2 * k <= l;
+            const uint32_t ki = ok ? (uint32_t)k : 0u;
+            const double dv = delta[(size_t)((hi ? d1 : d0) + 2u * ki)];
+            const double pv = psi[(size_t)((hi ? p1 : p0) + ki)];
+            rb2[q] = ok ? dv : 0.0;
+            rp[q] = ok ? pv : 0.0;
         }
     };
     const int lb0 = lstart & ~1;
@@ -367,17 +384,12 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
         // A: 2 parities x 16 l x 64 m complex; B: 2 parities x 16 l x 32 k
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int idx = tid + 256 * q;
-            const int mm = idx & 63, i = (idx >> 6) & 15, pp = idx >> 10;
-            As[pp][0][i][mm] = ra[q] * rf[q].x;
-            As[pp][1][i][mm] = ra[q] * rf[q].y;
+            const int i = w + 4 * (q & 3), pp = q >> 2;
+            As[pp][0][i][lane] = ra[q] * rf[q].x;
+            As[pp][1][i][lane] = ra[q] * rf[q].y;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int idx = tid + 256 * q;
-            const int kk = idx & 31, i = (idx >> 5) & 15, pp = idx >> 9;
-            Bs[pp][i][kk] = rb2[q] * rp[q];
-        }
+        for (int q = 0; q < 4; ++q) Bs[lane >> 5][w + 4 * q][lane & 31] = rb2[q] * rp[q];
         __syncthreads();
         if (lb + 32 <= lend) fetch(lb + 32);
 #pragma unroll
@@ -555,6 +567,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
     //   Z:    kk = idx & 15, mm = idx >> 4
     double rd[4], rp[4];
     cd rzp[4], rzn[4];
+    const cd *zt = Z + ((size_t)mp * L + m0) * Nep;  // cube row (m', m0)
     auto fetch = [&](int kb) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -562,8 +575,8 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
             const int kk = idx & 15, i = (idx >> 4) & 31, par = idx >> 9;
             const int l = l0 + par + 2 * i, k = kb + kk;
             const bool ok = k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l;
-            rd[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] : 0.0;
-            rp[q] = ok ? psi[(size_t)l * (h + 1) + k] : 0.0;
+            rd[q] = ok ? delta[(size_t)(delta_row32(l, mp) + (uint32_t)(2 * k))] : 0.0;
+            rp[q] = ok ? psi[(size_t)(uint32_t)(l * (h + 1) + k)] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -571,7 +584,8 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
             const int kk = idx & 15, mm = idx >> 4;
             const int k = kb + kk, m = m0 + mm;
             const bool ok = k <= kmax && m < L;
-            const cd *row = Z + ((size_t)mp * L + (ok ? m : 0)) * Nep;
+            // 32-bit offsets inside the tile's rows (64 rows of Nep <= 1024)
+            const cd *row = zt + (uint32_t)((ok ? mm : 0) * Nep);
             rzp[q] = ok ? row[h + k] : cd{0.0, 0.0};
             rzn[q] = (ok && k > 0) ? row[h - k] : cd{0.0, 0.0};
         }
@@ -636,13 +650,13 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
         for (int r = 0; r < 4; ++r) {
             const int l = l0 + wp + 2 * (16 * lf + 4 * r + lq);
             if (l > g.lhi) continue;
-            const double *drow = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *drow = delta + delta_row32(l, mp);
 #pragma unroll
             for (int mj = 0; mj < 2; ++mj) {
                 const int m = m0 + 32 * wm + 16 * mj + li;
                 if (m >= L) continue;
                 const double d = (mp <= l && m <= l) ? drow[m] : 0.0;
-                part[((size_t)mp * L + l) * L + m] =
+                part[(size_t)mp * L * L + (uint32_t)(l * L + m)] =
                     cd{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
             }
         }
@@ -703,7 +717,7 @@ __global__ __launch_bounds__(256) void k_unrot_contract_inv(ScaleGeom g, int Lf,
         double d0 = 0.0, d1 = 0.0;
         cd f0 = cd{0.0, 0.0}, f1 = cd{0.0, 0.0};
         if (on && m0 <= l) {
-            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *row = delta + delta_row32(l, mp);
             d0 = row[m0];
             f0 = fpad[(size_t)l * Lf + m0];
             if (m0 + 1 <= l) {
@@ -787,7 +801,7 @@ __global__ __launch_bounds__(256) void k_unrot_contract_fwd(ScaleGeom g, int Lf,
         const size_t plane = (size_t)2 * L * g.Nep;
         const C *yp = Y + unrot_off(g, m, l);
         const C *ym = Y + unrot_off(g, m, -l);
-        const double *dm = delta + delta_off(l) + m;  // Delta^l_{m'm} at dm[m' (l + 1)]
+        const double *dm = delta + (size_t)(delta_off32(l) + (uint32_t)m);  // Delta^l_{m'm} at dm[m' (l + 1)]
         const double *pl = pd + l;                    // pd[m'][l] at pl[m' L]
         const double both = l > 0 ? 1.0 : 0.0;
         int mp = w;
@@ -869,7 +883,7 @@ __global__ void k_gen_contract_inv(int L, int N, int Nnp, const double *__restri
     if (mp > l0) l0 = mp;
     cd s = cd{0.0, 0.0};
     for (int l = l0; l < L; ++l) {
-        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        const double *row = delta + delta_row32(l, mp);
         double w = row[am] * row[an] * (2.0 * l + 1.0) * (1.0 / (8.0 * M_PI * M_PI));
         const int flip = ((m < 0) + (n < 0)) * ((l + mp) & 1);
         if (flip & 1) w = -w;
@@ -896,7 +910,7 @@ __global__ void k_gen_contract_fwd(int L, int N, int Nnp, const double *__restri
     }
     cd s = cd{0.0, 0.0};
     for (int mp = 0; mp <= l; ++mp) {
-        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        const double *row = delta + delta_row32(l, mp);
         double w = row[am] * row[an];
         const int flip = ((m < 0) + (n < 0)) * ((l + mp) & 1);
         if (flip & 1) w = -w;
@@ -938,7 +952,7 @@ __global__ void k_spin_contract_inv(int L, int Nnp, int llo, int lhi,
     const int l1 = lhi < L - 1 ? lhi : L - 1;
     cd s = cd{0.0, 0.0};
     for (int l = l0; l <= l1; ++l) {
-        const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+        const double *row = delta + delta_row32(l, mp);
         double w = row[am] * row[an] * psi[(size_t)l * Nm + ni];
         const int flip = ((m < 0) + (n < 0)) * ((l + mp) & 1);
         if (flip & 1) w = -w;
@@ -1023,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_sht_inv_delta(int L, int Lf,
         int l0 = m > mp ? m : mp;
         if ((l0 + mp) & 1) ++l0;
         for (int l = l0 + 2 * w; l < L; l += 8) {
-            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *row = delta + delta_row32(l, mp);
             const double c = sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * row[m] * row[0];
             const cd f = fpad[(size_t)l * Lf + m];
             sx += c * f.x;
@@ -1053,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_sht_fwd_delta(int L, int Lf,
     double sx = 0.0, sy = 0.0;
     if (m <= l) {
         for (int mp = (l & 1) + 2 * w; mp <= l; mp += 8) {
-            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *row = delta + delta_row32(l, mp);
             const double c = row[m] * row[0];
             const cd z = Z[(size_t)mp * L + m];
             sx += c * z.x;
@@ -1123,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_sht_inv_delta_spin(int L, int s,
         int l0 = am > mp ? am : mp;
         if (as > l0) l0 = as;
         for (int l = l0 + w; l < L; l += 4) {
-            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *row = delta + delta_row32(l, mp);
             const double v = sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * row[am] * row[as] *
                              spin_sign(l, mp, m, s);
             const cd f = flm[(size_t)l * l + l + m];
@@ -1159,7 +1173,7 @@ __global__ __launch_bounds__(256) void k_sht_fwd_delta_spin(int L, int s,
     double sx = 0.0, sy = 0.0;
     if (live) {
         for (int mp = w; mp <= l; mp += 4) {
-            const double *row = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *row = delta + delta_row32(l, mp);
             const double v = row[am] * row[as] * spin_sign(l, mp, m, s);
             const cd z = Z[(size_t)mp * Nm + m + L - 1];
             sx += v * z.x;

@@ -322,7 +322,12 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
     if (m0 > lstart) lstart = m0;
     if (2 * k0 > lstart) lstart = 2 * k0;
     const int lend = g.lhi;
-    for (int lb = lstart & ~1; lb <= lend; lb += 64) {
+    // l chunks from the top down, at boundaries common to the whole launch:
+    // the tiles of one m tile (and of one k tile) then read the same Delta
+    // rows at about the same time, while the L2 still holds them (tiles
+    // differ only in where they stop, at their lstart).
+    const int ltop = (lend + 2) & ~1;  // even, past lend
+    for (int lb = ltop - 64; lb + 63 >= lstart; lb -= 64) {
         // A: 2 parities x 32 l x 64 m complex, 16 per thread (m fastest)
 #pragma unroll 4
         for (int q = 0; q < 16; ++q) {
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
             const int l = lb + pp + 2 * i, m = m0 + mm;
             float re = 0.f, im = 0.f;
             if (l >= lstart && l <= lend && m <= l && m < L) {
-                const double d = delta[delta_off(l) + (int64_t)mp * (l + 1) + m];
+                const double d = delta[(size_t)(delta_row32(l, mp) + (uint32_t)(m))];
                 const cd f = fpad[(size_t)l * Lf + m];
                 re = (float)(d * f.x);
                 im = (float)(d * f.y);
@@ -347,7 +352,7 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
             const int l = lb + pp + 2 * i, k = k0 + kk;
             float v = 0.f;
             if (l >= lstart && l <= lend && k <= h && 2 * k <= l)
-                v = (float)(delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] *
+                v = (float)(delta[(size_t)(delta_row32(l, mp) + (uint32_t)(2 * k))] *
                             psi[(size_t)l * (h + 1) + k]);
             Bs[pp][i][kk] = v;
         }
@@ -460,6 +465,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
     //   Z:    kk = idx & 31, mm = idx >> 5
     double rd[8], rp[8];
     cf rzp[8], rzn[8];
+    const cf *zt = Z + ((size_t)mp * L + m0) * Nep;  // cube row (m', m0)
     auto fetch = [&](int kb) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -467,8 +473,8 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
             const int kk = idx & 31, i = (idx >> 5) & 31, par = idx >> 10;
             const int l = l0 + par + 2 * i, k = kb + kk;
             const bool ok = k <= kmax && l <= g.lhi && 2 * k <= l && mp <= l;
-            rd[q] = ok ? delta[delta_off(l) + (int64_t)mp * (l + 1) + 2 * k] : 0.0;
-            rp[q] = ok ? psi[(size_t)l * (h + 1) + k] : 0.0;
+            rd[q] = ok ? delta[(size_t)(delta_row32(l, mp) + (uint32_t)(2 * k))] : 0.0;
+            rp[q] = ok ? psi[(size_t)(uint32_t)(l * (h + 1) + k)] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -476,7 +482,8 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
             const int kk = idx & 31, mm = idx >> 5;
             const int k = kb + kk, m = m0 + mm;
             const bool ok = k <= kmax && m < L;
-            const cf *row = Z + ((size_t)mp * L + (ok ? m : 0)) * Nep;
+            // 32-bit offsets inside the tile's rows (64 rows of Nep <= 1024)
+            const cf *row = zt + (uint32_t)((ok ? mm : 0) * Nep);
             rzp[q] = ok ? row[h + k] : cf{0.f, 0.f};
             rzn[q] = (ok && k > 0) ? row[h - k] : cf{0.f, 0.f};
         }
@@ -540,13 +547,13 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
         for (int r = 0; r < 4; ++r) {
             const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
             if (l > g.lhi) continue;
-            const double *drow = delta + delta_off(l) + (int64_t)mp * (l + 1);
+            const double *drow = delta + delta_row32(l, mp);
 #pragma unroll
             for (int mj = 0; mj < 2; ++mj) {
                 const int m = m0 + 32 * wm + 16 * mj + li;
                 if (m >= L) continue;
                 const float d = (mp <= l && m <= l) ? (float)drow[m] : 0.f;
-                part[((size_t)mp * L + l) * L + m] =
+                part[(size_t)mp * L * L + (uint32_t)(l * L + m)] =
                     cf{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
             }
         }
