@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
 // m, so one parity per tile).  Tile 128 rows x 64 real columns x 16 k; wave w
 // owns rows [32w, 32w+32) as 2 x 4 blocks of v_mfma_f64_16x16x4f64, whose lane
 // layout is A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16].  The factor i of
-// odd parity is applied while staging B: (re, im) -> (-im, re).  The next K
+// odd parity is applied to the result: (re, im) -> (-im, re).  The next K
 // tile is loaded into registers while the current one is multiplied.
 // uL > 0: the synthesis cube of the unrotated curvelets at band-limit uL,
 // whose outputs are read only at m' <= l and m <= l (l = |n|); a tile with
@@ -200,18 +200,32 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, i
         for (int j = 0; j < 4; ++j) acc[i][j] = cvl_d4{0.0, 0.0, 0.0, 0.0};
     const int lr = lane & 15, lk = lane >> 4;
     // Next K tile held in registers while the current one is multiplied.
+    // A whole tile (the usual case) loads without guards, so no load result
+    // is consumed (and waited for) before the next iteration stores it.
     double ra[8];
     double2 rb[2];
     const int kkb = tid >> 4, ccb = (tid & 15) * 4;  // 4 doubles = 2 complex
+    const double *Arow = A + (size_t)r0 * K;
+    const size_t col = 2 * (size_t)c0 + ccb;
     auto fetch = [&](int k0) {
+        const int k = k0 + kkb;
+        if (r0 + 128 <= M && k0 + 16 <= K && 2 * (size_t)c0 + 64 <= ld) {  // uniform
+            // element q: row (tid >> 4) + 16 q, column k0 + (tid & 15)
+            const double *pa = Arow + (uint32_t)((tid >> 4) * K + (tid & 15) + k0);
+            const uint32_t step = 16u * (uint32_t)K;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ra[q] = pa[q * step];
+            const double2 *src = reinterpret_cast<const double2 *>(in + (size_t)k * ld + col);
+            rb[0] = src[0];
+            rb[1] = src[1];
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int idx = tid + 256 * q;
-            const int r = r0 + (idx >> 4), k = k0 + (idx & 15);
-            ra[q] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.0;
+            const int r = idx >> 4, kq = k0 + (idx & 15);
+            ra[q] = (r0 + r < M && kq < K) ? Arow[(uint32_t)(r * K + kq)] : 0.0;
         }
-        const int k = k0 + kkb;
-        const size_t col = 2 * (size_t)c0 + ccb;
         rb[0] = make_double2(0.0, 0.0);
         rb[1] = make_double2(0.0, 0.0);
         if (k < K && col + 3 < ld) {
@@ -227,17 +241,8 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, i
             const int idx = tid + 256 * q;
             As[idx >> 4][idx & 15] = ra[q];
         }
-        if (par) {
-            Bs[kkb][ccb] = -rb[0].y;
-            Bs[kkb][ccb + 1] = rb[0].x;
-            Bs[kkb][ccb + 2] = -rb[1].y;
-            Bs[kkb][ccb + 3] = rb[1].x;
-        } else {
-            Bs[kkb][ccb] = rb[0].x;
-            Bs[kkb][ccb + 1] = rb[0].y;
-            Bs[kkb][ccb + 2] = rb[1].x;
-            Bs[kkb][ccb + 3] = rb[1].y;
-        }
+        *reinterpret_cast<double2 *>(&Bs[kkb][ccb]) = rb[0];
+        *reinterpret_cast<double2 *>(&Bs[kkb][ccb + 2]) = rb[1];
         __syncthreads();
         if (k0 + 16 < K) fetch(k0 + 16);
 #pragma unroll
@@ -253,6 +258,18 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, i
             }
         }
         __syncthreads();
+    }
+    // Odd parity: the factor i on the input columns, (re, im) -> (-im, re),
+    // applied to the result instead (the GEMM is linear in its columns).
+    // Column 16 j + lr: re at even lr, im at odd lr; the partner is lane ^ 1.
+    if (par) {
+        const double sg = (lr & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = sg * __shfl_xor(acc[i][j][r], 1);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -342,11 +359,15 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
     // multiplied.  A element q of a thread: parity pp = q >> 2, i = w + 4 (q & 3),
     // mm = lane, so l = lb + pp + 2 i is uniform over the wave.  B element q:
     // parity = lane >> 5, i = w + 4 q, kk = lane & 31 (two l per wave, both
-    // offsets scalar).  Loads out of range read element 0 and are replaced by 0.
+    // offsets scalar).  Loads out of range read element 0; their bit in `okm`
+    // is clear and the value is replaced by 0 only when the next iteration
+    // stores it, so that no load is waited for before the multiply.
     double ra[8], rb2[4], rp[4];
     cd rf[8];
+    uint32_t okm = 0;
     auto fetch = [&](int lb) {
         const int m = m0 + lane;
+        okm = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int l = lb + (q >> 2) + 2 * (w + 4 * (q & 3));
@@ -355,10 +376,9 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
             const uint32_t dro = lok ? delta_off32(l) + (uint32_t)(mp * (l + 1)) : 0u;
             const uint32_t fro = lok ? (uint32_t)(l * Lf) : 0u;
             const uint32_t mi = ok ? (uint32_t)m : 0u;
-            const double dv = delta[(size_t)(dro + mi)];
-            const cd fv = fpad[(size_t)(fro + mi)];
-            ra[q] = ok ? dv : 0.0;
-            rf[q] = ok ? fv : cd{0.0, 0.0};
+            ra[q] = delta[(size_t)(dro + mi)];
+            rf[q] = fpad[(size_t)(fro + mi)];
+            okm |= ok ? 1u << q : 0u;
         }
         const int hi = lane >> 5, k = k0 + (lane & 31);
 #pragma unroll
@@ -372,10 +392,9 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
             const int l = la + hi;
             const bool ok = (hi ? ok1 : ok0) && k <= h && 2 * k <= l;
             const uint32_t ki = ok ? (uint32_t)k : 0u;
-            const double dv = delta[(size_t)((hi ? d1 : d0) + 2u * ki)];
-            const double pv = psi[(size_t)((hi ? p1 : p0) + ki)];
-            rb2[q] = ok ? dv : 0.0;
-            rp[q] = ok ? pv : 0.0;
+            rb2[q] = delta[(size_t)((hi ? d1 : d0) + 2u * ki)];
+            rp[q] = psi[(size_t)((hi ? p1 : p0) + ki)];
+            okm |= ok ? 1u << (8 + q) : 0u;
         }
     };
     const int lb0 = lstart & ~1;
@@ -385,11 +404,13 @@ __global__ __launch_bounds__(256, 2) void k_contract_inv_mfma(ScaleGeom g, int L
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int i = w + 4 * (q & 3), pp = q >> 2;
-            As[pp][0][i][lane] = ra[q] * rf[q].x;
-            As[pp][1][i][lane] = ra[q] * rf[q].y;
+            const bool ok = (okm >> q) & 1u;
+            As[pp][0][i][lane] = ok ? ra[q] * rf[q].x : 0.0;
+            As[pp][1][i][lane] = ok ? ra[q] * rf[q].y : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[lane >> 5][w + 4 * q][lane & 31] = rb2[q] * rp[q];
+        for (int q = 0; q < 4; ++q)
+            Bs[lane >> 5][w + 4 * q][lane & 31] = ((okm >> (8 + q)) & 1u) ? rb2[q] * rp[q] : 0.0;
         __syncthreads();
         if (lb + 32 <= lend) fetch(lb + 32);
 #pragma unroll

@@ -63,12 +63,66 @@ __device__ __forceinline__ f4v mma32(const Op<PREC_BF16X3> &a, const Op<PREC_BF1
     return acc;
 }
 
+// Operand loads of one K tile of the FP32 beta GEMMs (128 rows x 32 k of A,
+// 32 k x 64 real columns of the input) into registers.  A whole tile (the
+// usual case) loads without guards: no load result is consumed, and so
+// waited for, before the next iteration stores the registers to LDS.
+__device__ __forceinline__ void beta_fetch_f32(const float *__restrict__ A,
+                                               const float *__restrict__ in, int M, int K,
+                                               size_t ld, int r0, int c0, int k0, int tid,
+                                               float (&ra)[16], float4 (&rb)[2]) {
+    const float *Arow = A + (size_t)r0 * K;
+    if (r0 + 128 <= M && k0 + 32 <= K && 2 * (size_t)c0 + 64 <= ld) {  // uniform
+        // element q: row (tid >> 5) + 8 q, column k0 + (tid & 31)
+        const float *pa = Arow + (uint32_t)((tid >> 5) * K + (tid & 31) + k0);
+        const uint32_t step = 8u * (uint32_t)K;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) ra[q] = pa[q * step];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + 256 * q;
+            const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
+            rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)(k0 + (idx >> 4)) * ld + col);
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * q;
+        const int r = r0 + (idx >> 5), k = k0 + (idx & 31);
+        ra[q] = (r < M && k < K) ? Arow[(uint32_t)((idx >> 5) * K + k)] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int idx = tid + 256 * q;
+        const int k = k0 + (idx >> 4);
+        const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
+        rb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < K && col + 3 < ld) rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
+    }
+}
+
+// The factor i of the odd beta parity, (re, im) -> (-im, re), applied to the
+// result of the GEMM on the raw columns (it is linear in them): in the 16 x 16
+// MFMA output layout column li holds re at even li, im at odd li, and the
+// partner column sits in lane ^ 1.
+__device__ __forceinline__ void beta_odd_parity(f4v (&acc)[2][4], int li) {
+    const float sg = (li & 1) ? 1.f : -1.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = sg * __shfl_xor(acc[i][j][r], 1);
+}
+
 // ---------------------------------------------------------------------------
 // Parity-folded beta stage in FP32 (curvelet layout, Nep % 32 == 0):
 //   out[r][c] = (i^par(c)) sum_k A^{par(c)}[r][k] in[k][c].
 // Tile 128 rows x 64 real columns x 32 k; wave w owns rows [32w, 32w+32) as
 // 2 x 4 blocks of v_mfma_f32_16x16x4_f32.  The next K tile is loaded into
-// registers while the current one is multiplied.
+// registers while the current one is multiplied; the odd parity's factor i is
+// applied to the result.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, int Nep,
                                                        const float *__restrict__ Ae,
@@ -96,22 +150,7 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
     // Next K tile held in registers while the current one is multiplied.
     float ra[16];
     float4 rb[2];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int idx = tid + 256 * q;
-            const int r = r0 + (idx >> 5), k = k0 + (idx & 31);
-            ra[q] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + 256 * q;
-            const int k = k0 + (idx >> 4);
-            const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
-            rb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < K && col + 3 < ld) rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
-        }
-    };
+    auto fetch = [&](int k0) { beta_fetch_f32(A, in, M, K, ld, r0, c0, k0, tid, ra, rb); };
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += 32) {
 #pragma unroll
@@ -123,18 +162,10 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
         for (int q = 0; q < 2; ++q) {
             const int idx = tid + 256 * q;
             const int kk = idx >> 4, cc = (idx & 15) * 4;
-            const float4 x = rb[q];
-            if (par) {
-                Bs[kk][cc] = -x.y;
-                Bs[kk][cc + 1] = x.x;
-                Bs[kk][cc + 2] = -x.w;
-                Bs[kk][cc + 3] = x.z;
-            } else {
-                Bs[kk][cc] = x.x;
-                Bs[kk][cc + 1] = x.y;
-                Bs[kk][cc + 2] = x.z;
-                Bs[kk][cc + 3] = x.w;
-            }
+            Bs[kk][cc] = rb[q].x;
+            Bs[kk][cc + 1] = rb[q].y;
+            Bs[kk][cc + 2] = rb[q].z;
+            Bs[kk][cc + 3] = rb[q].w;
         }
         __syncthreads();
         if (k0 + 32 < K) fetch(k0 + 32);
@@ -152,6 +183,7 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
         }
         __syncthreads();
     }
+    if (par) beta_odd_parity(acc, li);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -192,22 +224,7 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma_bf16x3(int M, int K, int n
     const int li = lane & 15, lq = lane >> 4;
     float ra[16];
     float4 rb[2];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int idx = tid + 256 * q;
-            const int r = r0 + (idx >> 5), k = k0 + (idx & 31);
-            ra[q] = (r < M && k < K) ? A[(size_t)r * K + k] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + 256 * q;
-            const int k = k0 + (idx >> 4);
-            const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
-            rb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < K && col + 3 < ld) rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
-        }
-    };
+    auto fetch = [&](int k0) { beta_fetch_f32(A, in, M, K, ld, r0, c0, k0, tid, ra, rb); };
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += 32) {
 #pragma unroll
@@ -219,18 +236,10 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma_bf16x3(int M, int K, int n
         for (int q = 0; q < 2; ++q) {
             const int idx = tid + 256 * q;
             const int kk = idx >> 4, cc = (idx & 15) * 4;
-            const float4 x = rb[q];
-            if (par) {
-                Bs[kk][cc] = -x.y;
-                Bs[kk][cc + 1] = x.x;
-                Bs[kk][cc + 2] = -x.w;
-                Bs[kk][cc + 3] = x.z;
-            } else {
-                Bs[kk][cc] = x.x;
-                Bs[kk][cc + 1] = x.y;
-                Bs[kk][cc + 2] = x.z;
-                Bs[kk][cc + 3] = x.w;
-            }
+            Bs[kk][cc] = rb[q].x;
+            Bs[kk][cc + 1] = rb[q].y;
+            Bs[kk][cc + 2] = rb[q].z;
+            Bs[kk][cc + 3] = rb[q].w;
         }
         __syncthreads();
         if (k0 + 32 < K) fetch(k0 + 32);
@@ -254,6 +263,7 @@ __global__ __launch_bounds__(256, 3) void k_beta_mfma_bf16x3(int M, int K, int n
         }
         __syncthreads();
     }
+    if (par) beta_odd_parity(acc, li);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -309,7 +319,9 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
     const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nkt * nmt);
     const int mp = lg / (nkt * nmt);
     const int m0 = ((lg / nkt) % nmt) * 64, k0 = (lg % nkt) * 32;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // w is the same across a wave: readfirstlane lets the compiler keep it,
+    // the l of each staged row and that row's offsets in scalar registers.
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int p = w & 1, c = w >> 1;
     const int li = lane & 15, lq = lane >> 4;
     f4v acc[4][2];
@@ -327,34 +339,64 @@ __global__ __launch_bounds__(256) void k_contract_inv_mx(ScaleGeom g, int Lf,
     // rows at about the same time, while the L2 still holds them (tiles
     // differ only in where they stop, at their lstart).
     const int ltop = (lend + 2) & ~1;  // even, past lend
+    const int m = m0 + lane, hi = lane >> 5, k = k0 + (lane & 31);
     for (int lb = ltop - 64; lb + 63 >= lstart; lb -= 64) {
-        // A: 2 parities x 32 l x 64 m complex, 16 per thread (m fastest)
-#pragma unroll 4
-        for (int q = 0; q < 16; ++q) {
-            const int idx = tid + 256 * q;
-            const int mm = idx & 63, i = (idx >> 6) & 31, pp = idx >> 11;
-            const int l = lb + pp + 2 * i, m = m0 + mm;
-            float re = 0.f, im = 0.f;
-            if (l >= lstart && l <= lend && m <= l && m < L) {
-                const double d = delta[(size_t)(delta_row32(l, mp) + (uint32_t)(m))];
-                const cd f = fpad[(size_t)l * Lf + m];
-                re = (float)(d * f.x);
-                im = (float)(d * f.y);
-            }
-            As[pp][0][i][mm] = re;
-            As[pp][1][i][mm] = im;
-        }
-        // B: 2 parities x 32 l x 32 k, 8 per thread (k fastest)
+        // A: 2 parities x 32 l x 64 m complex, 16 per thread in two batches
+        // of 8 loads in flight.  Element q: parity q >> 3, i = w + 4 (q & 7),
+        // mm = lane (l uniform over the wave).  Loads out of range read
+        // element 0 and are replaced by 0.
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int idx = tid + 256 * q;
-            const int kk = idx & 31, i = (idx >> 5) & 31, pp = idx >> 10;
-            const int l = lb + pp + 2 * i, k = k0 + kk;
-            float v = 0.f;
-            if (l >= lstart && l <= lend && k <= h && 2 * k <= l)
-                v = (float)(delta[(size_t)(delta_row32(l, mp) + (uint32_t)(2 * k))] *
-                            psi[(size_t)l * (h + 1) + k]);
-            Bs[pp][i][kk] = v;
+        for (int hb = 0; hb < 16; hb += 8) {
+            double dv[8];
+            cd fv[8];
+            uint32_t okb = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int q = hb + e, l = lb + (q >> 3) + 2 * (w + 4 * (q & 7));
+                const bool lok = l >= lstart && l <= lend;
+                const bool ok = lok && m <= l && m < L;
+                const uint32_t dro = lok ? delta_row32(l, mp) : 0u;
+                const uint32_t fro = lok ? (uint32_t)(l * Lf) : 0u;
+                const uint32_t mi = ok ? (uint32_t)m : 0u;
+                dv[e] = delta[(size_t)(dro + mi)];
+                fv[e] = fpad[(size_t)(fro + mi)];
+                okb |= ok ? 1u << e : 0u;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int q = hb + e, pp = q >> 3, i = w + 4 * (q & 7);
+                const bool ok = (okb >> e) & 1u;
+                As[pp][0][i][lane] = ok ? (float)(dv[e] * fv[e].x) : 0.f;
+                As[pp][1][i][lane] = ok ? (float)(dv[e] * fv[e].y) : 0.f;
+            }
+        }
+        // B: 2 parities x 32 l x 32 k, 8 per thread, all in flight together.
+        // Element e: parity e >> 2, i = 2 w + (lane >> 5) + 8 (e & 3), kk =
+        // lane & 31: two l per wave, both row offsets scalar.
+        {
+            double dv[8], pv[8];
+            uint32_t okb = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int la = lb + (e >> 2) + 2 * (2 * w + 8 * (e & 3));  // l at hi = 0
+                const bool ok0 = la >= lstart && la <= lend;
+                const bool ok1 = la + 2 >= lstart && la + 2 <= lend;
+                const uint32_t d0 = ok0 ? delta_row32(la, mp) : 0u;
+                const uint32_t d1 = ok1 ? delta_row32(la + 2, mp) : 0u;
+                const uint32_t p0 = ok0 ? (uint32_t)(la * (h + 1)) : 0u;
+                const uint32_t p1 = ok1 ? (uint32_t)((la + 2) * (h + 1)) : 0u;
+                const int l = la + 2 * hi;
+                const bool ok = (hi ? ok1 : ok0) && k <= h && 2 * k <= l;
+                const uint32_t ki = ok ? (uint32_t)k : 0u;
+                dv[e] = delta[(size_t)((hi ? d1 : d0) + 2u * ki)];
+                pv[e] = psi[(size_t)((hi ? p1 : p0) + ki)];
+                okb |= ok ? 1u << e : 0u;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int pp = e >> 2, i = 2 * w + hi + 8 * (e & 3);
+                Bs[pp][i][lane & 31] = ((okb >> e) & 1u) ? (float)(dv[e] * pv[e]) : 0.f;
+            }
         }
         __syncthreads();
         Op<MODE> bop[2];
