@@ -664,21 +664,36 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_m1(ScaleGeom g,
         }
         __syncthreads();
     }
-    // part[m'][l][m] = Delta^l_{m'm} T[l][m]  (output layout: row 4r + lq of block lf)
+    // part[m'][l][m] = Delta^l_{m'm} T[l][m]  (output layout: row 4r + lq of block lf).
+    // The 16 Delta values of a thread are loaded together (out-of-range ones
+    // read element 0 and are replaced by 0 when used), then the products stored.
+    double dd[2][4][2];
+#pragma unroll
+    for (int lf = 0; lf < 2; ++lf)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int l = l0 + wp + 2 * (16 * lf + 4 * r + lq);
+            const uint32_t dro = (l <= g.lhi && mp <= l) ? delta_row32(l, mp) : 0u;
+#pragma unroll
+            for (int mj = 0; mj < 2; ++mj) {
+                const int m = m0 + 32 * wm + 16 * mj + li;
+                const bool ok = l <= g.lhi && m < L && mp <= l && m <= l;
+                dd[lf][r][mj] = delta[(size_t)(dro + (ok ? (uint32_t)m : 0u))];
+            }
+        }
+    cd *pbase = part + (size_t)mp * L * L;
 #pragma unroll
     for (int lf = 0; lf < 2; ++lf)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int l = l0 + wp + 2 * (16 * lf + 4 * r + lq);
             if (l > g.lhi) continue;
-            const double *drow = delta + delta_row32(l, mp);
 #pragma unroll
             for (int mj = 0; mj < 2; ++mj) {
                 const int m = m0 + 32 * wm + 16 * mj + li;
                 if (m >= L) continue;
-                const double d = (mp <= l && m <= l) ? drow[m] : 0.0;
-                part[(size_t)mp * L * L + (uint32_t)(l * L + m)] =
-                    cd{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
+                const double d = (mp <= l && m <= l) ? dd[lf][r][mj] : 0.0;
+                pbase[(uint32_t)(l * L + m)] = cd{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
             }
         }
 }

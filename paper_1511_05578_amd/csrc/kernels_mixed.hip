@@ -582,23 +582,37 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
             }
         __syncthreads();
     }
-    // part[m'][l][m] = Delta^l_{m'm} T: output row 4 lq + r of block lf, column li
+    // part[m'][l][m] = Delta^l_{m'm} T: output row 4 lq + r of block lf, column li.
+    // The 8 Delta values of a block are loaded together (out-of-range ones
+    // read element 0 and are replaced by 0 when used), then the products stored.
+    cf *pbase = part + (size_t)mp * L * L;
 #pragma unroll
-    for (int lf = 0; lf < 2; ++lf)
+    for (int lf = 0; lf < 2; ++lf) {
+        double dd[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
+            const uint32_t dro = (l <= g.lhi && mp <= l) ? delta_row32(l, mp) : 0u;
+#pragma unroll
+            for (int mj = 0; mj < 2; ++mj) {
+                const int m = m0 + 32 * wm + 16 * mj + li;
+                const bool ok = l <= g.lhi && m < L && mp <= l && m <= l;
+                dd[r][mj] = delta[(size_t)(dro + (ok ? (uint32_t)m : 0u))];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int l = l0 + wp + 2 * (16 * lf + 4 * lq + r);
             if (l > g.lhi) continue;
-            const double *drow = delta + delta_row32(l, mp);
 #pragma unroll
             for (int mj = 0; mj < 2; ++mj) {
                 const int m = m0 + 32 * wm + 16 * mj + li;
                 if (m >= L) continue;
-                const float d = (mp <= l && m <= l) ? (float)drow[m] : 0.f;
-                part[(size_t)mp * L * L + (uint32_t)(l * L + m)] =
-                    cf{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
+                const float d = (mp <= l && m <= l) ? (float)dd[r][mj] : 0.f;
+                pbase[(uint32_t)(l * L + m)] = cf{d * t[lf][mj][0][r], d * t[lf][mj][1][r]};
             }
         }
+    }
 }
 
 hipError_t launch_contract_fwd_mx(int mode, const ScaleGeom &g, const double *delta,
