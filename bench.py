@@ -219,6 +219,27 @@ def rule_roofline(stage, Lj, GB, flops_per_launch, t_launch, peak_tf):
     return r
 
 
+def copy_ceiling(stage_gbs, nbytes=512 << 20, reps=5):
+    """The HBM rate a plain device copy reaches on this GPU (bytes read plus
+    bytes written per second, 512 MiB: twice the 256 MB last-level cache),
+    timed with HIP events, and the dominant launch's stage IO rate as a
+    fraction of it -- the practical ceiling beside the nominal 8 TB/s."""
+    import torch
+
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return {"GBs": gbs, "bytes": 2 * nbytes, "stage_io_frac": stage_gbs / gbs}
+
+
 def bluestein_size(Lj):
     n = 2 * (2 * Lj - 1) - 1
     P = 8
@@ -662,6 +683,7 @@ def main():
     roof["L_j"] = top[1]
     roof["launch_ms"] = t_top * 1e3
     roof["algorithmic_per_launch"] = {"bytes": bytes_per_launch, "flops": flops_per_launch}
+    roof["copy_ceiling"] = copy_ceiling(bytes_per_launch / t_top / 1e9)
     if args.copy_calibration:
         x = torch.ones(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
