@@ -253,11 +253,14 @@ def kernel_symbol(stage, Lj, prec, real_grids=False, unrot=False):
     c = "cd" if prec == "fp64" else "cf"
     P = bluestein_size(Lj)
     u = "Unrot" if unrot else ""
-    # the packed gamma stages at even L_j with P = 1024 run one FFT at half length
-    odd = "Odd" if (P == 1024 and Lj % 2 == 0 and not unrot) else ""
+    # the packed gamma stages at even L_j run one FFT at half length: the
+    # analysis one at 1024 <= P <= 4096, the synthesis one at P = 1024 and 4096
+    even = Lj % 2 == 0 and not unrot
+    odd_i = "Odd" if (even and 1024 <= P <= 4096) else ""
+    odd_f = "Odd" if (even and P in (1024, 4096)) else ""
     io = {"alpha_dft_inv": u + "InvAlphaIO", "alpha_dft_fwd": u + "FwdAlphaIO",
-          "gamma_dft_inv": u + ("InvGammaPack%sIO" % odd if P >= 256 else "InvGammaIO"),
-          "gamma_dft_fwd": u + ("FwdGammaPack%sIO" % odd if P >= 256 else "FwdGammaIO")}
+          "gamma_dft_inv": u + ("InvGammaPack%sIO" % odd_i if P >= 256 else "InvGammaIO"),
+          "gamma_dft_fwd": u + ("FwdGammaPack%sIO" % odd_f if P >= 256 else "FwdGammaIO")}
     if stage in io:
         targs = c
         if stage.startswith("gamma"):  # grid element type

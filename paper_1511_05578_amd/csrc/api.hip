@@ -107,6 +107,12 @@ struct ScaleRt {
     BluesteinF inv_full_f, fwd_full_f;
     int ngroups;  // m' groups of the synthesis contraction
     bool beta_fft;  // analysis beta stage as an FFT (large L_j) instead of a GEMM
+    // ... written line-major and transposed into W1 (FFT size 4096: one line
+    // per work-group), in complex64; W1 then lives in the first cube buffer,
+    // W2 in the second.  (In complex128 the wider stores merge well enough
+    // that the transpose costs more than it saves: L = 1024, 37.2 ms per
+    // launch direct against 39.5 ms line-major and transposed.)
+    bool beta_lines;
     BluesteinDev beta_inv;
     BluesteinF beta_inv_f;
 };
@@ -379,6 +385,11 @@ int check_params(const cvl_params *p, int *J) {
     return CVL_OK;
 }
 
+// The analysis beta DFT of band-limit L_j is written line-major and then
+// transposed when its Bluestein size (>= 4 L_j - 3) is 4096, i.e. from
+// L_j = 513 on (see launch_inv_beta_dft_lines).
+bool beta_lines_of(int Lj) { return Lj >= kBetaFftMinL && 4 * Lj - 3 > 2048; }
+
 ScaleGeom geom_of(int Lj) {
     ScaleGeom g{};
     g.L = Lj;
@@ -411,9 +422,11 @@ void curvelet_buf_elems(int L, double lam, int J0, int J, bool unrot, size_t *b0
         size_t cube = (size_t)g.L * (unrot ? 2 * g.L : g.L) * g.Nep;
         size_t w2 = (size_t)g.L * g.Nm * (unrot ? g.L : g.h + 1);
         size_t part = unrot ? 0 : (size_t)g.L * g.L * g.L;  // at most L_j groups
+        // line-major beta: W2 in the second buffer
+        const size_t w2b = (!unrot && beta_lines_of(g.L)) ? w2 : 0;
         size_t *x0 = g.L < top ? sb0 : b0, *x1 = g.L < top ? sb1 : b1;
         *x0 = std::max({*x0, cube, w2});
-        *x1 = std::max({*x1, cube, part});
+        *x1 = std::max({*x1, cube, part, w2b});
     }
 }
 
@@ -543,10 +556,12 @@ int get_plan(cvl_ctx *c, const cvl_params *p, Plan **out) {
         if ((rc = get_bluestein_f(c, Nm, Nm, -(Lj - 1), Nm, 0, +1, &S.inv_full_f))) return rc;
         if ((rc = get_bluestein_f(c, Nm, Nm, 0, Nm, -(Lj - 1), -1, &S.fwd_full_f))) return rc;
         S.beta_fft = Lj >= kBetaFftMinL;
+        S.beta_lines = false;
         if (S.beta_fft) {
             if ((rc = get_bluestein(c, Nm, Nm, -(Lj - 1), Nm, -(Lj - 1), +1, &S.beta_inv))) return rc;
             if ((rc = get_bluestein_f(c, Nm, Nm, -(Lj - 1), Nm, -(Lj - 1), +1, &S.beta_inv_f)))
                 return rc;
+            S.beta_lines = beta_lines_of(Lj);
         }
         P->scales.push_back(S);
     }
@@ -1187,20 +1202,28 @@ static int analysis_scale_run(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int
                          : unrot_analysis_t<cf>(ctx, P, S, precision, S.inv_full_f, S.beta_inv_f, B,
                                                 (cf *)grid_out, st);
     }
+    // X in b0; W1 in b1 (in b0 after a line-major beta DFT); W2 in the other one
+    // (complex128: W1 in b1, W2 in b0)
     if (precision != CVL_FP64) {
-        cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1;
+        cf *b0 = (cf *)B.b0, *b1 = (cf *)B.b1, *w1 = b1;
         LAUNCH(ST_CONTRACT_INV,
                launch_contract_inv_mx(precision, g, L, ctx->delta, B.fpad, S.psi, b0, st));
-        if (S.beta_fft)
+        if (S.beta_lines) {
+            LAUNCH(ST_BETA_INV, launch_inv_beta_dft_lines(g, S.beta_inv_f, b0, b1, st));
+            LAUNCH(ST_BETA_INV, launch_beta_lines_to_planes(g, b1, b0, st));
+            w1 = b0;
+        } else if (S.beta_fft) {
             LAUNCH(ST_BETA_INV, launch_inv_beta_dft(g, S.beta_inv_f, b0, b1, st));
-        else
+        } else {
             LAUNCH(ST_BETA_INV, launch_beta_gemm_f32(precision, g.L, g.L, g.L * g.Nep, g.Nep,
                                                      S.betaf.Cinv, S.betaf.Sinv, b0, b1, st));
-        LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, b1, b0, st));
+        }
+        cf *w2 = w1 == b0 ? b1 : b0;
+        LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, S.inv_full_f, w1, w2, st));
         if (real_grid)
-            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, (float *)grid_out, st));
+            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, w2, (float *)grid_out, st));
         else
-            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, b0, (cf *)grid_out, st));
+            LAUNCH(ST_GAMMA_INV, launch_inv_gamma(g, S.inv_full_f, w2, (cf *)grid_out, st));
         return CVL_OK;
     }
     cd *b0 = (cd *)B.b0, *b1 = (cd *)B.b1;
@@ -1296,11 +1319,14 @@ static hipError_t beta_gemm_any(int precision, int M, int K, int ncols, int Nep,
                                 inverse ? T32.Sinv : T32.Qs, (const cf *)in, (cf *)out, st);
 }
 
-// Analysis stages of one part (padded coefficients fp) up to its W2 plane w2
-// (cube scratch b0, b1).
+// Analysis stages of one part (padded coefficients fp) up to its W2 plane
+// (cube scratch b0, b1): into w2, or, with w2 null, into whichever cube
+// buffer the stages leave free (b0, or b1 after a line-major beta DFT);
+// *w2_out receives the plane.
 template <class C>
 static int analysis_to_w2(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
-                          bool unrot, const cd *fp, C *b0, C *b1, C *w2, hipStream_t st) {
+                          bool unrot, const cd *fp, C *b0, C *b1, C *w2, C **w2_out,
+                          hipStream_t st) {
     const ScaleGeom &g = S.g;
     const int L = P->L;
     if (unrot) {
@@ -1311,7 +1337,9 @@ static int analysis_to_w2(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int pre
         else
             LAUNCH(ST_BETA_INV, beta_gemm_any(precision, g.L, g.L, 2 * g.L * g.Nep, g.Nep,
                                               S.beta, S.betaf, true, b0, b1, st));
-        LAUNCH(ST_ALPHA_INV, launch_unrot_inv_alpha(g, FullTabs<C>::inv(S), b1, w2, st));
+        C *dst = w2 ? w2 : b0;
+        LAUNCH(ST_ALPHA_INV, launch_unrot_inv_alpha(g, FullTabs<C>::inv(S), b1, dst, st));
+        *w2_out = dst;
         return CVL_OK;
     }
     if constexpr (std::is_same<C, cd>::value)
@@ -1319,12 +1347,20 @@ static int analysis_to_w2(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int pre
     else
         LAUNCH(ST_CONTRACT_INV,
                launch_contract_inv_mx(precision, g, L, ctx->delta, fp, S.psi, b0, st));
-    if (S.beta_fft)
+    C *w1 = b1;
+    if (S.beta_lines && std::is_same<C, cf>::value) {
+        LAUNCH(ST_BETA_INV, launch_inv_beta_dft_lines(g, FullTabs<C>::beta(S), b0, b1, st));
+        LAUNCH(ST_BETA_INV, launch_beta_lines_to_planes(g, b1, b0, st));
+        w1 = b0;
+    } else if (S.beta_fft) {
         LAUNCH(ST_BETA_INV, launch_inv_beta_dft(g, FullTabs<C>::beta(S), b0, b1, st));
-    else
+    } else {
         LAUNCH(ST_BETA_INV, beta_gemm_any(precision, g.L, g.L, g.L * g.Nep, g.Nep, S.beta,
                                           S.betaf, true, b0, b1, st));
-    LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, FullTabs<C>::inv(S), b1, w2, st));
+    }
+    C *dst = w2 ? w2 : (w1 == b0 ? b1 : b0);
+    LAUNCH(ST_ALPHA_INV, launch_inv_alpha(g, FullTabs<C>::inv(S), w1, dst, st));
+    *w2_out = dst;
     return CVL_OK;
 }
 
@@ -1364,14 +1400,14 @@ static int synthesis_from_v1(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int 
 template <class C>
 static int analysis_scale_cplx_t(cvl_ctx *ctx, const Plan *P, const ScaleRt &S, int precision,
                                  bool unrot, const CurveletBufs &B, C *grid, hipStream_t st) {
-    C *b0 = (C *)B.b0, *b1 = (C *)B.b1, *b2 = (C *)B.b2;
-    int rc = analysis_to_w2<C>(ctx, P, S, precision, unrot, B.fpad, b0, b1, b2, st);
-    if (!rc) rc = analysis_to_w2<C>(ctx, P, S, precision, unrot, B.fpadb, b0, b1, b0, st);
+    C *b0 = (C *)B.b0, *b1 = (C *)B.b1, *b2 = (C *)B.b2, *wa = nullptr, *wb = nullptr;
+    int rc = analysis_to_w2<C>(ctx, P, S, precision, unrot, B.fpad, b0, b1, b2, &wa, st);
+    if (!rc) rc = analysis_to_w2<C>(ctx, P, S, precision, unrot, B.fpadb, b0, b1, nullptr, &wb, st);
     if (rc) return rc;
     if (unrot)
-        LAUNCH(ST_GAMMA_INV, launch_unrot_inv_gamma_cplx(S.g, FullTabs<C>::inv(S), b2, b0, grid, st));
+        LAUNCH(ST_GAMMA_INV, launch_unrot_inv_gamma_cplx(S.g, FullTabs<C>::inv(S), wa, wb, grid, st));
     else
-        LAUNCH(ST_GAMMA_INV, launch_inv_gamma_cplx(S.g, FullTabs<C>::inv(S), b2, b0, grid, st));
+        LAUNCH(ST_GAMMA_INV, launch_inv_gamma_cplx(S.g, FullTabs<C>::inv(S), wa, wb, grid, st));
     return CVL_OK;
 }
 

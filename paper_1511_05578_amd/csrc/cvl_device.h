@@ -159,6 +159,15 @@ hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const 
                                hipStream_t st);
 hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X, cf *W1,
                                hipStream_t st);
+// The same, each line's outputs contiguous in b: T[(m Nep + nn) L + b]; then
+// launch_beta_lines_to_planes moves T into the W1 layout [b][m][nn].  Used
+// in complex64 where one line fills a work-group (FFT size 4096).
+hipError_t launch_inv_beta_dft_lines(const ScaleGeom &g, const BluesteinDev &B, const cd *X,
+                                     cd *T, hipStream_t st);
+hipError_t launch_inv_beta_dft_lines(const ScaleGeom &g, const BluesteinF &B, const cf *X,
+                                     cf *T, hipStream_t st);
+hipError_t launch_beta_lines_to_planes(const ScaleGeom &g, const cd *T, cd *W1, hipStream_t st);
+hipError_t launch_beta_lines_to_planes(const ScaleGeom &g, const cf *T, cf *W1, hipStream_t st);
 
 // The same four stages in single precision (complex64 cubes and grids).
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinF &B, const cf *W1, cf *W2,

@@ -374,10 +374,10 @@ __device__ __forceinline__ void twiddle8(C v[8], C w1) {
     v[7] = cmul(v[7], cmul(w4, w3));
 }
 
-// u[e] *= W^{j + 64 e}, e = 0..7, W = e^{-2 pi i / 1024}: W^j from the table
-// times powers of the constant W^64 = e^{-i pi / 8}.
+// u[e] *= W^{j + (P/16) e}, e = 0..7, W = e^{-2 pi i / P}: W^j from the table
+// times powers of the constant W^{P/16} = e^{-i pi / 8} (the same for every P).
 template <class C>
-__device__ __forceinline__ void twiddle_stride64(C u[8], C wj) {
+__device__ __forceinline__ void twiddle_stride16th(C u[8], C wj) {
     const C c1 = cmk<C>(CVL_C1, -CVL_S1);  // e^{-i pi / 8}
     C w = wj;
 #pragma unroll
@@ -459,28 +459,60 @@ __device__ __forceinline__ void exchange8(C v[8], real_t<C> *lds, int wb, WO wo,
     line_sync<P>();
 }
 
-// Forward FFT of 512 points held by the 64 threads of a 1024-point line, 8
-// each: v[s] = element tid + 64 s on entry and on exit.  Stockham radix-8,
-// three passes (Ns = 1, 8, 64); twiddles e^{-2 pi i x / 512} = tw[2x] of the
-// 1024-point table.
+// Forward FFT of N = P/2 points held by the T = P/16 threads of a P-point
+// line, 8 each: v[s] = element tid + T s on entry and on exit.  Stockham,
+// radix-8 passes (Ns = 1, 8, 64) and, for N > 512, a last radix-(N/512) pass
+// (Ns = 512) of 8/R butterflies per thread; twiddles e^{-2 pi i x / N} =
+// tw[2x] of the P-point table.
 template <int P, class C>
-__device__ __forceinline__ void fft_r8_512(C v[8], real_t<C> *lds, const C *__restrict__ tw,
-                                           int tid) {
-    static_assert(P == 1024, "half-length FFT of a 1024-point line");
+__device__ __forceinline__ void fft_r8_half(C v[8], real_t<C> *lds, const C *__restrict__ tw,
+                                            int tid) {
+    constexpr int N = P / 2, T = P / 16, R = N / 512;
+    static_assert(N >= 512 && N <= 2048, "half-length FFT of a 1024- to 4096-point line");
     dft8(v);  // pass Ns = 1: outputs 8 tid + k
     const int rb = lpad(tid);
     exchange8<P>(
-        v, lds, lpad(8 * tid), [](int k) { return k; }, rb, [](int r) { return lpo(64 * r); });
+        v, lds, lpad(8 * tid), [](int k) { return k; }, rb, [](int r) { return lpo(T * r); });
     {  // pass Ns = 8: twiddle w^{r k}, w = e^{-2 pi i / 64}, k = tid mod 8
-        twiddle8(v, tw[16 * (tid & 7)]);
+        twiddle8(v, tw[(P / 64) * (tid & 7)]);
         dft8(v);  // outputs (tid / 8) 64 + (tid mod 8) + 8 k'
     }
     exchange8<P>(
         v, lds, lpad((tid >> 3) * 64 + (tid & 7)), [](int k) { return lpo(8 * k); }, rb,
-        [](int r) { return lpo(64 * r); });
-    // pass Ns = 64: twiddle w^{r tid}, w = e^{-2 pi i / 512}; outputs tid + 64 k'
-    twiddle8(v, tw[2 * tid]);
+        [](int r) { return lpo(T * r); });
+    // pass Ns = 64: twiddle w^{r k}, w = e^{-2 pi i / 512}, k = tid mod 64;
+    // outputs (tid / 64) 512 + (tid mod 64) + 64 k'
+    twiddle8(v, tw[(P / 512) * (tid & 63)]);
     dft8(v);
+    if constexpr (R > 1) {
+        constexpr int NB = 8 / R;  // butterflies per thread
+        // element j + 512 r (j = tid + T q) arrives in v[q R + r]
+        exchange8<P>(
+            v, lds, lpad((tid >> 6) * 512 + (tid & 63)), [](int k) { return lpo(64 * k); }, rb,
+            [](int idx) { return lpo(T * (idx / R) + 512 * (idx % R)); });
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            C *u = &v[q * R];
+            const C w1 = tw[2 * (tid + T * q)];  // w^j, w = e^{-2 pi i / N}
+            if constexpr (R == 2) {
+                u[1] = cmul(u[1], w1);
+            } else {
+                const C w2 = cmul(w1, w1);
+                u[1] = cmul(u[1], w1);
+                u[2] = cmul(u[2], w2);
+                u[3] = cmul(u[3], cmul(w2, w1));
+            }
+            dft_small<R>(u);
+        }
+        // element j + 512 r = tid + T (q + r NB): reorder to v[q + r NB]
+        C t[8];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[q + r * NB] = v[q * R + r];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = t[k];
+    }
 }
 
 // Three waves per SIMD for lines that fit one wavefront (the kernel is latency
@@ -518,7 +550,7 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
     // The chirp spectrum is read by every line between the two FFTs: one copy
     // in LDS per work-group instead of a cache-missing global read per line.
     // (Up to P = 2048; at P = 4096 the copy would cost occupancy.)
-    constexpr bool kVhLds = P <= 2048 && !FourWaves<IO>::value;
+    constexpr bool kVhLds = P <= 2048 && !(P <= 1024 && FourWaves<IO>::value);
     const C *vh = B.vhat;
     if constexpr (kVhLds) {
         C *v2 = reinterpret_cast<C *>(smem_d + LINES * LW);
@@ -528,14 +560,15 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
     }
     C v[16];
     constexpr bool kOI = OddIn<IO>::value, kOO = OddOut<IO>::value;
-    static_assert(!(kOI || kOO) || P == 1024, "odd-input / odd-output paths need P = 1024");
+    static_assert(!(kOI || kOO) || (P >= 1024 && P <= 4096),
+                  "odd-input / odd-output paths need 1024 <= P <= 4096");
     // Every load of a line is issued before any is used: indices are clamped
     // into the window and out-of-window elements zeroed afterwards, so no
     // load waits behind a branch (the IO policies' loads are branch-free too).
     if constexpr (kOI) {
         // inputs only at odd t = 2u + 1 < P/2: the FFT of the window is
         // FFT_P(a)(k) = W^k FFT_{P/2}(a'')(k mod P/2), a''_u = a_{2u+1},
-        // W = e^{-2 pi i / P}.  Load a''_u at u = tid + 64 s, s < 8.
+        // W = e^{-2 pi i / P}.  Load a''_u at u = tid + T s, s < 8.
         static_assert(IO::kLoad == IO_DIRECT, "odd-input path loads directly");
         C u8[8];
         if (line < nlines) {
@@ -565,9 +598,9 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
 #pragma unroll
             for (int e = 0; e < 8; ++e) u8[e] = C{0, 0};
         }
-        fft_r8_512<P>(u8, lds, B.tw, tid);
-        // v[s] = W^k Y''(k mod 512), k = tid + 64 s; W^{k + 512} = -W^k
-        twiddle_stride64(u8, B.tw[tid]);
+        fft_r8_half<P>(u8, lds, B.tw, tid);
+        // v[s] = W^k Y''(k mod P/2), k = tid + T s; W^{k + P/2} = -W^k
+        twiddle_stride16th(u8, B.tw[tid]);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             v[e] = u8[e];
@@ -647,12 +680,12 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
     if constexpr (kOO) {
         // only odd outputs q = 2 v' + 1 are read: FFT_P(c)(2v'+1) =
         // FFT_{P/2}(d)(v'), d_j = (c_j - c_{j+P/2}) W^j; v[s] then holds
-        // output 2 (tid + 64 s) + 1 for s < 8
+        // output 2 (tid + T s) + 1 for s < 8
         C u8[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) u8[e] = csub(v[e], v[e + 8]);
-        twiddle_stride64(u8, B.tw[tid]);
-        fft_r8_512<P>(u8, lds, B.tw, tid);
+        twiddle_stride16th(u8, B.tw[tid]);
+        fft_r8_half<P>(u8, lds, B.tw, tid);
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = u8[e];
     } else {
@@ -689,7 +722,7 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
         // Kout <= P/2 complex fit in the line viewed as complex.
         C *buf = reinterpret_cast<C *>(lds);
         line_sync<P>();
-        if constexpr (kOO) {  // odd positions q = 2 (tid + 64 e) + 1 only
+        if constexpr (kOO) {  // odd positions q = 2 (tid + T e) + 1 only
             C pq[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -755,7 +788,9 @@ static hipError_t launch_r16(const IO &io, int nlines, const BlueT<typename IO::
                              hipStream_t st) {
     using G = R16<P>;
     const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>) +
-                       (P <= 2048 && !FourWaves<IO>::value ? (size_t)P * sizeof(typename IO::C) : 0);
+                       (P <= 2048 && !(P <= 1024 && FourWaves<IO>::value)
+                            ? (size_t)P * sizeof(typename IO::C)
+                            : 0);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -980,7 +1015,7 @@ struct FwdGammaPackIO {
     }
 };
 
-// The two packed gamma stages at an even band-limit L with P = 1024: the
+// The two packed gamma stages at an even band-limit L with 1024 <= P <= 4096: the
 // analysis window (n = t - (L-1)) holds non-zero coefficients (even n) only
 // at odd t, and the synthesis reads only the outputs of even n, at odd
 // positions q = n + L - 1; each then runs one of its two FFTs at half length.
@@ -1070,6 +1105,61 @@ struct BetaInvPairIO {
         if (c.wo) c.wo[row] = C{(zmk.x - zk.x) * h, (zmk.y - zk.y) * h};
     }
 };
+
+// The same analysis beta DFT writing each line's outputs contiguously in b,
+// T[(m Nep + nn) L + b] (line-major), for a tiled transpose into W1 after it.
+// At P = 4096 a work-group holds one line, and its stores one element per b
+// plane (8 MB apart at L = 1024 in complex64) merged so poorly in the L2 that
+// the kernel wrote 3.4 times its output bytes; written line-major they are
+// whole cache lines.
+template <class C_>
+struct BetaInvLineIO : BetaInvPairIO<C_> {
+    using C = C_;
+    using Ctx = typename BetaInvPairIO<C_>::Ctx;
+    __device__ Ctx at(int line) const {
+        Ctx c = BetaInvPairIO<C_>::at(line);
+        const int p = line / this->Ne, nn = line % this->Ne;
+        const int me = 2 * p, mo = 2 * p + 1;
+        c.we = this->W1 + ((size_t)me * this->Nep + nn) * this->L;
+        c.wo = mo < this->rows ? this->W1 + ((size_t)mo * this->Nep + nn) * this->L : nullptr;
+        return c;
+    }
+    __device__ void store_pair(const Ctx &c, int k, C zk, C zmk) const {
+        const int b = this->L - 1 - k;  // Z(beta_b) = zmk
+        const real_t<C> h = (real_t<C>)0.5;
+        c.we[b] = C{(zmk.x + zk.x) * h, (zmk.y + zk.y) * h};
+        if (c.wo) c.wo[b] = C{(zmk.x - zk.x) * h, (zmk.y - zk.y) * h};
+    }
+};
+
+// W1[b][m][nn] = T[(m Nep + nn) L + b] for nn < Ne (the padding columns of W1
+// are not read).  Work-group: one m, 32 nn x 64 b through LDS; reads of T rows
+// and writes of W1 rows both contiguous.
+template <class C>
+__global__ __launch_bounds__(256) void k_lines_to_planes(const C *__restrict__ T,
+                                                         C *__restrict__ W1, int L, int Ne,
+                                                         int Nep) {
+    __shared__ C tile[32][65];
+    const int nn0 = blockIdx.x * 32, b0 = blockIdx.y * 64, m = blockIdx.z;
+    const int tid = threadIdx.x;
+    {
+        const int cb = tid & 63, r0 = tid >> 6;
+        const int b = b0 + cb;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int nn = nn0 + r0 + 4 * i;
+            if (nn < Ne && b < L) tile[r0 + 4 * i][cb] = T[((size_t)m * Nep + nn) * L + b];
+        }
+    }
+    __syncthreads();
+    const int cn = tid & 31, rb = tid >> 5;
+    const int nn = nn0 + cn;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int b = b0 + rb + 8 * i;
+        if (b < L && nn < Ne) W1[((size_t)b * L + m) * Nep + nn] = tile[cn][rb + 8 * i];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Unrotated curvelets (every n in (-L, L)).  Cube rows per unrot_off; W2 and
@@ -1511,9 +1601,12 @@ template <class C, class G>
 static hipError_t inv_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const C *W2, G *grid,
                               hipStream_t st) {
     const int nreal = g.Nm * g.L;
-    if (B.P == 1024 && (g.L & 1) == 0) {
+    if (B.P >= 1024 && B.P <= 4096 && (g.L & 1) == 0) {
         InvGammaPackOddIO<C, G> io{{W2, grid, g.L, g.h, g.Nm, nreal}};
-        return launch_r16<1024>(io, (nreal + 1) / 2, B, st);
+        const int n = (nreal + 1) / 2;
+        return B.P == 1024 ? launch_r16<1024>(io, n, B, st)
+               : B.P == 2048 ? launch_r16<2048>(io, n, B, st)
+                             : launch_r16<4096>(io, n, B, st);
     }
     if (B.P >= 256) {
         InvGammaPackIO<C, G> io{W2, grid, g.L, g.h, g.Nm, nreal};
@@ -1526,9 +1619,12 @@ template <class C, class G>
 static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const G *grid, C *V1,
                               hipStream_t st) {
     const int nreal = g.Nm * g.L;
-    if (B.P == 1024 && (g.L & 1) == 0) {
+    // (not at P = 2048: there the half-length FFT's extra exchange, a
+    // work-group barrier for a two-wave line, cost more than it saved)
+    if ((B.P == 1024 || B.P == 4096) && (g.L & 1) == 0) {
         FwdGammaPackOddIO<C, G> io{{grid, V1, g.L, g.h, g.Nm, nreal}};
-        return launch_r16<1024>(io, (nreal + 1) / 2, B, st);
+        const int n = (nreal + 1) / 2;
+        return B.P == 1024 ? launch_r16<1024>(io, n, B, st) : launch_r16<4096>(io, n, B, st);
     }
     if (B.P >= 256) {
         FwdGammaPackIO<C, G> io{grid, V1, g.L, g.h, g.Nm, nreal};
@@ -1557,6 +1653,32 @@ hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinDev &B, const 
 hipError_t launch_inv_beta_dft(const ScaleGeom &g, const BluesteinF &B, const cf *X, cf *W1,
                                hipStream_t st) {
     return inv_beta_t(g, B, X, W1, st);
+}
+template <class C>
+static hipError_t inv_beta_lines_t(const ScaleGeom &g, const BlueT<C> &B, const C *X, C *T,
+                                   hipStream_t st) {
+    BetaInvLineIO<C> io{{X, T, g.L, g.Ne, g.Nep, g.L, (size_t)g.L * g.Nep}};
+    return run_bluestein(io, ((g.L + 1) / 2) * g.Ne, B, st);
+}
+hipError_t launch_inv_beta_dft_lines(const ScaleGeom &g, const BluesteinDev &B, const cd *X,
+                                     cd *T, hipStream_t st) {
+    return inv_beta_lines_t(g, B, X, T, st);
+}
+hipError_t launch_inv_beta_dft_lines(const ScaleGeom &g, const BluesteinF &B, const cf *X,
+                                     cf *T, hipStream_t st) {
+    return inv_beta_lines_t(g, B, X, T, st);
+}
+template <class C>
+static hipError_t lines_to_planes_t(const ScaleGeom &g, const C *T, C *W1, hipStream_t st) {
+    dim3 grid((g.Ne + 31) / 32, (g.L + 63) / 64, g.L);
+    hipLaunchKernelGGL(k_lines_to_planes<C>, grid, dim3(256), 0, st, T, W1, g.L, g.Ne, g.Nep);
+    return hipGetLastError();
+}
+hipError_t launch_beta_lines_to_planes(const ScaleGeom &g, const cd *T, cd *W1, hipStream_t st) {
+    return lines_to_planes_t(g, T, W1, st);
+}
+hipError_t launch_beta_lines_to_planes(const ScaleGeom &g, const cf *T, cf *W1, hipStream_t st) {
+    return lines_to_planes_t(g, T, W1, st);
 }
 
 hipError_t launch_inv_alpha(const ScaleGeom &g, const BluesteinDev &B, const cd *W1, cd *W2,

@@ -487,8 +487,10 @@ __global__ __launch_bounds__(256, 2) void k_contract_fwd_mx1(ScaleGeom g,
     const int lbase = g.llo & ~1;
     const int nl = g.lhi - lbase + 1;
     const int nlt = (nl + 63) / 64, nmt = (L + 63) / 64;
-    // logical tile: l tile fastest, then m tile, then m'
-    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt);
+    // logical tile: l tile fastest, then m tile, then m'; all tiles of one m'
+    // run on one XCD (those of one (m', m tile) read the same cube rows, those
+    // of one (m', l tile) the same Delta rows)
+    const int lg = xcd_group_runs(blockIdx.x, gridDim.x, nlt * nmt);
     const int m0 = ((lg / nlt) % nmt) * 64;
     const int l0 = lbase + (lg % nlt) * 64;
     const int mp = lg / (nlt * nmt);

@@ -217,6 +217,53 @@ def test_complex_l256_rows(ctx):
         c.close()
 
 
+def test_complex_line_major_beta_linearity():
+    # L = 514, FP32: the finest scale's analysis beta DFT has FFT size 4096 and
+    # is written line-major, then transposed; for a complex map the second
+    # part's W2 plane then lands in the other cube buffer.  Linearity ties the
+    # complex path to the real one (checked against oracle rows at L = 1024):
+    # W(x + i y) = W(x) + i W(y) for real maps x, y, at every scale.
+    L, lam, J0 = 514, 2.0, 2
+    c = api.Context(L, 0)
+    try:
+        f = inputs.uniform_complex_flm(L, 3)
+        z = c.sht_inverse(dev(f), L, complex_map=True)
+        x = z.real.contiguous()
+        y = z.imag.contiguous()
+        sz, gz = c.curvelet_analysis(z, lam, J0, precision="fp32")
+        sx, gx = c.curvelet_analysis(x, lam, J0, precision="fp32")
+        sy, gy = c.curvelet_analysis(y, lam, J0, precision="fp32")
+        assert gz[-1].shape[1] == L
+        nonzero = 0
+        for s_ in range(len(gz)):
+            ref = torch.complex(gx[s_].real, gy[s_].real)
+            rmax = ref.abs().max().item()
+            if rmax == 0.0:
+                # a scale whose kernel vanishes on [0, L) (at L = 514 the last
+                # one: kappa^(10) is zero for l <= 513) has an all-zero grid
+                say("complex L=514 fp32 scale %d: all zero" % s_)
+                assert gz[s_].abs().max().item() == 0.0
+                continue
+            d = (gz[s_] - ref).abs().max().item() / rmax
+            e = (torch.linalg.norm(gz[s_] - ref) / torch.linalg.norm(ref)).item()
+            say("complex L=514 fp32 scale %d: vs W(x) + i W(y) rel L2 %.2e max-abs rel %.2e"
+                % (s_, e, d))
+            assert e < 1e-5 and d < 1e-5
+            nonzero += 1
+            del ref
+        assert nonzero >= len(gz) - 1
+        ref = torch.complex(sx.real, sy.real)
+        assert (torch.linalg.norm(sz - ref) / torch.linalg.norm(ref)).item() < 1e-5
+        del gx, gy
+        rec = c.curvelet_synthesis(sz, gz, L, lam, J0, precision="fp32")
+        e = (torch.linalg.norm(rec - z) / torch.linalg.norm(z)).item()
+        say("  round trip rel L2 %.2e" % e)
+        assert e < 1e-5
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
 @pytest.mark.parametrize("L,s", [(16, 1), (32, 2), (32, -2), (20, 3)])
 def test_spin_rotated_curvelets(ctx, L, s):
     lam, J0 = 2.0, 2
