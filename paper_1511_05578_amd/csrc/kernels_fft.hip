@@ -866,7 +866,7 @@ template <class C_>
 struct InvAlphaIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most half the line (Kin <= P/2)
     const C *W1;
     C *W2;
     int L, h, Nep, Nm;
@@ -1037,7 +1037,7 @@ template <class C_>
 struct FwdAlphaIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most half the line (Kin <= P/2)
     const C *V1;
     C *V2;
     int L, h, Nm, Nep;

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_beta_gemm(int M, int K, int ncols, int 
 // none of those is skipped (its outputs are left unwritten).
 typedef double cvl_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256, 3) void k_beta_mfma(int M, int K, int ncols, int Nep,
+__global__ __launch_bounds__(256, 4) void k_beta_mfma(int M, int K, int ncols, int Nep,
                                                    const double *__restrict__ Ae,
                                                    const double *__restrict__ Ao,
                                                    const double *__restrict__ in,
