@@ -893,7 +893,7 @@ template <class C_, class G>
 struct InvGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const C *W2;
     G *grid;
     int L, h, Nm;
@@ -957,7 +957,7 @@ template <class C_, class G>
 struct FwdGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const G *grid;
     C *V1;
     int L, h, Nm;
@@ -983,7 +983,7 @@ template <class C_, class G>
 struct FwdGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const G *grid;
     C *V1;
     int L, h, Nm, nreal;
@@ -1173,7 +1173,7 @@ template <class C_>
 struct UnrotInvAlphaIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const C *W1;
     C *W2;
     ScaleGeom g;
@@ -1255,7 +1255,7 @@ template <class C_, class G>
 struct UnrotInvGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const C *W2;
     G *grid;
     int L, Nm;
@@ -1316,7 +1316,7 @@ template <class C_, class G>
 struct UnrotFwdGammaIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const G *grid;
     C *V1;
     int L, Nm;
@@ -1340,7 +1340,7 @@ template <class C_, class G>
 struct UnrotFwdGammaPackIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const G *grid;
     C *V1;
     int L, Nm, nreal;
@@ -1376,7 +1376,7 @@ template <class C_>
 struct UnrotFwdAlphaIO {
     using C = C_;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const C *V1;
     C *V2;
     ScaleGeom g;
@@ -1442,7 +1442,7 @@ template <class C_>
 struct FwdGammaCplxIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const C *grid;
     C *V1a, *V1b;
     int L, h, Nm;
@@ -1497,7 +1497,7 @@ template <class C_>
 struct UnrotFwdGammaCplxIO {
     using C = C_;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_PAIR;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const C *grid;
     C *V1a, *V1b;
     int L, Nm;
@@ -1523,7 +1523,7 @@ struct UnrotFwdGammaCplxIO {
 struct ShtInvPhiCplxIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *G;
     cd *map;
     int L, Nm;
@@ -1541,7 +1541,7 @@ struct ShtInvPhiCplxIO {
 struct ShtFwdPhiCplxIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *map;
     cd *F1;
     int L, Nm;
@@ -1559,7 +1559,7 @@ struct ShtFwdPhiCplxIO {
 struct ShtInvPhiIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *G;
     double *map;
     int L, Nm;
@@ -1578,7 +1578,7 @@ struct ShtInvPhiIO {
 struct ShtFwdPhiIO {
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const double *map;
     cd *F1;
     int L, Nm;
@@ -1916,7 +1916,7 @@ static inline int nnp_of(int N) { return ((2 * N - 1) + 31) / 32 * 32; }
 struct GenInvAlphaIO {  // line (b, n); in m; out a
     using C = cd;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *W1;
     cd *W2;
     int L, Nn, Nnp, Nm;
@@ -1934,7 +1934,7 @@ struct GenInvAlphaIO {  // line (b, n); in m; out a
 struct GenInvGammaIO {  // line (a, b); in n; out g
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *W2;
     cd *grid;
     int L, N, Nnp, Nm, Ng;
@@ -1952,7 +1952,7 @@ struct GenInvGammaIO {  // line (a, b); in n; out g
 struct GenFwdGammaIO {  // line (a, b); in g; out n
     using C = cd;
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *grid;
     cd *V1;
     int L, N, Nnp, Nm, Ng;
@@ -1970,7 +1970,7 @@ struct GenFwdGammaIO {  // line (a, b); in g; out n
 struct GenFwdAlphaIO {  // line (b, n); in a; out m
     using C = cd;
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
-    static constexpr int kBatch = 16;  // loads in flight per thread
+    static constexpr int kBatch = 8;  // inputs fill at most about half the line
     const cd *V1;
     cd *V2;
     int L, Nn, Nnp, Nm;
