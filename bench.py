@@ -412,6 +412,59 @@ def large_leg(steps=3, L=1024, n_sources=64):
             "warmup": 1, "round_trip_rel_l2": err, "setup_s": setup_s}
 
 
+def precision_leg(prec, steps=2, L=512, batch=16):
+    """The precision workload: a batch of 16 real maps at L = 512 (Gaussian
+    fields, seeds 0..15) through one batched analysis and synthesis with the
+    l-contraction and beta GEMMs in FP32 or split BF16 on the matrix cores
+    (complex64 grids; Delta and the final accumulation in FP64).  One warm-up
+    round trip, then `steps` timed ones; the error of map 0's grids against
+    the FP64 path, relative L2 and max-abs relative."""
+    import torch
+    from paper_1511_05578_amd import api, inputs
+    lam, J0 = 2.0, 2
+    ctx = api.Context(L, 0)
+    try:
+        ctx.prepare(L, lam, J0)
+        maps = torch.stack([ctx.sht_inverse(torch.from_numpy(inputs.gaussian_real_flm(L, seed=s))
+                                            .cuda(), L) for s in range(batch)]).contiguous()
+        scal, grids = ctx.alloc_outputs(L, lam, J0, batch, precision=prec)
+        rec = torch.empty_like(maps)
+
+        def step():
+            ctx.curvelet_analysis(maps, lam, J0, out=(scal, grids), precision=prec)
+            ctx.curvelet_synthesis(scal, grids, L, lam, J0, out=rec, precision=prec)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = (torch.linalg.norm(rec - maps) / torch.linalg.norm(maps)).item()
+        _, g64 = ctx.curvelet_analysis(maps[:1], lam, J0, precision="fp64")
+        num = den = mx = mref = 0.0
+        for a, b in zip(grids[0], g64[0]):
+            for i0 in range(0, a.shape[0], 64):  # in slabs: bounded temporaries
+                d = a[i0:i0 + 64].to(b.dtype) - b[i0:i0 + 64]
+                num += torch.linalg.norm(d).item() ** 2
+                den += torch.linalg.norm(b[i0:i0 + 64]).item() ** 2
+                mx = max(mx, d.abs().max().item())
+                mref = max(mref, b[i0:i0 + 64].abs().max().item())
+                del d
+        del g64, grids, scal, rec, maps
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+        torch.cuda.empty_cache()
+    return {"workload": "batch of %d real spin-0 maps, L=%d, lambda=2, J0=2, J=%d, complex64 grids, "
+                        "%s MFMA contractions and beta GEMMs, FP64 Delta and final accumulation"
+                        % (batch, L, api.num_scales(L), {"fp32": "FP32", "bf16x3": "split-BF16"}[prec]),
+            "value": batch * 1e3 / ms, "unit": "maps/s", "ms_per_batch": ms, "steps": steps,
+            "warmup": 1, "round_trip_rel_l2": err,
+            "vs_fp64_path": {"grids_rel_l2": math.sqrt(num / den), "grids_max_abs_rel": mx / mref}}
+
+
 def serving_leg(n=128, rho=0.7, bandlimits=(64, 128, 256, 512), slots=4):
     """The serving workload on a short trace: closed-loop capacity of the
     continuous-batching server (4 stream slots, same-L batching, HBM admission)
@@ -540,7 +593,8 @@ def main():
                          "(graph_replay_ms_per_step; not the headline value)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
-                    help="skip the secondary workloads (L=1024 streamed FP32, serving trace)")
+                    help="skip the secondary workloads (L=1024 streamed FP32, L=512 batch 16 FP32 and "
+                         "BF16x3, serving trace)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after timing, copy BYTES of device memory once (a plain copy kernel "
                          "of known size, for scaling hardware byte counters)")
@@ -757,6 +811,8 @@ def main():
         # the other configurations of the metric, measured in the same run
         print("large workload (L=1024 streamed FP32)", file=sys.stderr, flush=True)
         out["large"] = large_leg()
+        print("precision workloads (L=512, 16 maps)", file=sys.stderr, flush=True)
+        out["precision"] = {p: precision_leg(p) for p in ("fp32", "bf16x3")}
         print("serving trace", file=sys.stderr, flush=True)
         out["serving"] = serving_leg()
     print(json.dumps(out), flush=True)
