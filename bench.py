@@ -270,7 +270,9 @@ def kernel_symbol(stage, Lj, prec, real_grids=False, unrot=False):
         return eng
     mode = {"fp64": "", "fp32": "<1>", "bf16x3": "<2>"}[prec]
     if stage == "beta_gemm_inv" and Lj >= BETA_FFT_MIN_L:
-        return "k_blue_r16<%d, BetaInvPairIO<%s> >" % (P, c)
+        # complex64 at FFT size 4096: written line-major, then transposed
+        io = "BetaInvLineIO" if (prec != "fp64" and P == 4096 and not unrot) else "BetaInvPairIO"
+        return "k_blue_r16<%d, %s%s<%s> >" % (P, "Unrot" if unrot else "", io, c)
     if stage.startswith("beta"):
         return {"fp64": "k_beta_mfma", "fp32": "k_beta_mfma_f32", "bf16x3": "k_beta_mfma_bf16x3"}[prec]
     if unrot and stage in ("contract_inv", "contract_fwd"):
