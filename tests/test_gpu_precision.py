@@ -192,3 +192,46 @@ def test_l512_batch16():
         torch.cuda.synchronize()
         c.close()
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("complex_map", [False, True])
+def test_line_major_beta_odd_bandlimit(complex_map):
+    # Odd L = 515: the finest scales' analysis beta DFT has FFT size 4096 and,
+    # in complex64, is written line-major and transposed; at odd L_j the last
+    # m row has no odd partner in the paired transform and the W2 plane that
+    # then moves to the second cube buffer is larger than the cube.  The
+    # complex128 path keeps the direct stores, so FP32 against FP64 on the same
+    # map checks the line-major path (every grid within the FP32 bound).
+    L, lam, J0 = 515, 2.0, 2
+    c = api.Context(L, 0)
+    try:
+        if complex_map:
+            f = inputs.uniform_complex_flm(L, 11)
+            m = c.sht_inverse(dev(f), L, complex_map=True)
+        else:
+            f = inputs.gaussian_real_flm(L, seed=11)
+            m = c.sht_inverse(dev(f), L)
+        s64, g64 = c.curvelet_analysis(m, lam, J0)
+        s32, g32 = c.curvelet_analysis(m, lam, J0, precision="fp32")
+        assert g32[-1].shape[1] == L
+        checked = 0
+        for s_, (a, b) in enumerate(zip(g32, g64)):
+            ref = b.abs().max().item()
+            if ref == 0.0:  # a scale whose kernel vanishes below L
+                assert a.abs().max().item() == 0.0
+                continue
+            e = (torch.linalg.norm(a.to(b.dtype) - b) / torch.linalg.norm(b)).item()
+            mx = (a.to(b.dtype) - b).abs().max().item() / ref
+            say("L=515 complex=%s scale %d: FP32 vs FP64 rel L2 %.2e max-abs rel %.2e"
+                % (complex_map, s_, e, mx))
+            assert e < BOUND["fp32"] and mx < BOUND["fp32"]
+            checked += 1
+        assert checked >= len(g64) - 1
+        rec = c.curvelet_synthesis(s32, g32, L, lam, J0, precision="fp32")
+        e = (torch.linalg.norm(rec - m) / torch.linalg.norm(m)).item()
+        say("  FP32 round trip rel L2 %.2e" % e)
+        assert e < BOUND["fp32"]
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+        torch.cuda.empty_cache()
