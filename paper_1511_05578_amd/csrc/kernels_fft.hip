@@ -851,14 +851,28 @@ static hipError_t run_bluestein(const IO &io, int nlines, const BlueT<typename I
 // or as complex numbers with a zero imaginary part (G = C).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void grid_put(double *p, double x) { *p = x; }
-__device__ __forceinline__ void grid_put(float *p, float x) { *p = x; }
-__device__ __forceinline__ void grid_put(cd *p, double x) { *p = cd{x, 0.0}; }
-__device__ __forceinline__ void grid_put(cf *p, float x) { *p = cf{x, 0.0f}; }
-__device__ __forceinline__ double grid_get(const double *p) { return *p; }
-__device__ __forceinline__ float grid_get(const float *p) { return *p; }
-__device__ __forceinline__ double grid_get(const cd *p) { return p->x; }
-__device__ __forceinline__ float grid_get(const cf *p) { return p->x; }
+// Grid elements are written once per analysis and read by nothing else in
+// it: non-temporal (streaming) stores, which do not keep the lines in the
+// caches for the stages that follow.
+typedef double cvl_d2v __attribute__((ext_vector_type(2)));
+typedef float cvl_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void grid_put(double *p, double x) { __builtin_nontemporal_store(x, p); }
+__device__ __forceinline__ void grid_put(float *p, float x) { __builtin_nontemporal_store(x, p); }
+__device__ __forceinline__ void grid_put(cd *p, double x) {
+    __builtin_nontemporal_store(cvl_d2v{x, 0.0}, reinterpret_cast<cvl_d2v *>(p));
+}
+__device__ __forceinline__ void grid_put(cf *p, float x) {
+    __builtin_nontemporal_store(cvl_f2v{x, 0.0f}, reinterpret_cast<cvl_f2v *>(p));
+}
+// ... and read once per synthesis: non-temporal loads.
+__device__ __forceinline__ double grid_get(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float grid_get(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double grid_get(const cd *p) {
+    return __builtin_nontemporal_load(&p->x);
+}
+__device__ __forceinline__ float grid_get(const cf *p) {
+    return __builtin_nontemporal_load(&p->x);
+}
 
 // alpha DFT of the analysis: line (b, k >= 0); input over m in (-L, L) with the
 // reality condition W1(b, -m, -n) = conj W1(b, m, n); output a in [0, 2L-1).
