@@ -454,7 +454,8 @@ def precision_leg(prec, steps=2, L=512, batch=16):
                 mx = max(mx, d.abs().max().item())
                 mref = max(mref, b[i0:i0 + 64].abs().max().item())
                 del d
-        del g64, grids, scal, rec, maps
+            del a, b
+        del g64, grids, scal, rec, maps, step
     finally:
         torch.cuda.synchronize()
         ctx.close()
@@ -813,10 +814,10 @@ def main():
         # the other configurations of the metric, measured in the same run
         print("large workload (L=1024 streamed FP32)", file=sys.stderr, flush=True)
         out["large"] = large_leg()
-        print("precision workloads (L=512, 16 maps)", file=sys.stderr, flush=True)
-        out["precision"] = {p: precision_leg(p) for p in ("fp32", "bf16x3")}
         print("serving trace", file=sys.stderr, flush=True)
         out["serving"] = serving_leg()
+        print("precision workloads (L=512, 16 maps)", file=sys.stderr, flush=True)
+        out["precision"] = {p: precision_leg(p) for p in ("fp32", "bf16x3")}
     print(json.dumps(out), flush=True)
 
 
