@@ -126,6 +126,11 @@ class CurveletServer:
                 self.ws[s] = None
                 self.ws[s] = t.empty(nb, dtype=t.uint8, device=self.dev)
         t.cuda.synchronize()
+        # blocks the caching allocator still holds from earlier work (say, large
+        # grids of other calls) go back to the device first, so that the budget
+        # and the server's allocations start from the same, unfragmented pool
+        # (after a 170 GB batched call, capacity had once measured half of it)
+        t.cuda.empty_cache()
         free, _ = t.cuda.mem_get_info(self.dev)
         self.budget = self.hbm_budget if self.hbm_budget is not None else int(0.85 * free)
 
