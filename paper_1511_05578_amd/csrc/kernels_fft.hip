@@ -527,7 +527,11 @@ struct FourWaves<T, std::void_t<decltype(T::kFourWaves)>>
     : std::integral_constant<bool, T::kFourWaves> {};
 template <int P, class IO>
 struct WavesFor {
-    static constexpr int v = P <= 1024 ? (FourWaves<IO>::value ? 4 : 3) : 2;
+    static constexpr bool f32 = sizeof(real_t<typename IO::C>) == 4;
+    static constexpr int v = P <= 1024   ? (FourWaves<IO>::value ? 4 : 3)
+                             : !f32      ? 2
+                             : P == 4096 ? 5
+                                         : 2;
 };
 
 template <int P, class IO>

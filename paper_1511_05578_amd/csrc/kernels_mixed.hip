@@ -64,42 +64,87 @@ __device__ __forceinline__ f4v mma32(const Op<PREC_BF16X3> &a, const Op<PREC_BF1
 }
 
 // Operand loads of one K tile of the FP32 beta GEMMs (128 rows x 32 k of A,
-// 32 k x 64 real columns of the input) into registers.  A whole tile (the
-// usual case) loads without guards: no load result is consumed, and so
-// waited for, before the next iteration stores the registers to LDS.
+// 32 k x 64 real columns of the input) into registers: A as four 16-byte
+// pieces along k (eight threads per 128-byte row segment; single values when
+// K is not a multiple of 4), the input as eight single values down k (a wave
+// reads one 256-byte row segment per load), so that both land in LDS
+// k-contiguous per row and column.  Indices are clamped into the operands, so
+// every load is in bounds and none is guarded: no load result is consumed,
+// and so waited for, before the next iteration stores the registers to LDS.
+// Rows past M only feed outputs that are not stored; k past K is zeroed in A
+// when the tile is staged (the clamped input rows it meets are finite).
+// Columns are always whole (ncols is a multiple of 32).
+template <bool KV4>
 __device__ __forceinline__ void beta_fetch_f32(const float *__restrict__ A,
                                                const float *__restrict__ in, int M, int K,
                                                size_t ld, int r0, int c0, int k0, int tid,
-                                               float (&ra)[16], float4 (&rb)[2]) {
+                                               float4 (&ra)[4], float (&rb)[8]) {
+    const int ar = tid >> 3, ak = 4 * (tid & 7);   // A: rows ar + 32 q, k0 + ak .. + 3
+    const int bc = tid & 63, bk = 4 * (tid >> 6);  // input: column bc, k0 + bk + 16 g + e
     const float *Arow = A + (size_t)r0 * K;
-    if (r0 + 128 <= M && k0 + 32 <= K && 2 * (size_t)c0 + 64 <= ld) {  // uniform
-        // element q: row (tid >> 5) + 8 q, column k0 + (tid & 31)
-        const float *pa = Arow + (uint32_t)((tid >> 5) * K + (tid & 31) + k0);
-        const uint32_t step = 8u * (uint32_t)K;
+    const int rmax = M - 1 - r0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) ra[q] = pa[q * step];
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t rofs = (uint32_t)min(ar + 32 * q, rmax) * (uint32_t)K;
+        if constexpr (KV4) {
+            ra[q] = *reinterpret_cast<const float4 *>(Arow + rofs + min(k0 + ak, K - 4));
+        } else {
+            float x[4];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + 256 * q;
-            const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
-            rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)(k0 + (idx >> 4)) * ld + col);
+            for (int e = 0; e < 4; ++e) x[e] = Arow[rofs + min(k0 + ak + e, K - 1)];
+            ra[q] = make_float4(x[0], x[1], x[2], x[3]);
         }
-        return;
+    }
+    const float *pb = in + (size_t)k0 * ld + 2 * (size_t)c0 + bc;
+    const int kmax = K - 1 - k0;
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            rb[4 * g + e] = pb[(uint32_t)min(bk + 16 * g + e, kmax) * (uint32_t)ld];
+}
+
+// One K tile in LDS, k-contiguous: As[row][k], Bt[column][k]; rows of 36
+// floats keep the 16-byte writes and reads free of bank conflicts.
+struct BetaTileF32 {
+    float As[128][36];
+    float Bt[64][36];
+};
+
+__device__ __forceinline__ void beta_stage_f32(BetaTileF32 &t, float4 (&ra)[4],
+                                               const float (&rb)[8], int tid, int k0, int K) {
+    const int ar = tid >> 3, ak = 4 * (tid & 7);
+    const int bc = tid & 63, bk = 4 * (tid >> 6);
+    if (k0 + 32 > K) {  // last, partial K tile (uniform): zero A past K
+        const int kk = k0 + ak;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ra[q].x = kk < K ? ra[q].x : 0.f;
+            ra[q].y = kk + 1 < K ? ra[q].y : 0.f;
+            ra[q].z = kk + 2 < K ? ra[q].z : 0.f;
+            ra[q].w = kk + 3 < K ? ra[q].w : 0.f;
+        }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int idx = tid + 256 * q;
-        const int r = r0 + (idx >> 5), k = k0 + (idx & 31);
-        ra[q] = (r < M && k < K) ? Arow[(uint32_t)((idx >> 5) * K + k)] : 0.f;
-    }
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4 *>(&t.As[ar + 32 * q][ak]) = ra[q];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int idx = tid + 256 * q;
-        const int k = k0 + (idx >> 4);
-        const size_t col = 2 * (size_t)c0 + (idx & 15) * 4;
-        rb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (k < K && col + 3 < ld) rb[q] = *reinterpret_cast<const float4 *>(in + (size_t)k * ld + col);
-    }
+    for (int g = 0; g < 2; ++g)
+        *reinterpret_cast<float4 *>(&t.Bt[bc][bk + 16 * g]) =
+            make_float4(rb[4 * g], rb[4 * g + 1], rb[4 * g + 2], rb[4 * g + 3]);
+}
+
+__device__ __forceinline__ float f4get(const float4 &v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
+// A lane's eight k of one 16-row (or 16-column) block: k = 8 lq + e.  The
+// MFMA of step e sums its four k-lanes lq, so a K tile's 32 k are covered
+// once, in an order that lets each lane read its eight k as two 16-byte words.
+__device__ __forceinline__ void beta_operand(const float (&row)[36], int lq, float (&x)[8]) {
+    const float4 *src = reinterpret_cast<const float4 *>(&row[8 * lq]);
+    const float4 x0 = src[0], x1 = src[1];
+    x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+    x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
 }
 
 // The factor i of the odd beta parity, (re, im) -> (-im, re), applied to the
@@ -116,21 +161,37 @@ __device__ __forceinline__ void beta_odd_parity(f4v (&acc)[2][4], int li) {
             for (int r = 0; r < 4; ++r) acc[i][j][r] = sg * __shfl_xor(acc[i][j][r], 1);
 }
 
+__device__ __forceinline__ void beta_store_f32(const f4v (&acc)[2][4], float *__restrict__ out,
+                                               int M, size_t ld, int r0, int c0, int w, int li,
+                                               int lq) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 32 * w + 16 * i + 4 * lq + r;
+                const size_t col = 2 * (size_t)c0 + 16 * j + li;
+                if (row < M && col < ld) out[(size_t)row * ld + col] = acc[i][j][r];
+            }
+}
+
 // ---------------------------------------------------------------------------
 // Parity-folded beta stage in FP32 (curvelet layout, Nep % 32 == 0):
 //   out[r][c] = (i^par(c)) sum_k A^{par(c)}[r][k] in[k][c].
 // Tile 128 rows x 64 real columns x 32 k; wave w owns rows [32w, 32w+32) as
-// 2 x 4 blocks of v_mfma_f32_16x16x4_f32.  The next K tile is loaded into
-// registers while the current one is multiplied; the odd parity's factor i is
-// applied to the result.
+// 2 x 4 blocks of v_mfma_f32_16x16x4_f32 (MODE PREC_FP32) or of split-BF16
+// v_mfma_f32_16x16x32_bf16 triples (PREC_BF16X3, operands split in
+// registers).  The next K tile is loaded into registers while the current one
+// is multiplied; the odd parity's factor i is applied to the result.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, int Nep,
-                                                       const float *__restrict__ Ae,
-                                                       const float *__restrict__ Ao,
-                                                       const float *__restrict__ in,
-                                                       float *__restrict__ out) {
-    __shared__ float As[128][33];
-    __shared__ float Bs[32][64];
+template <int MODE, bool KV4>
+__global__ __launch_bounds__(256, MODE == PREC_FP32 ? 4 : 3) void k_beta_mfma_mx(int M, int K, int ncols, int Nep,
+                                                      const float *__restrict__ Ae,
+                                                      const float *__restrict__ Ao,
+                                                      const float *__restrict__ in,
+                                                      float *__restrict__ out) {
+    __shared__ __align__(16) BetaTileF32 t;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // logical tile (row tile fastest: the row tiles of one column tile share
     // its B operand, so they run together on one XCD)
@@ -147,145 +208,75 @@ __global__ __launch_bounds__(256) void k_beta_mfma_f32(int M, int K, int ncols, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     const int li = lane & 15, lq = lane >> 4;
-    // Next K tile held in registers while the current one is multiplied.
-    float ra[16];
-    float4 rb[2];
-    auto fetch = [&](int k0) { beta_fetch_f32(A, in, M, K, ld, r0, c0, k0, tid, ra, rb); };
-    fetch(0);
+    float4 ra[4];
+    float rb[8];
+    beta_fetch_f32<KV4>(A, in, M, K, ld, r0, c0, 0, tid, ra, rb);
     for (int k0 = 0; k0 < K; k0 += 32) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int idx = tid + 256 * q;
-            As[idx >> 5][idx & 31] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + 256 * q;
-            const int kk = idx >> 4, cc = (idx & 15) * 4;
-            Bs[kk][cc] = rb[q].x;
-            Bs[kk][cc + 1] = rb[q].y;
-            Bs[kk][cc + 2] = rb[q].z;
-            Bs[kk][cc + 3] = rb[q].w;
-        }
+        beta_stage_f32(t, ra, rb, tid, k0, K);
         __syncthreads();
-        if (k0 + 32 < K) fetch(k0 + 32);
+        if (k0 + 32 < K) beta_fetch_f32<KV4>(A, in, M, K, ld, r0, c0, k0 + 32, tid, ra, rb);
+        if constexpr (MODE == PREC_FP32) {
+            // two halves of four k (one 16-byte read per operand), step e
+            // outermost: eight independent accumulators between two products
+            // into the same one
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int k = 4 * ks + lq;
-            const float a0 = As[32 * w + li][k];
-            const float a1 = As[32 * w + 16 + li][k];
+            for (int h = 0; h < 2; ++h) {
+                float4 a4[2], b4[4];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    a4[i] = *reinterpret_cast<const float4 *>(&t.As[32 * w + 16 * i + li][8 * lq + 4 * h]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    b4[j] = *reinterpret_cast<const float4 *>(&t.Bt[16 * j + li][8 * lq + 4 * h]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                f4get(a4[i], e), f4get(b4[j], e), acc[i][j], 0, 0, 0);
+            }
+        } else {
+            Op<MODE> aop[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                float x[8];
+                beta_operand(t.As[32 * w + 16 * i + li], lq, x);
+                aop[i].set(x);
+            }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float b = Bs[k][16 * j + li];
-                acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][j], 0, 0, 0);
-                acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][j], 0, 0, 0);
+                float x[8];
+                beta_operand(t.Bt[16 * j + li], lq, x);
+                Op<MODE> bop;
+                bop.set(x);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][j] = mma32(aop[i], bop, acc[i][j]);
             }
         }
         __syncthreads();
     }
     if (par) beta_odd_parity(acc, li);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = r0 + 32 * w + 16 * i + 4 * lq + r;
-                const size_t col = 2 * (size_t)c0 + 16 * j + li;
-                if (row < M && col < ld) out[(size_t)row * ld + col] = acc[i][j][r];
-            }
-}
-
-// The same beta stage with split-BF16 products (BF16x3 mode): K tiles of 32,
-// one v_mfma_f32_16x16x32_bf16 triple per 16 x 16 block and tile.  Operands
-// are staged in FP32 and split in registers.
-__global__ __launch_bounds__(256, 3) void k_beta_mfma_bf16x3(int M, int K, int ncols, int Nep,
-                                                          const float *__restrict__ Ae,
-                                                          const float *__restrict__ Ao,
-                                                          const float *__restrict__ in,
-                                                          float *__restrict__ out) {
-    __shared__ __align__(16) float As[128][36];
-    __shared__ float Bs[32][68];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // logical tile (row tile fastest: the row tiles of one column tile share
-    // its B operand, so they run together on one XCD)
-    const int nrt = (M + 127) / 128;
-    const int lg = xcd_group(blockIdx.x, gridDim.x);
-    const int r0 = (lg % nrt) * 128;
-    const int c0 = (lg / nrt) * 32;  // complex column base
-    const size_t ld = 2 * (size_t)ncols;
-    const int par = (c0 / Nep) & 1;
-    const float *A = par ? Ao : Ae;
-    f4v acc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-    const int li = lane & 15, lq = lane >> 4;
-    float ra[16];
-    float4 rb[2];
-    auto fetch = [&](int k0) { beta_fetch_f32(A, in, M, K, ld, r0, c0, k0, tid, ra, rb); };
-    fetch(0);
-    for (int k0 = 0; k0 < K; k0 += 32) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int idx = tid + 256 * q;
-            As[idx >> 5][idx & 31] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int idx = tid + 256 * q;
-            const int kk = idx >> 4, cc = (idx & 15) * 4;
-            Bs[kk][cc] = rb[q].x;
-            Bs[kk][cc + 1] = rb[q].y;
-            Bs[kk][cc + 2] = rb[q].z;
-            Bs[kk][cc + 3] = rb[q].w;
-        }
-        __syncthreads();
-        if (k0 + 32 < K) fetch(k0 + 32);
-        Op<PREC_BF16X3> aop[2];
-#pragma unroll
-        for (int rb2 = 0; rb2 < 2; ++rb2) {
-            const float4 *src = reinterpret_cast<const float4 *>(&As[32 * w + 16 * rb2 + li][8 * lq]);
-            const float4 x0 = src[0], x1 = src[1];
-            const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-            aop[rb2].set(x);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float x[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = Bs[8 * lq + e][16 * j + li];
-            Op<PREC_BF16X3> bop;
-            bop.set(x);
-            acc[0][j] = mma32(aop[0], bop, acc[0][j]);
-            acc[1][j] = mma32(aop[1], bop, acc[1][j]);
-        }
-        __syncthreads();
-    }
-    if (par) beta_odd_parity(acc, li);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = r0 + 32 * w + 16 * i + 4 * lq + r;
-                const size_t col = 2 * (size_t)c0 + 16 * j + li;
-                if (row < M && col < ld) out[(size_t)row * ld + col] = acc[i][j][r];
-            }
+    beta_store_f32(acc, out, M, ld, r0, c0, w, li, lq);
 }
 
 hipError_t launch_beta_gemm_f32(int mode, int M, int K, int ncols, int Nep, const float *Aeven,
                                 const float *Aodd, const cf *in, cf *out, hipStream_t st) {
-    if (Nep % 32 != 0) return hipErrorInvalidValue;
-    dim3 g(((ncols + 31) / 32) * ((M + 127) / 128));
+    // whole 32-column tiles; 32 input rows of 2 ncols floats within 32-bit offsets
+    if (Nep % 32 != 0 || ncols % 32 != 0 || M < 1 || K < 1 ||
+        (uint64_t)32 * 2 * (uint64_t)ncols >= ((uint64_t)1 << 32))
+        return hipErrorInvalidValue;
+    dim3 g((ncols / 32) * ((M + 127) / 128));
+    const bool v4 = K % 4 == 0;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
+                           (const float *)in, (float *)out);
+    };
     if (mode == PREC_BF16X3)
-        hipLaunchKernelGGL(k_beta_mfma_bf16x3, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
-                           (const float *)in, (float *)out);
+        v4 ? go(k_beta_mfma_mx<PREC_BF16X3, true>) : go(k_beta_mfma_mx<PREC_BF16X3, false>);
     else
-        hipLaunchKernelGGL(k_beta_mfma_f32, g, dim3(256), 0, st, M, K, ncols, Nep, Aeven, Aodd,
-                           (const float *)in, (float *)out);
+        v4 ? go(k_beta_mfma_mx<PREC_FP32, true>) : go(k_beta_mfma_mx<PREC_FP32, false>);
     return hipGetLastError();
 }
 
