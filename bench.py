@@ -253,14 +253,13 @@ def kernel_symbol(stage, Lj, prec, real_grids=False, unrot=False):
     c = "cd" if prec == "fp64" else "cf"
     P = bluestein_size(Lj)
     u = "Unrot" if unrot else ""
-    # the packed gamma stages at even L_j run one FFT at half length: the
-    # analysis one at 1024 <= P <= 4096, the synthesis one at P = 1024 and 4096
+    # the packed gamma stages at even L_j run one FFT at half length at
+    # 1024 <= P <= 4096
     even = Lj % 2 == 0 and not unrot
-    odd_i = "Odd" if (even and 1024 <= P <= 4096) else ""
-    odd_f = "Odd" if (even and P in (1024, 4096)) else ""
+    odd = "Odd" if (even and 1024 <= P <= 4096) else ""
     io = {"alpha_dft_inv": u + "InvAlphaIO", "alpha_dft_fwd": u + "FwdAlphaIO",
-          "gamma_dft_inv": u + ("InvGammaPack%sIO" % odd_i if P >= 256 else "InvGammaIO"),
-          "gamma_dft_fwd": u + ("FwdGammaPack%sIO" % odd_f if P >= 256 else "FwdGammaIO")}
+          "gamma_dft_inv": u + ("InvGammaPack%sIO" % odd if P >= 256 else "InvGammaIO"),
+          "gamma_dft_fwd": u + ("FwdGammaPack%sIO" % odd if P >= 256 else "FwdGammaIO")}
     if stage in io:
         targs = c
         if stage.startswith("gamma"):  # grid element type
@@ -274,7 +273,10 @@ def kernel_symbol(stage, Lj, prec, real_grids=False, unrot=False):
         io = "BetaInvLineIO" if (prec != "fp64" and P == 4096 and not unrot) else "BetaInvPairIO"
         return "k_blue_r16<%d, %s%s<%s> >" % (P, "Unrot" if unrot else "", io, c)
     if stage.startswith("beta"):
-        return {"fp64": "k_beta_mfma", "fp32": "k_beta_mfma_f32", "bf16x3": "k_beta_mfma_bf16x3"}[prec]
+        if prec == "fp64":
+            return "k_beta_mfma"
+        # template instance: precision mode, K = L_j a multiple of 4
+        return "k_beta_mfma_mx%s" % (mode[:-1] + (", true>" if Lj % 4 == 0 else ", false>"))
     if unrot and stage in ("contract_inv", "contract_fwd"):
         return "k_unrot_%s<%s>" % (stage, c)
     if stage == "contract_inv":

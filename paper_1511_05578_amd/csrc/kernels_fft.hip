@@ -1637,12 +1637,12 @@ template <class C, class G>
 static hipError_t fwd_gamma_t(const ScaleGeom &g, const BlueT<C> &B, const G *grid, C *V1,
                               hipStream_t st) {
     const int nreal = g.Nm * g.L;
-    // (not at P = 2048: there the half-length FFT's extra exchange, a
-    // work-group barrier for a two-wave line, cost more than it saved)
-    if ((B.P == 1024 || B.P == 4096) && (g.L & 1) == 0) {
+    if ((B.P == 1024 || B.P == 2048 || B.P == 4096) && (g.L & 1) == 0) {
         FwdGammaPackOddIO<C, G> io{{grid, V1, g.L, g.h, g.Nm, nreal}};
         const int n = (nreal + 1) / 2;
-        return B.P == 1024 ? launch_r16<1024>(io, n, B, st) : launch_r16<4096>(io, n, B, st);
+        return B.P == 1024   ? launch_r16<1024>(io, n, B, st)
+               : B.P == 2048 ? launch_r16<2048>(io, n, B, st)
+                             : launch_r16<4096>(io, n, B, st);
     }
     if (B.P >= 256) {
         FwdGammaPackIO<C, G> io{grid, V1, g.L, g.h, g.Nm, nreal};

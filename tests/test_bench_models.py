@@ -70,7 +70,14 @@ def test_kernel_symbols():
         "k_blue_r16<1024, UnrotInvAlphaIO<cd> >"
     assert bench.kernel_symbol("gamma_dft_fwd", 256, "fp64", True, True) == \
         "k_blue_r16<1024, UnrotFwdGammaPackIO<cd, double> >"
-    assert bench.kernel_symbol("beta_gemm_fwd", 256, "fp32") == "k_beta_mfma_f32"
+    assert bench.kernel_symbol("beta_gemm_fwd", 256, "fp32") == "k_beta_mfma_mx<1, true>"
+    assert bench.kernel_symbol("beta_gemm_inv", 13, "bf16x3") == "k_beta_mfma_mx<2, false>"
+    assert bench.kernel_symbol("gamma_dft_fwd", 512, "fp32") == \
+        "k_blue_r16<2048, FwdGammaPackOddIO<cf, cf> >"
+    assert bench.kernel_symbol("gamma_dft_fwd", 512, "fp64") == \
+        "k_blue_r16<2048, FwdGammaPackOddIO<cd, cd> >"
+    assert bench.kernel_symbol("gamma_dft_fwd", 515, "fp64") == \
+        "k_blue_r16<4096, FwdGammaPackIO<cd, cd> >"
     assert bench.bluestein_size(256) == 1024 and bench.bluestein_size(1024) == 4096
     assert math.isclose(bench.stage_peak("contract_inv", "bf16x3"), bench.BF16_MFMA_PEAK_TFLOPS)
 
