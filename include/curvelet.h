@@ -93,7 +93,10 @@ typedef struct cvl_ctx cvl_ctx;
  * cvl_c128, with complex grids), optionally CVL_REAL_GRIDS (real maps only)
  * and CVL_UNROTATED; other bits are rejected.  Spin s != 0 needs
  * CVL_UNROTATED (CVL_EUNSUPPORTED otherwise).  The workspace size depends on
- * CVL_UNROTATED and CVL_REAL (cvl_workspace_bytes). */
+ * CVL_UNROTATED and CVL_REAL (cvl_workspace_bytes).  The odd-length DFTs run
+ * on power-of-two FFTs of at most 4096 points, which bounds L (and N) at 1024
+ * for the curvelet, Wigner and complex-map SHT calls (the real-map SHTs reach
+ * a little higher); a larger L returns CVL_EUNSUPPORTED before any launch. */
 typedef struct {
     int L;
     int N;

@@ -2,6 +2,7 @@
 // (Sec. III-A-2) and Bluestein chirp tables for the odd-length MW DFTs.
 #include "host_tables.h"
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <map>
@@ -276,6 +277,10 @@ Bluestein make_bluestein(int Nd, int Kin, int j0, int Kout, int k0, int sigma,
     B.sigma = sigma;
     B.P = next_pow2(Kin + Kout - 1);
     if (B.P < 8) B.P = 8;
+    // The register engine (P >= 256) stages a line's inputs and outputs in one
+    // padded LDS line of P + P/16 reals: a window wider than half of that
+    // (an SHT's 2L - 1 samples to L outputs, say) takes the next size.
+    while (B.P >= 256 && 2 * std::max(Kin, Kout) > B.P + B.P / 16) B.P *= 2;
     B.pre.resize(Kin);
     B.post.resize(Kout);
     for (int t = 0; t < Kin; ++t) B.pre[t] = chirp(j0 + t, Nd, sigma);

@@ -152,6 +152,48 @@ def test_l256_sampled_rows_and_round_trip(ctx, prec):
     assert e < bound
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", [150, 200])
+def test_beta_gemm_edge_tiles(ctx, prec, L):
+    # Below L_j = 256 both beta stages are the parity-folded GEMM (128-row x
+    # 32-k tiles).  L_j = 200: a partial row tile and a partial last K tile;
+    # L_j = 150 also a K that is not a multiple of 4 (single-value loads), and
+    # an SHT whose phi DFT takes the next FFT size.  Oracle beta rows on both
+    # sides of the row-tile edge and the last row (FP64 path and reduced
+    # precision), every grid against the library's FP64 path, and the round trip.
+    lam, J0 = 2.0, 2
+    bound = BOUND[prec]
+    plan = ocurv.Plan(L, lam, J0)
+    f = inputs.gaussian_real_flm(L, seed=L + 1)
+    fmap = osht.inverse(f, L).real
+    say("%s L=%d: GPU analysis" % (prec, L))
+    scal, grids = ctx.curvelet_analysis(dev(fmap), lam, J0, precision=prec)
+    s64, g64 = ctx.curvelet_analysis(dev(fmap), lam, J0)
+    for s, j in enumerate(plan.scales):
+        ref64 = host(g64[s])
+        g = host(grids[s])
+        if np.abs(ref64).max() == 0.0:  # a scale whose kernel vanishes below L
+            assert np.abs(g).max() == 0.0
+            continue
+        e = rel_l2(g, ref64)
+        say("  scale %d (L_j=%d): vs FP64 path rel L2 %.2e" % (j, plan.Lj[j], e))
+        assert e < bound
+        if plan.Lj[j] == L:
+            rr = [0, 127, 128, L - 1]
+            ref = ocurv.analysis_scale(plan, f, j, rows=rr)
+            e = rel_l2(ref64[:, rr, :], ref)
+            say("  scale %d rows %s FP64 path vs oracle rel L2 %.2e" % (j, rr, e))
+            assert e < 1e-10
+            e = rel_l2(g[:, rr, :], ref)
+            say("  scale %d rows %s vs oracle rel L2 %.2e, max %.2e"
+                % (j, rr, e, rel_max(g[:, rr, :], ref)))
+            assert e < bound
+    rec = host(ctx.curvelet_synthesis(scal, grids, L, lam, J0, precision=prec))
+    e = rel_l2(rec, fmap)
+    say("  round trip rel L2 %.2e" % e)
+    assert e < bound
+
+
 def test_l512_batch16():
     # 16 real maps at L = 512 in one batched call per precision (the batched
     # precision-path configuration): complex64 grids of all maps resident at
