@@ -70,3 +70,62 @@ def test_unrotated_round_trip(ctx, L):
     e = round_trip(ctx, L, "fp64", unrotated=True)
     say("L=%d unrotated FP64 round trip rel L2 %.2e" % (L, e))
     assert e < BOUND["fp64"]
+
+
+def _rel(a, b):
+    return (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+
+
+def _complex_map(ctx, L, spin, seed):
+    f = inputs.uniform_complex_flm(L, seed)
+    f[: spin * spin] = 0  # spin-s coefficients start at l = |s| (index l^2 + l + m)
+    return ctx.sht_inverse(torch.from_numpy(f).cuda(), L, spin=spin, complex_map=True)
+
+
+@pytest.mark.parametrize("L,spin,prec,unrot", [(137, 0, "fp64", False), (300, 0, "fp64", False),
+                                               (300, 0, "fp32", False), (171, 0, "fp64", True),
+                                               (137, 2, "fp64", False), (257, -2, "fp64", False),
+                                               (171, -3, "fp64", True), (300, 1, "fp32", True)])
+def test_complex_and_spin_round_trip(ctx, L, spin, prec, unrot):
+    m = _complex_map(ctx, L, spin, seed=L + spin)
+    scal, grids = ctx.curvelet_analysis(m, precision=prec, unrotated=unrot, spin=spin)
+    rec = ctx.curvelet_synthesis(scal, grids, L, precision=prec, unrotated=unrot, spin=spin)
+    torch.cuda.synchronize()
+    e = _rel(rec, m)
+    say("L=%d spin=%d %s unrotated=%s complex round trip rel L2 %.2e" % (L, spin, prec, unrot, e))
+    assert e < BOUND[prec]
+    del scal, grids, rec
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("L,lam,J0", [(137, 1.5, 1), (200, 3.0, 1), (171, 2.0, 4)])
+def test_other_dilations_round_trip(ctx, L, lam, J0):
+    e = round_trip(ctx, L, "fp64", lam=lam, J0=J0)
+    say("L=%d lambda=%g J0=%d FP64 round trip rel L2 %.2e" % (L, lam, J0, e))
+    assert e < BOUND["fp64"]
+
+
+def test_batch_real_grids_and_streamed_at_odd_bandlimit(ctx):
+    # a batch of three maps at L = 171: each map's grids bitwise those of its
+    # own call, float64 grids bitwise the complex grids' real parts, and the
+    # scale-at-a-time round trip
+    L = 171
+    maps = torch.stack([ctx.sht_inverse(torch.from_numpy(inputs.gaussian_real_flm(L, s)).cuda(), L)
+                        for s in range(3)])
+    sb, gb = ctx.curvelet_analysis(maps)  # grids: one list of scales per map
+    s1, g1 = ctx.curvelet_analysis(maps[1])
+    assert torch.equal(sb[1], s1)
+    for a, b in zip(gb[1], g1):
+        assert torch.equal(a, b)
+    _, gr = ctx.curvelet_analysis(maps[1], real_grids=True)
+    for a, b in zip(gr, g1):
+        assert torch.equal(a, b.real)
+    rb = ctx.curvelet_synthesis(sb, gb, L)
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert _rel(rb[i], maps[i]) < BOUND["fp64"]
+    rec_s, _ = ctx.round_trip_streamed(maps[2])
+    torch.cuda.synchronize()
+    e = _rel(rec_s, maps[2])
+    say("L=%d streamed round trip rel L2 %.2e" % (L, e))
+    assert e < BOUND["fp64"]
