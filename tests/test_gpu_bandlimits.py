@@ -6,7 +6,10 @@ in FP64 and below the reduced-precision bars (1e-5 FP32, 1e-3 BF16x3).  The
 sweep covers odd and even L around the FFT-size boundaries (odd DFT lengths
 2L - 1 whose Bluestein sizes change, SHT windows that take the next FFT size),
 the GEMM / FFT switch of the analysis beta stage (L_j = 256) and the
-line-major beta stage (L_j > 512).
+line-major beta stage (L_j > 512); complex and spin-s maps, other dilations,
+batches, float64 grids and the streamed interface at odd L; and the general
+Wigner transforms (forward after inverse is the identity) at large and
+degenerate (N = 1, 2) azimuthal band-limits.
 """
 import sys
 
@@ -129,3 +132,25 @@ def test_batch_real_grids_and_streamed_at_odd_bandlimit(ctx):
     e = _rel(rec_s, maps[2])
     say("L=%d streamed round trip rel L2 %.2e" % (L, e))
     assert e < BOUND["fp64"]
+
+
+@pytest.mark.parametrize("L,N", [(137, 5), (171, 171), (300, 64), (257, 1), (513, 2)])
+def test_wigner_round_trip(ctx, L, N):
+    # the forward Wigner transform inverts the inverse one exactly (MW
+    # sampling of SO(3)) on coefficients with |m|, |n| <= l
+    rng = np.random.default_rng(L * 1000 + N)
+    shape = (L, 2 * L - 1, 2 * N - 1)
+    F = rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)
+    l = np.arange(L)[:, None, None]
+    m = np.arange(-(L - 1), L)[None, :, None]
+    n = np.arange(-(N - 1), N)[None, None, :]
+    F[(np.abs(m) > l) | (np.abs(n) > l)] = 0
+    Fd = torch.from_numpy(F).cuda()
+    W = ctx.wigner_inverse(Fd, L, N)
+    F2 = ctx.wigner_forward(W, L, N)
+    torch.cuda.synchronize()
+    e = _rel(F2, Fd)
+    say("L=%d N=%d Wigner round trip rel L2 %.2e" % (L, N, e))
+    assert e < BOUND["fp64"]
+    del W, F2, Fd
+    torch.cuda.empty_cache()
