@@ -525,6 +525,12 @@ struct FourWaves : std::false_type {};
 template <class T>
 struct FourWaves<T, std::void_t<decltype(T::kFourWaves)>>
     : std::integral_constant<bool, T::kFourWaves> {};
+template <class T, class = void>
+struct LoadPrio : std::false_type {};
+template <class T>
+struct LoadPrio<T, std::void_t<decltype(T::kLoadPrio)>>
+    : std::integral_constant<bool, T::kLoadPrio> {};
+
 template <int P, class IO>
 struct WavesFor {
     static constexpr bool f32 = sizeof(real_t<typename IO::C>) == 4;
@@ -563,6 +569,11 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
         vh = v2;
     }
     C v[16];
+    // Raised wave priority while the line's loads are issued (complex128
+    // policies that declare `kLoadPrio`, FFT sizes up to 1024): waves in their
+    // load phase get their requests out ahead of waves computing.
+    constexpr bool kPrio = LoadPrio<IO>::value && sizeof(R) == 8 && P <= 1024;
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(2);
     constexpr bool kOI = OddIn<IO>::value, kOO = OddOut<IO>::value;
     static_assert(!(kOI || kOO) || (P >= 1024 && P <= 4096),
                   "odd-input / odd-output paths need 1024 <= P <= 4096");
@@ -602,6 +613,7 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
 #pragma unroll
             for (int e = 0; e < 8; ++e) u8[e] = C{0, 0};
         }
+        if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         fft_r8_half<P>(u8, lds, B.tw, tid);
         // v[s] = W^k Y''(k mod P/2), k = tid + T s; W^{k + P/2} = -W^k
         twiddle_stride16th(u8, B.tw[tid]);
@@ -678,6 +690,7 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
         }
         __syncthreads();
     }
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
     if constexpr (!kOI) fft_r16<P>(v, lds, B.tw, tid);
 #pragma unroll
     for (int s = 0; s < 16; ++s) v[s] = cconj(cmul(v[s], vh[tid + T * s]));
@@ -883,6 +896,7 @@ __device__ __forceinline__ float grid_get(const cf *p) {
 template <class C_>
 struct InvAlphaIO {
     using C = C_;
+    static constexpr bool kLoadPrio = true;  // (complex128, P <= 1024)
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     static constexpr int kBatch = 8;  // inputs fill at most half the line (Kin <= P/2)
     const C *W1;
@@ -936,6 +950,7 @@ struct InvGammaIO {
 template <class C_, class G>
 struct InvGammaPackIO {
     using C = C_;
+    static constexpr bool kLoadPrio = true;  // (complex128, P <= 1024)
     static constexpr int kLoad = IO_DIRECT, kStore = IO_DIRECT;
     static constexpr int kBatch = 8;  // two loads per element
     const C *W2;
@@ -1054,6 +1069,7 @@ struct FwdGammaPackOddIO : FwdGammaPackIO<C_, G> {
 template <class C_>
 struct FwdAlphaIO {
     using C = C_;
+    static constexpr bool kLoadPrio = true;  // (complex128, P <= 1024)
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED;
     static constexpr int kBatch = 8;  // inputs fill at most half the line (Kin <= P/2)
     const C *V1;
@@ -1089,6 +1105,7 @@ struct FwdAlphaIO {
 template <class C_>
 struct BetaInvPairIO {
     using C = C_;
+    static constexpr bool kLoadPrio = true;  // (complex128, P <= 1024)
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED_PAIR;
     static constexpr int kBatch = 8;  // two loads per element
     const C *X;
