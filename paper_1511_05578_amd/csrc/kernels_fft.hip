@@ -531,6 +531,21 @@ template <class T>
 struct LoadPrio<T, std::void_t<decltype(T::kLoadPrio)>>
     : std::integral_constant<bool, T::kLoadPrio> {};
 
+// The chirp spectrum is copied to LDS (once per work-group) up to P = 1024;
+// at 2048 only for a policy that declares `kVhLds2048` — elsewhere the copy's
+// LDS would cost work-groups per CU.
+template <class T, class = void>
+struct VhLds2048 : std::false_type {};
+template <class T>
+struct VhLds2048<T, std::void_t<decltype(T::kVhLds2048)>>
+    : std::integral_constant<bool, T::kVhLds2048> {};
+
+template <int P, class IO>
+struct VhLds {
+    static constexpr bool v =
+        (P <= 1024 && !FourWaves<IO>::value) || (P == 2048 && VhLds2048<IO>::value);
+};
+
 template <int P, class IO>
 struct WavesFor {
     static constexpr bool f32 = sizeof(real_t<typename IO::C>) == 4;
@@ -558,9 +573,9 @@ __global__ __launch_bounds__(R16<P>::WG, (WavesFor<P, IO>::v)) void k_blue_r16(
     const int line = line0 + li;
     R *lds = smem_d + li * LW;
     // The chirp spectrum is read by every line between the two FFTs: one copy
-    // in LDS per work-group instead of a cache-missing global read per line.
-    // (Up to P = 2048; at P = 4096 the copy would cost occupancy.)
-    constexpr bool kVhLds = P <= 2048 && !(P <= 1024 && FourWaves<IO>::value);
+    // in LDS per work-group instead of a cache-missing global read per line
+    // (where the copy does not cost occupancy, see VhLds).
+    constexpr bool kVhLds = VhLds<P, IO>::v;
     const C *vh = B.vhat;
     if constexpr (kVhLds) {
         C *v2 = reinterpret_cast<C *>(smem_d + LINES * LW);
@@ -805,9 +820,7 @@ static hipError_t launch_r16(const IO &io, int nlines, const BlueT<typename IO::
                              hipStream_t st) {
     using G = R16<P>;
     const size_t lds = (size_t)G::LINES * G::LW * sizeof(real_t<typename IO::C>) +
-                       (P <= 2048 && !(P <= 1024 && FourWaves<IO>::value)
-                            ? (size_t)P * sizeof(typename IO::C)
-                            : 0);
+                       (VhLds<P, IO>::v ? (size_t)P * sizeof(typename IO::C) : 0);
     if (lds > 65536) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -1105,6 +1118,7 @@ struct FwdAlphaIO {
 template <class C_>
 struct BetaInvPairIO {
     using C = C_;
+    static constexpr bool kVhLds2048 = sizeof(real_t<C_>) == 4;  // complex64 only
     static constexpr bool kLoadPrio = true;  // (complex128, P <= 1024)
     static constexpr int kLoad = IO_STAGED, kStore = IO_STAGED_PAIR;
     static constexpr int kBatch = 8;  // two loads per element
